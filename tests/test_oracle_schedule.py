@@ -1,0 +1,205 @@
+"""Pins of the Stream-K schedule simulator (CPU only).
+
+The simulator is checked against: the utilisation figure the report prints
+(Background section, Figure 1), hand-derived worked schedules
+(tests/golden/schedule_examples.json), closed forms of the two configurations
+it is used on, and -- by brute force over many small shapes, tile sizes,
+workgroup counts and modes -- the invariants of a valid work-centric
+schedule, computed from the segment list alone.  Mutation tests plant
+mistakes in a simulated schedule and require the checker to flag them.
+"""
+import json
+import os
+import random
+from dataclasses import replace
+
+import pytest
+
+from oracle import schedule as sch
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_figure1_utilisation():
+    d = json.load(open(os.path.join(GOLD, "paper_numbers.json")))
+    f = d["figure1_dp_utilisation"]
+    assert sch.dp_efficiency(f["tiles"], f["cores"]) == f["utilisation"]
+    # other small (tiles, cores) pairs with the same 75% utilisation
+    assert sch.dp_efficiency(3, 4) == 0.75 and sch.dp_efficiency(6, 4) == 0.75
+    assert sch.dp_efficiency(8, 4) == 1.0 and sch.dp_efficiency(0, 4) == 1.0
+
+
+@pytest.mark.parametrize("mode_name,mode", [("sk", sch.MODE_SK),
+                                            ("hybrid", sch.MODE_HYBRID)])
+def test_worked_examples(mode_name, mode):
+    d = json.load(open(os.path.join(GOLD, "schedule_examples.json")))
+    M, N, K = d["problem"]
+    bm, bn, bk = d["tile"]
+    plan, segs = sch.simulate([(M, N, K)], bm, bn, bk, d["g"], mode)
+    assert [list(s.as_tuple()) for s in segs] == d[mode_name]["segments"]
+    sch.check([(M, N, K)], bm, bn, bk, d["g"], mode, segs)
+
+
+def test_c1_closed_form():
+    # FP32 512^3, 128x128x32 tiles, 256 workgroups, pure Stream-K:
+    # 16 tiles x 16 iterations = 256 iterations, one per workgroup.
+    plan, segs = sch.simulate([(512, 512, 512)], 128, 128, 32, 256, sch.MODE_SK)
+    assert (plan.T, plan.S, plan.W, plan.q, plan.rho) == (16, 16, 256, 1, 0)
+    s = sch.summary(segs)
+    assert s["FINISH"] == 16 and s["PARTIAL"] == 240 and "FULL" not in s
+    assert s["max_contributors"] == 16
+    for seg in segs:
+        assert seg.tile == seg.wg // 16 and seg.k_begin == seg.wg % 16
+        if seg.role == sch.FINISH:
+            assert seg.wg % 16 == 0 and seg.npeers == 15
+
+
+def test_c2_closed_form():
+    # FP16 3840x4096x4096, 256x128x64 tiles, 256 workgroups, hybrid rule.
+    plan, segs = sch.simulate([(3840, 4096, 4096)], 256, 128, 64, 256)
+    assert (plan.T, plan.S, plan.W, plan.q) == (480, 480, 30720, 120)
+    s = sch.summary(segs)
+    assert s["PARTIAL"] == 224 and s["FINISH"] == 224
+    assert s["max_contributors"] == 2
+    aligned = [x for x in range(256) if sch.wg_range(plan, x)[0] % 64 == 0]
+    assert aligned == list(range(0, 256, 8))
+    sch.check([(3840, 4096, 4096)], 256, 128, 64, 256, sch.MODE_HYBRID, segs)
+
+
+def test_hybrid_split_rule():
+    for T, g, S in [(9, 4, 5), (8, 4, 0), (3, 4, 3), (480, 256, 480),
+                    (2752, 256, 448), (1024, 256, 0), (1376, 256, 352)]:
+        tm = T  # one tile column: T tiles of 1 row each
+        plan = sch.make_plan([(tm, 1, 1)], 1, 1, 1, g, sch.MODE_HYBRID)
+        assert plan.S == S, (T, g, plan.S)
+    plan = sch.make_plan([(9, 1, 1)], 1, 1, 1, 4, sch.MODE_HYBRID, dp_tiles=2)
+    assert plan.S == 7
+    plan = sch.make_plan([(9, 1, 1)], 1, 1, 1, 4, sch.MODE_HYBRID, dp_tiles=99)
+    assert plan.S == 0
+
+
+def test_group_m_tile_order_is_a_bijection():
+    for tm, tn, gm in [(5, 3, 2), (7, 4, 3), (8, 8, 4), (1, 9, 4), (6, 1, 8)]:
+        coords = [sch.tile_coords(u, tm, tn, gm) for u in range(tm * tn)]
+        assert sorted(coords) == [(r, c) for r in range(tm) for c in range(tn)]
+    # band walk: group_m rows down first, then across
+    assert [sch.tile_coords(u, 4, 3, 2) for u in range(6)] == [
+        (0, 0), (1, 0), (0, 1), (1, 1), (0, 2), (1, 2)]
+
+
+SIZES = [1, 7, 64, 65, 127, 129, 200, 257]
+TILES = [(128, 128, 32), (256, 128, 64), (64, 64, 16), (32, 128, 128)]
+GS = [1, 2, 3, 4, 5, 7, 8, 16, 31, 64, 120, 255, 256]
+
+
+def _cases(seed, n):
+    rng = random.Random(seed)
+    for _ in range(n):
+        shape = (rng.choice(SIZES), rng.choice(SIZES), rng.choice(SIZES + [0]))
+        yield shape, rng.choice(TILES), rng.choice(GS)
+
+
+@pytest.mark.parametrize("mode", [sch.MODE_SK, sch.MODE_HYBRID, sch.MODE_DP])
+def test_brute_force_invariants(mode):
+    for shape, (bm, bn, bk), g in _cases(10 + mode, 400):
+        for gm in (0, 3):
+            for dp in ((-1,) if mode == sch.MODE_DP else (-1, 0, 2)):
+                plan, segs = sch.simulate([shape], bm, bn, bk, g, mode, dp, gm)
+                sch.check([shape], bm, bn, bk, g, mode, segs, dp, gm)
+
+
+def test_brute_force_grouped():
+    rng = random.Random(99)
+    for _ in range(150):
+        probs = [(rng.choice(SIZES + [0]), rng.choice(SIZES), rng.choice(SIZES + [0]))
+                 for _ in range(rng.randint(1, 6))]
+        bm, bn, bk = rng.choice(TILES)
+        g = rng.choice(GS)
+        for mode in (sch.MODE_SK, sch.MODE_HYBRID, sch.MODE_DP):
+            plan, segs = sch.simulate(probs, bm, bn, bk, g, mode)
+            sch.check(probs, bm, bn, bk, g, mode, segs)
+
+
+def test_every_wg_count_on_paper_shapes():
+    # The report traces its sub-maximal "Compute Units" failures to the block
+    # to tile mapping (Methodology, Results) and a 480x512x512 failure
+    # (Results, Table 1): the schedule must be valid for every g.
+    for shape in [(480, 512, 512), (1920, 2000, 2000)]:
+        for g in range(1, 257, 5):
+            for mode in (sch.MODE_SK, sch.MODE_HYBRID):
+                plan, segs = sch.simulate([shape], 256, 128, 64, g, mode)
+                sch.check([shape], 256, 128, 64, g, mode, segs)
+
+
+# --- mutation tests: the checker must reject planted mistakes --------------
+
+def _base():
+    prob = [(384, 384, 128)]
+    plan, segs = sch.simulate(prob, 128, 128, 32, 4, sch.MODE_SK)
+    return prob, segs
+
+
+def _rejects(prob, segs, mode=sch.MODE_SK):
+    with pytest.raises(sch.ScheduleError):
+        sch.check(prob, 128, 128, 32, 4, mode, segs)
+
+
+def test_mutation_dropped_iteration():
+    prob, segs = _base()
+    i = next(i for i, s in enumerate(segs) if s.role == sch.PARTIAL)
+    segs[i] = replace(segs[i], k_begin=segs[i].k_begin + 1)
+    _rejects(prob, segs)
+
+
+def test_mutation_double_coverage():
+    prob, segs = _base()
+    i = next(i for i, s in enumerate(segs) if s.role == sch.FINISH)
+    segs[i] = replace(segs[i], k_end=segs[i].k_end + 1)
+    _rejects(prob, segs)
+
+
+def test_mutation_wrong_npeers():
+    prob, segs = _base()
+    i = next(i for i, s in enumerate(segs) if s.role == sch.FINISH)
+    segs[i] = replace(segs[i], npeers=segs[i].npeers + 1)
+    _rejects(prob, segs)
+
+
+def test_mutation_wrong_role():
+    prob, segs = _base()
+    i = next(i for i, s in enumerate(segs) if s.role == sch.PARTIAL)
+    segs[i] = replace(segs[i], role=sch.FULL)
+    _rejects(prob, segs)
+
+
+def test_mutation_swapped_tile_coords():
+    prob, segs = _base()
+    segs = [replace(s, tile_m=s.tile_n, tile_n=s.tile_m) if s.tile == 1 else s
+            for s in segs]
+    _rejects(prob, segs)
+
+
+def test_mutation_unbalanced_split():
+    prob = [(384, 384, 128)]
+    plan, segs = sch.simulate(prob, 128, 128, 32, 4, sch.MODE_SK)
+    # move one iteration of WG3's FULL tile 8 into a fake fifth range
+    segs = [s for s in segs if s.tile != 8] + [
+        sch.Segment(3, 0, 8, 2, 2, 0, 3, sch.FINISH, 1),
+        sch.Segment(3, 0, 8, 2, 2, 3, 4, sch.PARTIAL, 0)]
+    _rejects(prob, segs)
+
+
+def test_mutation_partial_not_first():
+    prob = [(384, 384, 128)]
+    plan, segs = sch.simulate(prob, 128, 128, 32, 4, sch.MODE_SK)
+    wg1 = [s for s in segs if s.wg == 1]
+    rest = [s for s in segs if s.wg != 1]
+    _rejects(prob, rest + wg1[::-1])
+
+
+def test_mutation_dp_on_wrong_wg():
+    prob = [(384, 384, 128)]
+    plan, segs = sch.simulate(prob, 128, 128, 32, 4, sch.MODE_HYBRID)
+    i = next(i for i, s in enumerate(segs) if s.role == sch.DP)
+    segs[i] = replace(segs[i], wg=(segs[i].wg + 1) % 4)
+    _rejects(prob, segs, sch.MODE_HYBRID)
