@@ -1,0 +1,281 @@
+/*
+ * streamk.h -- C ABI of the MI355X (gfx950) Stream-K GEMM library
+ * (libstreamk.so).
+ *
+ * The library computes the general matrix product the report studies
+ * (Introduction, Background; measured as M x N x K problems in Results,
+ * Table 1):
+ *
+ *     C_out = alpha * scale_a * scale_b * (A x B) + beta * C_in
+ *
+ * with A of size M x K, B of size K x N and C of size M x N, using Stream-K's
+ * work-centric decomposition (Background section): the multiply-accumulate
+ * (MAC) loop iterations of all output tiles are counted together and split
+ * evenly over one persistent workgroup per compute unit -- the report's
+ * "Compute Units" launch parameter (Methodology) -- and a tile whose
+ * iterations straddle two or more workgroups is finished by a partial-sum
+ * fixup.  A data-parallel (one tile per workgroup) + Stream-K hybrid covers
+ * the tile count's remainder, and a plain data-parallel grid is available as
+ * the baseline the method is compared with.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers.     Every data pointer (A, B, C_in, C_out, workspace, device
+ *               descriptors) is caller-owned device memory of the current HIP
+ *               device.  The library never allocates or frees device memory
+ *               and never keeps a pointer after a call returns.
+ * Streams.      `hip_stream` is a hipStream_t passed as void* (NULL = the
+ *               null stream).  Launch entry points only enqueue work and
+ *               return; they do not synchronise.
+ * Errors.       Every entry point returns an sk_status; nothing aborts and no
+ *               C++ exception crosses the ABI.  On an error return no work has
+ *               been enqueued.  Errors raised inside a kernel (a fixup wait
+ *               that exceeded its spin limit) are reported later by
+ *               sk_check_device_error.
+ * Threads.      Entry points are thread-safe; concurrent launches must use
+ *               distinct workspaces.
+ * Layout.       Element (i,k) of A is a[i*lda + k] (SK_ROW_MAJOR) or
+ *               a[k*lda + i] (SK_COL_MAJOR); element (k,j) of B is
+ *               b[k*ldb + j] (row-major) or b[j*ldb + k] (column-major);
+ *               C is always row-major: c[i*ldc + j].  Leading dimensions are
+ *               in elements.  C_in and C_out share ldc and dtype_c and may
+ *               alias (in-place update).
+ * Padding.      Problems are not padded (the report's padding study, Results
+ *               and Table 1): out-of-range rows/columns/k-elements of a tile
+ *               read as zero and out-of-range outputs are not written.
+ * Alignment.    Any element-aligned pointer and leading dimension works.  The
+ *               fast 16-byte load path is used when A and B start on 16-byte
+ *               boundaries and lda*size, ldb*size are multiples of 16 bytes;
+ *               otherwise the element-wise path is used (same results).
+ */
+#ifndef STREAMK_H
+#define STREAMK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SK_OK = 0,
+  SK_ERR_INVALID_ARG = -1,    /* a dimension, leading dimension, pointer or
+                                 config field is out of range */
+  SK_ERR_UNSUPPORTED = -2,    /* dtype / tile / layout combination not built */
+  SK_ERR_WORKSPACE = -3,      /* workspace missing or smaller than required */
+  SK_ERR_OCCUPANCY = -4,      /* more persistent workgroups than the device
+                                 can keep resident at once */
+  SK_ERR_HIP = -5,            /* a HIP runtime call failed */
+  SK_ERR_CAPACITY = -6,       /* an output array is too small */
+  SK_ERR_DEVICE_TIMEOUT = -7  /* a fixup wait gave up (see spin_limit) */
+} sk_status;
+
+/* Input (A, B) element types.  SK_F8E4M3 is the OCP 8-bit e4m3 "fn" format
+ * (finite, max 448) that gfx950 matrix cores consume.  Accumulation is FP32
+ * for every input type. */
+typedef enum { SK_F32 = 0, SK_F16 = 1, SK_BF16 = 2, SK_F8E4M3 = 3 } sk_dtype;
+typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
+
+/* How output tiles are distributed (Background section):
+ *   SK_MODE_HYBRID  data-parallel + Stream-K: tiles [S, T) are whole tiles
+ *                   handed round-robin to the persistent workgroups, tiles
+ *                   [0, S) are split by MAC iterations; S = 0 when T is a
+ *                   multiple of g, else min(T, T mod g + g) ("two-tile" rule),
+ *                   unless sk_config.dp_tiles >= 0 sets S = T - dp_tiles.
+ *   SK_MODE_SK      every tile is a Stream-K tile (S = T).
+ *   SK_MODE_DP      baseline data-parallel grid: one workgroup per tile,
+ *                   no persistence, no fixup, no workspace. */
+typedef enum { SK_MODE_HYBRID = 0, SK_MODE_SK = 1, SK_MODE_DP = 2 } sk_mode;
+
+/* Role of a schedule segment (what a workgroup does with one tile). */
+typedef enum {
+  SK_ROLE_FULL = 0,     /* all MAC iterations of the tile, then the epilogue */
+  SK_ROLE_FINISH = 1,   /* iterations [0, k_end), then waits for npeers
+                           partial tiles, sums them and runs the epilogue */
+  SK_ROLE_PARTIAL = 2,  /* iterations [k_begin, k_end) with k_begin > 0;
+                           stores the partial tile and signals its owner */
+  SK_ROLE_DP = 3        /* a whole data-parallel tile */
+} sk_role;
+
+/* One GEMM.  dtype_c is SK_F32, SK_F16 or SK_BF16 (results are rounded to
+ * nearest-even from FP32).  scale_a / scale_b are the per-tensor scales of
+ * FP8 inputs (use 1 otherwise).  beta == 0 means C_in is never read. */
+typedef struct {
+  int64_t M, N, K;
+  int32_t layout_a, layout_b;   /* sk_layout */
+  int64_t lda, ldb, ldc;        /* elements */
+  int32_t dtype_ab;             /* sk_dtype of A and B */
+  int32_t dtype_c;              /* sk_dtype of C_in / C_out */
+  float alpha, beta, scale_a, scale_b;
+} sk_problem;
+
+/* Launch configuration.  block_m x block_n x block_k must be a tile built
+ * for dtype_ab (sk_supported_tiles); block_k is the number of K elements of
+ * one MAC-loop iteration, which is 128 bytes of K: 32 (f32), 64 (f16, bf16)
+ * or 128 (e4m3).  A zeroed struct plus a tile is a valid default. */
+typedef struct {
+  int32_t block_m, block_n, block_k;
+  int32_t num_cu;      /* compute units to use, 1..device CUs; 0 = all
+                          (the report's "Compute Units" argument) */
+  int32_t wg_per_cu;   /* persistent workgroups per CU; 0 means 1.
+                          g = num_cu * wg_per_cu persistent workgroups */
+  int32_t mode;        /* sk_mode */
+  int64_t dp_tiles;    /* -1: hybrid rule; >= 0: S = T - min(dp_tiles, T)
+                          (ignored in SK_MODE_DP) */
+  int32_t group_m;     /* 0: row-major tile order; > 0: bands of group_m
+                          tile rows, walked down the band first */
+  int32_t xcd_remap;   /* 1: hardware workgroup b runs logical id
+                          (b mod 8)*(g/8) + b/8 (when g mod 8 == 0) so
+                          consecutive logical ids share an XCD's L2 */
+  int64_t spin_limit;  /* polls a fixup wait makes before giving up and
+                          raising SK_ERR_DEVICE_TIMEOUT; 0 = default (about
+                          four seconds) */
+} sk_config;
+
+/* One schedule segment (sk_schedule output, and the device trace). */
+typedef struct {
+  int32_t wg;        /* logical workgroup id (tile id for SK_MODE_DP) */
+  int32_t problem;   /* index into the problem array */
+  int32_t tile;      /* global tile index (problem-major) */
+  int32_t tile_m, tile_n;   /* tile coordinates inside the problem */
+  int32_t k_begin, k_end;   /* MAC iterations [k_begin, k_end) of the tile */
+  int32_t role;      /* sk_role */
+  int32_t npeers;    /* FINISH: number of partial tiles it waits for */
+} sk_segment;
+
+/* Schedule parameters of a problem set under a config. */
+typedef struct {
+  int64_t T;         /* output tiles */
+  int64_t S;         /* Stream-K tiles [0, S); data-parallel tiles [S, T) */
+  int64_t W;         /* MAC iterations of the Stream-K tiles */
+  int64_t g;         /* workgroups launched (T for SK_MODE_DP) */
+  int64_t q, rho;    /* workgroup x owns q + (x < rho) iterations */
+  int64_t workspace_bytes;
+  int64_t max_iters; /* largest per-tile iteration count */
+} sk_plan_info;
+
+/* Returns a static English description of a status code. */
+const char* sk_status_string(int32_t status);
+
+/* Device facts for the current HIP device: number of compute units, and the
+ * number of workgroups of the kernel selected by (cfg tile, dtype_ab) that
+ * can be resident on one CU at once.  Either output may be NULL. */
+sk_status sk_device_query(int32_t* num_cu, int32_t* max_wg_per_cu,
+                          const sk_config* cfg, int32_t dtype_ab);
+
+/* Lists the tiles built for dtype_ab as (block_m, block_n, block_k)
+ * triples in `out` (3*capacity ints; may be NULL to count).  `count`
+ * receives the number of tiles. */
+sk_status sk_supported_tiles(int32_t dtype_ab, int32_t* out, int32_t capacity,
+                             int32_t* count);
+
+/* Host-only.  Schedule parameters of `nprobs` problems (concatenated in the
+ * given order, as in a grouped launch) under `cfg`.  cfg->num_cu must be > 0
+ * when no HIP device is present. */
+sk_status sk_plan(const sk_problem* probs, int32_t nprobs,
+                  const sk_config* cfg, sk_plan_info* info);
+
+/* Host-only.  The complete schedule: for each logical workgroup in order,
+ * its Stream-K segments in processing order, then its data-parallel tiles
+ * in increasing tile order.  With out == NULL only *count is set; with too
+ * small a capacity *count is set and SK_ERR_CAPACITY returned. */
+sk_status sk_schedule(const sk_problem* probs, int32_t nprobs,
+                      const sk_config* cfg, sk_segment* out, int64_t capacity,
+                      int64_t* count);
+
+/* Bytes of workspace a launch of `probs` under `cfg` needs: an error word,
+ * one int32 ready flag per Stream-K tile and one FP32 partial-tile slot per
+ * persistent workgroup.  0 for SK_MODE_DP. */
+sk_status sk_workspace_size(const sk_problem* probs, int32_t nprobs,
+                            const sk_config* cfg, size_t* bytes);
+
+/* Zeroes `bytes` of workspace on `hip_stream` with a fill kernel (safe to
+ * record into a HIP graph).  Required once before a workspace's first use and
+ * after an SK_ERR_DEVICE_TIMEOUT; afterwards the flags return to zero at the
+ * end of every launch by themselves. */
+sk_status sk_workspace_init(void* workspace, size_t bytes, void* hip_stream);
+
+/* One GEMM: C_out = alpha*scale_a*scale_b*A*B + beta*C_in.
+ * workspace/ws_bytes: at least sk_workspace_size bytes, initialised once by
+ * sk_workspace_init; not shared with a concurrent launch.  May be NULL for
+ * SK_MODE_DP.  M == 0 or N == 0 is a no-op; K == 0 gives beta*C_in.
+ * Asynchronous on hip_stream; capturable into a HIP graph. */
+sk_status sk_gemm(const sk_problem* p, const void* A, const void* B,
+                  const void* C_in, void* C_out, void* workspace,
+                  size_t ws_bytes, const sk_config* cfg, void* hip_stream);
+
+/* Debug hooks of sk_gemm_debug (all device pointers may be NULL). */
+typedef struct {
+  sk_segment* trace;        /* device array: one record per segment run */
+  int64_t trace_capacity;   /* records that fit in `trace` */
+  int64_t* trace_count;     /* device counter, zeroed by the caller; receives
+                               the number of records (may exceed capacity) */
+  int32_t* cover;           /* device array [T * cover_stride], zeroed by the
+                               caller; cover[t*cover_stride + k] counts the
+                               runs of MAC iteration k of tile t */
+  int64_t cover_stride;     /* >= sk_plan_info.max_iters */
+  int32_t partial_delay;    /* sleep rounds (~64 clocks each) a PARTIAL
+                               segment waits before publishing */
+  int32_t reverse_ids;      /* 1: hardware workgroup b runs logical id
+                               g-1-b (stress of the fixup ordering) */
+} sk_debug;
+
+/* sk_gemm with the debug hooks above: same arithmetic and schedule, plus
+ * a device trace of the segments run and per-iteration coverage counts.
+ * For tests; never used for timing. */
+sk_status sk_gemm_debug(const sk_problem* p, const void* A, const void* B,
+                        const void* C_in, void* C_out, void* workspace,
+                        size_t ws_bytes, const sk_config* cfg,
+                        const sk_debug* dbg, void* hip_stream);
+
+/* Reads and clears the workspace's device error word (synchronises
+ * hip_stream).  Returns SK_ERR_DEVICE_TIMEOUT if a fixup wait of an earlier
+ * launch gave up, SK_OK otherwise; *code receives the raw word if non-NULL. */
+sk_status sk_check_device_error(void* workspace, size_t ws_bytes,
+                                int32_t* code, void* hip_stream);
+
+/* ---- Grouped GEMM: one persistent launch over several problems ----------
+ * The MAC iterations of all problems' Stream-K tiles are counted together
+ * and split evenly over the persistent workgroups; problems are
+ * concatenated in the given order.  All problems share dtype_ab, dtype_c,
+ * layout_a and layout_b. */
+
+/* Host-side plan of a grouped launch, filled by sk_grouped_prepare. */
+typedef struct {
+  int32_t nprobs;
+  int32_t mode;                 /* sk_mode the plan was made for */
+  int32_t dtype_ab, dtype_c, layout_a, layout_b;
+  int32_t block_m, block_n, block_k;
+  int64_t T, S, W, g, q, rho;
+  int64_t workspace_bytes;
+  int32_t xcd_remap, group_m;
+  int64_t spin_limit;
+  int32_t all_aligned;
+} sk_grouped_plan;
+
+/* Bytes of device descriptor memory sk_grouped_prepare needs. */
+sk_status sk_grouped_desc_size(int32_t nprobs, size_t* bytes);
+
+/* Validates the problems, computes the plan and copies the per-problem
+ * descriptors (pointers, sizes, strides, scales, tile and iteration
+ * offsets) into `dev_desc` (device memory of at least sk_grouped_desc_size
+ * bytes).  Synchronises hip_stream; not capturable.  The descriptor stays
+ * valid while the pointed-to buffers do. */
+sk_status sk_grouped_prepare(const sk_problem* probs, const void* const* A,
+                             const void* const* B, const void* const* C_in,
+                             void* const* C_out, int32_t nprobs,
+                             const sk_config* cfg, void* dev_desc,
+                             size_t desc_bytes, sk_grouped_plan* plan,
+                             void* hip_stream);
+
+/* Launches one grouped GEMM described by plan + dev_desc.  Launch only:
+ * asynchronous and capturable into a HIP graph. */
+sk_status sk_gemm_grouped(const sk_grouped_plan* plan, const void* dev_desc,
+                          void* workspace, size_t ws_bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STREAMK_H */

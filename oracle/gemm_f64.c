@@ -13,10 +13,11 @@
  *     C[i][j] = alpha * sum_{k=0}^{K-1} A(i,k) * B(k,j)  +  beta * Cin[i][j]
  *
  * in IEEE double precision, with the k-sum taken in increasing k for every
- * output element.  The loop nest is i, then k, then j (an axpy of row k of B
- * into row i of C); this is a loop interchange of the definition that keeps
- * the per-element summation order, so the result is identical to the i-j-k
- * dot-product form.  No blocking, no BLAS.
+ * output element, starting from 0.  With B column-major the loops are i, j, k
+ * (one dot product per element, both operands walked along k); with B
+ * row-major they are i, k, j (row k of B added into row i of C).  The two
+ * nests are interchanges of the same definition and give every element the
+ * same sequence of roundings.  No blocking, no BLAS.
  *
  * Layouts (element addressing):
  *   A row-major    A(i,k) = a[i*lda + k]      A column-major  A(i,k) = a[k*lda + i]
@@ -58,12 +59,18 @@ int oracle_gemm_f64(int64_t M, int64_t N, int64_t K,
         int64_t i = rows ? rows[r] : r;
         if (i < 0 || i >= M) { fail = 1; continue; }
         double *acc = c + r * ldc;
-        for (int64_t j = 0; j < N; ++j) acc[j] = 0.0;
-        for (int64_t k = 0; k < K; ++k) {
-            double aik = a_col_major ? a[k * lda + i] : a[i * lda + k];
-            if (b_col_major) {
-                for (int64_t j = 0; j < N; ++j) acc[j] += aik * b[j * ldb + k];
-            } else {
+        if (b_col_major) {
+            for (int64_t j = 0; j < N; ++j) {
+                const double *bcol = b + j * ldb;
+                double sum = 0.0;
+                for (int64_t k = 0; k < K; ++k)
+                    sum += (a_col_major ? a[k * lda + i] : a[i * lda + k]) * bcol[k];
+                acc[j] = sum;
+            }
+        } else {
+            for (int64_t j = 0; j < N; ++j) acc[j] = 0.0;
+            for (int64_t k = 0; k < K; ++k) {
+                double aik = a_col_major ? a[k * lda + i] : a[i * lda + k];
                 const double *brow = b + k * ldb;
                 for (int64_t j = 0; j < N; ++j) acc[j] += aik * brow[j];
             }

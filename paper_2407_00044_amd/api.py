@@ -1,0 +1,393 @@
+"""Torch-facing API of the Stream-K GEMM (argument marshalling only).
+
+Torch supplies device memory and streams; every arithmetic step of a GEMM
+runs in libstreamk.so's HIP kernels.  Functions here infer layouts from
+tensor strides, fill the C structures, manage the reusable workspace and
+translate status codes into exceptions.
+"""
+import ctypes
+from dataclasses import dataclass, replace
+
+import torch
+
+from . import _abi
+from ._abi import (SK_COL_MAJOR, SK_ROW_MAJOR, SkConfig, SkDebug, SkGroupedPlan,
+                   SkPlanInfo, SkProblem, SkSegment, check, load)
+
+DTYPE_CODES = {torch.float32: _abi.SK_F32, torch.float16: _abi.SK_F16,
+               torch.bfloat16: _abi.SK_BF16, torch.float8_e4m3fn: _abi.SK_F8E4M3}
+OUT_CODES = {torch.float32: _abi.SK_F32, torch.float16: _abi.SK_F16,
+             torch.bfloat16: _abi.SK_BF16}
+K_PER_ITER = {_abi.SK_F32: 32, _abi.SK_F16: 64, _abi.SK_BF16: 64, _abi.SK_F8E4M3: 128}
+
+SEGMENT_FIELDS = ("wg", "problem", "tile", "tile_m", "tile_n", "k_begin", "k_end",
+                  "role", "npeers")
+
+
+@dataclass(frozen=True)
+class Config:
+    """Launch configuration (mirrors sk_config).
+
+    tile: (block_m, block_n); block_k follows from the input type.
+    mode: 'hybrid' (data-parallel + Stream-K), 'sk' or 'dp' (baseline grid).
+    num_cu: compute units (0 = all); wg_per_cu: persistent workgroups per CU.
+    dp_tiles: -1 = two-tile hybrid rule, else number of data-parallel tiles.
+    """
+    tile: tuple = (256, 256)
+    mode: str = "hybrid"
+    num_cu: int = 0
+    wg_per_cu: int = 1
+    dp_tiles: int = -1
+    group_m: int = 0
+    xcd_remap: int = 1
+    spin_limit: int = 0
+
+    def c_struct(self, dtype_code):
+        return SkConfig(self.tile[0], self.tile[1], K_PER_ITER[dtype_code], self.num_cu,
+                        self.wg_per_cu, _abi.MODES[self.mode], self.dp_tiles, self.group_m,
+                        self.xcd_remap, self.spin_limit)
+
+
+def default_tile(M, N, K, dtype):
+    """Tile for a problem when none is given: the largest tile whose grid still
+    gives every compute unit work, smaller tiles for small or skinny shapes."""
+    code = DTYPE_CODES[dtype]
+    if code == _abi.SK_F32:
+        return (128, 128)
+    if M >= 2048 and N >= 2048:
+        return (256, 256)
+    if M >= 256 and N >= 128:
+        return (256, 128)
+    if code == _abi.SK_F8E4M3 and M <= 64:
+        return (64, 128)
+    return (128, 128)
+
+
+def operand_layout(t):
+    """(layout, ld) of a 2-D tensor with unit stride in one dimension."""
+    if t.dim() != 2:
+        raise ValueError("operands must be 2-D")
+    r, c = t.shape
+    s0, s1 = t.stride()
+    if (s1 == 1 or c <= 1) and s0 >= max(1, c):
+        return SK_ROW_MAJOR, max(s0, 1)
+    if (s0 == 1 or r <= 1) and s1 >= max(1, r):
+        return SK_COL_MAJOR, max(s1, 1)
+    raise ValueError(f"operand with strides {t.stride()} is neither row- nor column-major")
+
+
+def _problem(A, B, C, alpha, beta, scale_a, scale_b):
+    M, K = A.shape
+    K2, N = B.shape
+    if K != K2 or tuple(C.shape) != (M, N):
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, "
+                         f"C {tuple(C.shape)}")
+    if A.dtype != B.dtype or A.dtype not in DTYPE_CODES:
+        raise TypeError(f"A and B must share one of {list(DTYPE_CODES)}")
+    if C.dtype not in OUT_CODES:
+        raise TypeError(f"C must be one of {list(OUT_CODES)}")
+    la, lda = operand_layout(A)
+    lb, ldb = operand_layout(B)
+    if C.stride(1) != 1 and N > 1:
+        raise ValueError("C must be row-major")
+    ldc = max(C.stride(0), N, 1)
+    return SkProblem(M, N, K, la, lb, lda, ldb, ldc, DTYPE_CODES[A.dtype],
+                     OUT_CODES[C.dtype], alpha, beta, scale_a, scale_b)
+
+
+class Workspace:
+    """Reusable fixup workspace for one device and stream (grows on demand;
+    zeroed with the library's fill kernel whenever it is (re)allocated)."""
+
+    def __init__(self, device=None):
+        self.device = torch.device(device or "cuda")
+        self.buf = None
+
+    def get(self, nbytes, stream):
+        if nbytes == 0:
+            return None, 0
+        if self.buf is None or self.buf.numel() < nbytes:
+            size = max(nbytes, 1 << 20)
+            self.buf = torch.empty(size, dtype=torch.uint8, device=self.device)
+            check("sk_workspace_init",
+                  load().sk_workspace_init(ctypes.c_void_p(self.buf.data_ptr()),
+                                           self.buf.numel(), ctypes.c_void_p(stream)))
+        return self.buf.data_ptr(), self.buf.numel()
+
+
+_workspaces = {}
+
+
+def workspace_for(device, stream):
+    key = (torch.device(device).index, stream)
+    ws = _workspaces.get(key)
+    if ws is None:
+        ws = _workspaces[key] = Workspace(device)
+    return ws
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def gemm(A, B, C=None, *, alpha=1.0, beta=0.0, out=None, out_dtype=torch.float32,
+         scale_a=1.0, scale_b=1.0, config=None, workspace=None, stream=None):
+    """out = alpha * scale_a * scale_b * (A @ B) + beta * C on the GPU.
+
+    A (M x K) and B (K x N) may each be row- or column-major (unit stride in
+    one dimension); out and C are row-major.  With C given and out None the
+    update is in place (out = C)."""
+    lib = load()
+    if not (A.is_cuda and B.is_cuda):
+        raise ValueError("operands must be on the GPU")
+    M, N = A.shape[0], B.shape[1]
+    if out is None:
+        out = C if (C is not None and beta != 0.0) else torch.empty(
+            (M, N), dtype=out_dtype, device=A.device)
+    if beta != 0.0 and C is None:
+        raise ValueError("beta != 0 needs C")
+    cfg = config or Config(tile=default_tile(M, N, A.shape[1], A.dtype))
+    p = _problem(A, B, out, alpha, beta, scale_a, scale_b)
+    if C is not None and beta != 0.0:
+        if tuple(C.shape) != (M, N) or C.dtype != out.dtype or C.stride() != out.stride():
+            raise ValueError("C must match out in shape, dtype and strides")
+    c = cfg.c_struct(p.dtype_ab)
+    sp = _stream_ptr(stream)
+    nbytes = ctypes.c_size_t()
+    check("sk_workspace_size", lib.sk_workspace_size(ctypes.byref(p), 1, ctypes.byref(c),
+                                                      ctypes.byref(nbytes)))
+    ws = workspace or workspace_for(A.device, sp)
+    wptr, wlen = ws.get(nbytes.value, sp)
+    cin = C.data_ptr() if (C is not None and beta != 0.0) else None
+    check("sk_gemm", lib.sk_gemm(ctypes.byref(p), ctypes.c_void_p(A.data_ptr()),
+                                 ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(cin),
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(wptr),
+                                 wlen, ctypes.byref(c), ctypes.c_void_p(sp)))
+    return out
+
+
+def gemm_debug(A, B, *, out_dtype=torch.float32, config, partial_delay=0, reverse_ids=0,
+               alpha=1.0, scale_a=1.0, scale_b=1.0):
+    """gemm() through sk_gemm_debug: returns (out, segments, cover) where
+    segments is the device trace of the segments each workgroup ran (list of
+    tuples in SEGMENT_FIELDS order, sorted by workgroup, SK before DP, then
+    tile) and cover[t][k] counts the runs of MAC iteration k of tile t."""
+    lib = load()
+    M, N = A.shape[0], B.shape[1]
+    out = torch.empty((M, N), dtype=out_dtype, device=A.device)
+    p = _problem(A, B, out, alpha, 0.0, scale_a, scale_b)
+    c = config.c_struct(p.dtype_ab)
+    info = SkPlanInfo()
+    check("sk_plan", lib.sk_plan(ctypes.byref(p), 1, ctypes.byref(c), ctypes.byref(info)))
+    cap = int(info.T) * 4 + int(info.g) * 4 + 16
+    trace = torch.zeros((cap, 9), dtype=torch.int32, device=A.device)
+    count = torch.zeros(1, dtype=torch.int64, device=A.device)
+    stride = max(1, int(info.max_iters))
+    cover = torch.zeros((max(1, int(info.T)), stride), dtype=torch.int32, device=A.device)
+    dbg = SkDebug(trace.data_ptr(), cap, count.data_ptr(), cover.data_ptr(), stride,
+                  partial_delay, reverse_ids)
+    sp = _stream_ptr()
+    ws = Workspace(A.device)
+    wptr, wlen = ws.get(int(info.workspace_bytes), sp)
+    check("sk_gemm_debug", lib.sk_gemm_debug(ctypes.byref(p), ctypes.c_void_p(A.data_ptr()),
+                                             ctypes.c_void_p(B.data_ptr()), None,
+                                             ctypes.c_void_p(out.data_ptr()),
+                                             ctypes.c_void_p(wptr), wlen, ctypes.byref(c),
+                                             ctypes.byref(dbg), ctypes.c_void_p(sp)))
+    if wptr is not None:
+        code = ctypes.c_int32()
+        check("sk_check_device_error", lib.sk_check_device_error(
+            ctypes.c_void_p(wptr), wlen, ctypes.byref(code), ctypes.c_void_p(sp)))
+    torch.cuda.synchronize()
+    n = int(count.item())
+    if n > cap:
+        raise RuntimeError(f"trace overflow: {n} segments > capacity {cap}")
+    rows = [tuple(int(v) for v in r) for r in trace[:n].cpu().tolist()]
+    rows.sort(key=lambda s: (s[0], s[7] == _abi.SK_ROLE_DP, s[2]))
+    return out, rows, cover.cpu()
+
+
+def check_device_error(workspace=None, stream=None):
+    """Raise if a fixup wait of an earlier launch on this workspace timed out."""
+    sp = _stream_ptr(stream)
+    ws = workspace or workspace_for(torch.device("cuda", torch.cuda.current_device()), sp)
+    if ws.buf is None:
+        return 0
+    code = ctypes.c_int32()
+    check("sk_check_device_error", load().sk_check_device_error(
+        ctypes.c_void_p(ws.buf.data_ptr()), ws.buf.numel(), ctypes.byref(code),
+        ctypes.c_void_p(sp)))
+    return code.value
+
+
+# ---------------------------------------------------------------------------
+# Host-only queries (no GPU needed when num_cu is given).
+
+def _host_problem(M, N, K, dtype, layout_a="row", layout_b="col"):
+    code = DTYPE_CODES[dtype] if isinstance(dtype, torch.dtype) else dtype
+    la = SK_ROW_MAJOR if layout_a == "row" else SK_COL_MAJOR
+    lb = SK_ROW_MAJOR if layout_b == "row" else SK_COL_MAJOR
+    lda = max(1, K if la == SK_ROW_MAJOR else M)
+    ldb = max(1, N if lb == SK_ROW_MAJOR else K)
+    return SkProblem(M, N, K, la, lb, lda, ldb, max(1, N), code, _abi.SK_F32, 1.0, 0.0,
+                     1.0, 1.0)
+
+
+def _problems_array(shapes, dtype):
+    arr = (SkProblem * len(shapes))()
+    for i, (M, N, K) in enumerate(shapes):
+        arr[i] = _host_problem(M, N, K, dtype)
+    return arr
+
+
+def plan(shapes, dtype, config):
+    """Schedule parameters (dict) of problems [(M, N, K), ...]."""
+    lib = load()
+    probs = _problems_array(shapes, dtype)
+    c = config.c_struct(probs[0].dtype_ab)
+    info = SkPlanInfo()
+    check("sk_plan", lib.sk_plan(probs, len(shapes), ctypes.byref(c), ctypes.byref(info)))
+    return {f: int(getattr(info, f)) for f, _ in SkPlanInfo._fields_}
+
+
+def schedule(shapes, dtype, config):
+    """Full schedule from the library's host code: list of segment tuples."""
+    lib = load()
+    probs = _problems_array(shapes, dtype)
+    c = config.c_struct(probs[0].dtype_ab)
+    count = ctypes.c_int64()
+    check("sk_schedule", lib.sk_schedule(probs, len(shapes), ctypes.byref(c), None, 0,
+                                         ctypes.byref(count)))
+    segs = (SkSegment * max(1, count.value))()
+    check("sk_schedule", lib.sk_schedule(probs, len(shapes), ctypes.byref(c), segs,
+                                         count.value, ctypes.byref(count)))
+    return [tuple(getattr(segs[i], f) for f in SEGMENT_FIELDS) for i in range(count.value)]
+
+
+def supported_tiles(dtype):
+    lib = load()
+    code = DTYPE_CODES[dtype] if isinstance(dtype, torch.dtype) else dtype
+    n = ctypes.c_int32()
+    check("sk_supported_tiles", lib.sk_supported_tiles(code, None, 0, ctypes.byref(n)))
+    buf = (ctypes.c_int32 * (3 * n.value))()
+    check("sk_supported_tiles", lib.sk_supported_tiles(code, buf, n.value, ctypes.byref(n)))
+    return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(n.value)]
+
+
+def device_query(config=None, dtype=torch.bfloat16):
+    lib = load()
+    cus = ctypes.c_int32()
+    per = ctypes.c_int32()
+    cfg = config or Config()
+    c = cfg.c_struct(DTYPE_CODES[dtype])
+    check("sk_device_query", lib.sk_device_query(ctypes.byref(cus), ctypes.byref(per),
+                                                 ctypes.byref(c), DTYPE_CODES[dtype]))
+    return cus.value, per.value
+
+
+# ---------------------------------------------------------------------------
+# Grouped GEMM.
+
+class GroupedGemm:
+    """One persistent Stream-K launch over several problems.
+
+    problems: list of (A, B, out) or (A, B, out, C_in, beta) tuples sharing
+    the input dtype, output dtype and operand layouts.  Descriptors and the
+    workspace are set up once here (not capturable); run() only launches and
+    can be captured into a HIP graph (torch.cuda.CUDAGraph)."""
+
+    def __init__(self, problems, config=None, alpha=1.0, scales=None, stream=None):
+        lib = load()
+        n = len(problems)
+        if n == 0:
+            raise ValueError("no problems")
+        self.problems = problems
+        probs = (SkProblem * n)()
+        ptrs = {k: (ctypes.c_void_p * n)() for k in ("A", "B", "Cin", "Cout")}
+        for i, pr in enumerate(problems):
+            A, B, out = pr[:3]
+            Cin = pr[3] if len(pr) > 3 else None
+            beta = pr[4] if len(pr) > 4 else 0.0
+            sa, sb = scales[i] if scales is not None else (1.0, 1.0)
+            probs[i] = _problem(A, B, out, alpha, beta, sa, sb)
+            ptrs["A"][i] = A.data_ptr()
+            ptrs["B"][i] = B.data_ptr()
+            ptrs["Cin"][i] = Cin.data_ptr() if (Cin is not None and beta != 0.0) else None
+            ptrs["Cout"][i] = out.data_ptr()
+        dev = problems[0][0].device
+        M0, N0, K0 = probs[0].M, probs[0].N, probs[0].K
+        self.config = config or Config(tile=default_tile(M0, N0, K0, problems[0][0].dtype))
+        c = self.config.c_struct(probs[0].dtype_ab)
+        dbytes = ctypes.c_size_t()
+        check("sk_grouped_desc_size", lib.sk_grouped_desc_size(n, ctypes.byref(dbytes)))
+        self.desc = torch.empty(dbytes.value, dtype=torch.uint8, device=dev)
+        self.plan = SkGroupedPlan()
+        sp = _stream_ptr(stream)
+        check("sk_grouped_prepare", lib.sk_grouped_prepare(
+            probs, ptrs["A"], ptrs["B"], ptrs["Cin"], ptrs["Cout"], n, ctypes.byref(c),
+            ctypes.c_void_p(self.desc.data_ptr()), dbytes.value, ctypes.byref(self.plan),
+            ctypes.c_void_p(sp)))
+        self.workspace = Workspace(dev)
+        self.ws_ptr, self.ws_len = self.workspace.get(int(self.plan.workspace_bytes), sp)
+        torch.cuda.current_stream().synchronize()
+
+    def info(self):
+        return {f: int(getattr(self.plan, f)) for f, _ in SkGroupedPlan._fields_}
+
+    def run(self, stream=None):
+        check("sk_gemm_grouped", load().sk_gemm_grouped(
+            ctypes.byref(self.plan), ctypes.c_void_p(self.desc.data_ptr()),
+            ctypes.c_void_p(self.ws_ptr), self.ws_len, ctypes.c_void_p(_stream_ptr(stream))))
+
+    def capture(self):
+        """A torch.cuda.CUDAGraph (a HIP graph on ROCm) holding one run()."""
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.run()   # warm-up launch outside the graph
+        torch.cuda.current_stream().wait_stream(s)
+        with torch.cuda.graph(g):
+            self.run()
+        return g
+
+
+# ---------------------------------------------------------------------------
+# Differentiable linear layer.
+
+class StreamKLinearFn(torch.autograd.Function):
+    """Y = X @ W^T with a hand-written backward through the same kernels:
+    dX = dY @ W and dW = dY^T @ X, expressed purely with layout flags (W read
+    as a column-major K x N operand in the forward; dY read column-major for
+    dW), so no transposed copies are made."""
+
+    @staticmethod
+    def forward(ctx, X, W, config_fwd=None, config_dx=None, config_dw=None):
+        ctx.save_for_backward(X, W)
+        ctx.cfgs = (config_dx, config_dw)
+        Y = torch.empty((X.shape[0], W.shape[0]), dtype=X.dtype, device=X.device)
+        return gemm(X, W.t(), out=Y, config=config_fwd)
+
+    @staticmethod
+    def backward(ctx, dY):
+        X, W = ctx.saved_tensors
+        cfg_dx, cfg_dw = ctx.cfgs
+        if dY.stride(1) != 1 and dY.stride(0) != 1:
+            dY = dY.contiguous()
+        dX = dW = None
+        if ctx.needs_input_grad[0]:
+            dX = torch.empty_like(X, memory_format=torch.contiguous_format)
+            gemm(dY, W, out=dX, config=cfg_dx)
+        if ctx.needs_input_grad[1]:
+            dW = torch.empty_like(W, memory_format=torch.contiguous_format)
+            gemm(dY.t(), X, out=dW, config=cfg_dw)
+        return dX, dW, None, None, None
+
+
+def linear(X, W, config_fwd=None, config_dx=None, config_dw=None):
+    return StreamKLinearFn.apply(X, W, config_fwd, config_dx, config_dw)
+
+
+def with_tile(config, tile):
+    return replace(config, tile=tuple(tile))

@@ -1,0 +1,518 @@
+// C ABI of the Stream-K GEMM library: validation, planning, schedule
+// enumeration and kernel launches.  See include/streamk.h for the contract of
+// every entry point.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "../../include/streamk.h"
+#include "sk_params.hpp"
+#include "sk_registry.hpp"
+#include "sk_sched.hpp"
+
+namespace sk {
+
+static std::vector<KernelEntry>& registry() {
+  static std::vector<KernelEntry> r;
+  return r;
+}
+
+bool register_kernel(const KernelEntry& e) {
+  registry().push_back(e);
+  return true;
+}
+
+static const KernelEntry* find_kernel(int dt, int la, int lb, int bm, int bn) {
+  for (const KernelEntry& e : registry())
+    if (e.dt == dt && e.la == la && e.lb == lb && e.bm == bm && e.bn == bn) return &e;
+  return nullptr;
+}
+
+static bool tile_built(int dt, int bm, int bn) {
+  for (const KernelEntry& e : registry())
+    if (e.dt == dt && e.bm == bm && e.bn == bn) return true;
+  return false;
+}
+
+// Default fixup-wait bound: polls of ~128 clocks of s_sleep plus an L2 round
+// trip each, a few seconds in all.
+constexpr int64_t kDefaultSpinLimit = int64_t(1) << 22;
+constexpr int64_t kMaxIndex = (int64_t(1) << 31) - 1;
+
+struct Plan {
+  int64_t T = 0, S = 0, W = 0, g = 0, q = 0, rho = 0, max_iters = 0;
+  int64_t ws_bytes = 0;
+  std::vector<ProbDesc> descs;   // pointers left null by plan_problems
+};
+
+static sk_status device_cus(int32_t* n) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SK_ERR_HIP;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return SK_ERR_HIP;
+  *n = v;
+  return SK_OK;
+}
+
+static sk_status check_problem(const sk_problem& p) {
+  if (p.M < 0 || p.N < 0 || p.K < 0) return SK_ERR_INVALID_ARG;
+  if (p.M > kMaxIndex || p.N > kMaxIndex || p.K > kMaxIndex) return SK_ERR_UNSUPPORTED;
+  if (p.dtype_ab < 0 || p.dtype_ab > 3) return SK_ERR_UNSUPPORTED;
+  if (p.dtype_c < 0 || p.dtype_c > 2) return SK_ERR_UNSUPPORTED;
+  if ((p.layout_a != SK_ROW_MAJOR && p.layout_a != SK_COL_MAJOR) ||
+      (p.layout_b != SK_ROW_MAJOR && p.layout_b != SK_COL_MAJOR))
+    return SK_ERR_INVALID_ARG;
+  const int64_t need_a = p.layout_a == SK_ROW_MAJOR ? p.K : p.M;
+  const int64_t need_b = p.layout_b == SK_ROW_MAJOR ? p.N : p.K;
+  if (p.lda < std::max<int64_t>(1, need_a)) return SK_ERR_INVALID_ARG;
+  if (p.ldb < std::max<int64_t>(1, need_b)) return SK_ERR_INVALID_ARG;
+  if (p.ldc < std::max<int64_t>(1, p.N)) return SK_ERR_INVALID_ARG;
+  return SK_OK;
+}
+
+// Resolves g and checks the config against the tile menu.
+static sk_status resolve_config(const sk_config* cfg, int32_t dtype_ab, int64_t* g_out) {
+  if (cfg == nullptr) return SK_ERR_INVALID_ARG;
+  if (cfg->mode < 0 || cfg->mode > 2) return SK_ERR_INVALID_ARG;
+  if (cfg->block_k != k_per_iter(dtype_ab)) return SK_ERR_UNSUPPORTED;
+  if (!tile_built(dtype_ab, cfg->block_m, cfg->block_n)) return SK_ERR_UNSUPPORTED;
+  if (cfg->group_m < 0 || cfg->wg_per_cu < 0 || cfg->num_cu < 0) return SK_ERR_INVALID_ARG;
+  if (cfg->dp_tiles < -1) return SK_ERR_INVALID_ARG;
+  if (cfg->spin_limit < 0) return SK_ERR_INVALID_ARG;
+  int32_t cus = cfg->num_cu;
+  if (cus == 0) {
+    sk_status st = device_cus(&cus);
+    if (st != SK_OK) return st;
+  }
+  const int64_t wpc = cfg->wg_per_cu == 0 ? 1 : cfg->wg_per_cu;
+  *g_out = (int64_t)cus * wpc;
+  return SK_OK;
+}
+
+// Tile counts, split point, iteration space and per-problem offsets.
+static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_config* cfg,
+                               Plan* out) {
+  if (probs == nullptr || n <= 0) return SK_ERR_INVALID_ARG;
+  for (int32_t i = 0; i < n; ++i) {
+    sk_status st = check_problem(probs[i]);
+    if (st != SK_OK) return st;
+    if (probs[i].dtype_ab != probs[0].dtype_ab || probs[i].dtype_c != probs[0].dtype_c ||
+        probs[i].layout_a != probs[0].layout_a || probs[i].layout_b != probs[0].layout_b)
+      return SK_ERR_UNSUPPORTED;
+  }
+  int64_t g = 0;
+  sk_status st = resolve_config(cfg, probs[0].dtype_ab, &g);
+  if (st != SK_OK) return st;
+  const int64_t bm = cfg->block_m, bn = cfg->block_n, bk = cfg->block_k;
+
+  Plan P;
+  P.descs.resize(n);
+  int64_t T = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const sk_problem& p = probs[i];
+    ProbDesc& d = P.descs[i];
+    memset(&d, 0, sizeof(d));
+    d.M = p.M; d.N = p.N; d.K = p.K;
+    d.lda = p.lda; d.ldb = p.ldb; d.ldc = p.ldc;
+    d.alpha_s = p.alpha * p.scale_a * p.scale_b;
+    d.beta = p.beta;
+    d.tm = (int32_t)(p.M > 0 ? cdiv(p.M, bm) : 0);
+    d.tn = (int32_t)(p.N > 0 ? cdiv(p.N, bn) : 0);
+    d.I = (int32_t)std::max<int64_t>(1, cdiv(p.K, bk));
+    d.tile_start = T;
+    T += (int64_t)d.tm * d.tn;
+    P.max_iters = std::max<int64_t>(P.max_iters, d.I);
+  }
+  if (T > kMaxIndex) return SK_ERR_UNSUPPORTED;
+  P.T = T;
+  if (cfg->mode == SK_MODE_DP) {
+    P.S = 0;
+    P.g = T;
+  } else {
+    P.g = g;
+    P.S = split_point(T, g, cfg->mode, cfg->dp_tiles);
+  }
+  // Stream-K iteration offsets (problem-major, so J is monotone in p).
+  int64_t J = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    ProbDesc& d = P.descs[i];
+    const int64_t ti = (int64_t)d.tm * d.tn;
+    d.iter_start = J;
+    const int64_t sk_tiles = std::max<int64_t>(0, std::min<int64_t>(ti, P.S - d.tile_start));
+    J += sk_tiles * d.I;
+  }
+  if (J > kMaxIndex) return SK_ERR_UNSUPPORTED;
+  P.W = J;
+  if (cfg->mode != SK_MODE_DP && P.g > 0) {
+    P.q = P.W / P.g;
+    P.rho = P.W % P.g;
+  }
+  P.ws_bytes = cfg->mode == SK_MODE_DP ? 0
+                                       : ws_bytes(P.S, P.S > 0 ? P.g : 0, bm, bn);
+  *out = std::move(P);
+  return SK_OK;
+}
+
+// Host mirror of the kernel's tile lookups.
+static int32_t host_find_problem(const Plan& P, int64_t key, bool by_iter) {
+  int32_t lo = 0, hi = (int32_t)P.descs.size() - 1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    int64_t s = by_iter ? P.descs[mid].iter_start : P.descs[mid].tile_start;
+    if (s <= key) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+static void host_segments(const Plan& P, const sk_config* cfg, std::vector<sk_segment>* out) {
+  auto emit = [&](int64_t x, int32_t p, int64_t t, int64_t u, int kb, int ke, int role,
+                  int npeers) {
+    const ProbDesc& d = P.descs[p];
+    sk_segment s;
+    s.wg = (int32_t)x;
+    s.problem = p;
+    s.tile = (int32_t)t;
+    tile_coords(u, d.tm, d.tn, cfg->group_m, &s.tile_m, &s.tile_n);
+    s.k_begin = kb;
+    s.k_end = ke;
+    s.role = role;
+    s.npeers = npeers;
+    out->push_back(s);
+  };
+  if (cfg->mode == SK_MODE_DP) {
+    for (int64_t t = 0; t < P.T; ++t) {
+      int32_t p = host_find_problem(P, t, false);
+      emit(t, p, t, t - P.descs[p].tile_start, 0, P.descs[p].I, SK_ROLE_DP, 0);
+    }
+    return;
+  }
+  for (int64_t x = 0; x < P.g; ++x) {
+    const int64_t s = range_begin(x, P.q, P.rho);
+    const int64_t e = s + P.q + (x < P.rho ? 1 : 0);
+    int64_t it = s;
+    while (it < e) {
+      int32_t p = host_find_problem(P, it, true);
+      const ProbDesc& d = P.descs[p];
+      int64_t u = (it - d.iter_start) / d.I;
+      int64_t J = d.iter_start + u * d.I;
+      int kb = (int)(it - J);
+      int ke = (int)(std::min(e, J + d.I) - J);
+      int role, npeers = 0;
+      if (kb > 0) role = SK_ROLE_PARTIAL;
+      else if (ke == d.I) role = SK_ROLE_FULL;
+      else {
+        role = SK_ROLE_FINISH;
+        npeers = (int)(iter_owner(J + d.I - 1, P.q, P.rho) - x);
+      }
+      emit(x, p, d.tile_start + u, u, kb, ke, role, npeers);
+      it = J + ke;
+    }
+    for (int64_t t = P.S + x; t < P.T; t += P.g) {
+      int32_t p = host_find_problem(P, t, false);
+      emit(x, p, t, t - P.descs[p].tile_start, 0, P.descs[p].I, SK_ROLE_DP, 0);
+    }
+  }
+}
+
+__global__ void fill_zero_kernel(uint32_t* p, int64_t words) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+static sk_status launch(const Plan& P, const sk_config* cfg, int32_t dt, int32_t la, int32_t lb,
+                        int32_t dtype_c, const ProbDesc* single, const ProbDesc* dev_group,
+                        int32_t nprobs, void* ws, size_t ws_len, const sk_debug* dbg,
+                        hipStream_t stream) {
+  const KernelEntry* ke = find_kernel(dt, la, lb, cfg->block_m, cfg->block_n);
+  if (ke == nullptr) return SK_ERR_UNSUPPORTED;
+  if (P.T == 0) return SK_OK;
+  if (cfg->mode != SK_MODE_DP) {
+    if (ws == nullptr || (int64_t)ws_len < P.ws_bytes) return SK_ERR_WORKSPACE;
+    int32_t cus = 0;
+    sk_status st = device_cus(&cus);
+    if (st != SK_OK) return st;
+    if (cfg->num_cu > cus) return SK_ERR_INVALID_ARG;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ke->fn, 256, 0) != hipSuccess)
+      return SK_ERR_HIP;
+    // Stream-K workgroups wait for each other: all must be resident at once.
+    if (P.g > (int64_t)cus * per_cu) return SK_ERR_OCCUPANCY;
+  }
+  KParams kp;
+  memset(&kp, 0, sizeof(kp));
+  if (single) kp.prob = *single;
+  kp.group = dev_group;
+  kp.nprobs = nprobs;
+  kp.dtype_c = dtype_c;
+  kp.T = P.T; kp.S = P.S; kp.W = P.W; kp.g = P.g; kp.q = P.q; kp.rho = P.rho;
+  kp.group_m = cfg->group_m;
+  kp.xcd_remap = cfg->xcd_remap;
+  kp.dp_grid = cfg->mode == SK_MODE_DP ? 1 : 0;
+  kp.spin_limit = cfg->spin_limit > 0 ? cfg->spin_limit : kDefaultSpinLimit;
+  if (ws) {
+    char* w = (char*)ws;
+    kp.err = (int32_t*)w;
+    kp.flags = (int32_t*)(w + ws_flags_offset());
+    kp.slots = (float*)(w + ws_slots_offset(P.S));
+  }
+  if (dbg) {
+    kp.trace = dbg->trace;
+    kp.trace_cap = dbg->trace_capacity;
+    kp.trace_count = dbg->trace_count;
+    kp.cover = dbg->cover;
+    kp.cover_stride = dbg->cover_stride;
+    kp.partial_delay = dbg->partial_delay;
+    kp.reverse_ids = dbg->reverse_ids;
+    if (kp.trace && !kp.trace_count) return SK_ERR_INVALID_ARG;
+    if (kp.cover && kp.cover_stride < P.max_iters) return SK_ERR_INVALID_ARG;
+  }
+  void* args[] = {&kp};
+  const int64_t grid = cfg->mode == SK_MODE_DP ? P.T : P.g;
+  if (hipLaunchKernel(ke->fn, dim3((unsigned)grid), dim3(256), args, 0, stream) != hipSuccess)
+    return SK_ERR_HIP;
+  return SK_OK;
+}
+
+static sk_status gemm_common(const sk_problem* p, const void* A, const void* B, const void* Cin,
+                             void* Cout, void* ws, size_t ws_bytes_, const sk_config* cfg,
+                             const sk_debug* dbg, void* stream) {
+  if (p == nullptr) return SK_ERR_INVALID_ARG;
+  Plan P;
+  sk_status st = plan_problems(p, 1, cfg, &P);
+  if (st != SK_OK) return st;
+  if (p->M == 0 || p->N == 0) return SK_OK;
+  if (Cout == nullptr) return SK_ERR_INVALID_ARG;
+  if (p->K > 0 && (A == nullptr || B == nullptr)) return SK_ERR_INVALID_ARG;
+  if (p->beta != 0.f && Cin == nullptr) return SK_ERR_INVALID_ARG;
+  ProbDesc& d = P.descs[0];
+  d.A = A; d.B = B; d.Cin = Cin; d.Cout = Cout;
+  const int eb = elem_bytes(p->dtype_ab);
+  d.aligned = aligned16(A) && aligned16(B) && (p->lda * eb) % 16 == 0 && (p->ldb * eb) % 16 == 0;
+  return launch(P, cfg, p->dtype_ab, p->layout_a, p->layout_b, p->dtype_c, &d, nullptr, 1, ws,
+                ws_bytes_, dbg, (hipStream_t)stream);
+}
+
+}  // namespace sk
+
+using namespace sk;
+
+extern "C" {
+
+const char* sk_status_string(int32_t status) {
+  switch (status) {
+    case SK_OK: return "success";
+    case SK_ERR_INVALID_ARG: return "invalid argument";
+    case SK_ERR_UNSUPPORTED: return "unsupported dtype, layout or tile";
+    case SK_ERR_WORKSPACE: return "workspace missing or too small";
+    case SK_ERR_OCCUPANCY: return "more persistent workgroups than can be resident";
+    case SK_ERR_HIP: return "HIP runtime error";
+    case SK_ERR_CAPACITY: return "output array too small";
+    case SK_ERR_DEVICE_TIMEOUT: return "a fixup wait on the device timed out";
+    default: return "unknown status";
+  }
+}
+
+sk_status sk_device_query(int32_t* num_cu, int32_t* max_wg_per_cu, const sk_config* cfg,
+                          int32_t dtype_ab) {
+  int32_t cus = 0;
+  sk_status st = device_cus(&cus);
+  if (st != SK_OK) return st;
+  if (num_cu) *num_cu = cus;
+  if (max_wg_per_cu) {
+    if (cfg == nullptr) return SK_ERR_INVALID_ARG;
+    const KernelEntry* ke = nullptr;
+    for (int la = 0; la < 2 && !ke; ++la)
+      for (int lb = 0; lb < 2 && !ke; ++lb)
+        ke = find_kernel(dtype_ab, la, lb, cfg->block_m, cfg->block_n);
+    if (ke == nullptr) return SK_ERR_UNSUPPORTED;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ke->fn, 256, 0) != hipSuccess)
+      return SK_ERR_HIP;
+    *max_wg_per_cu = per_cu;
+  }
+  return SK_OK;
+}
+
+sk_status sk_supported_tiles(int32_t dtype_ab, int32_t* out, int32_t capacity, int32_t* count) {
+  if (count == nullptr) return SK_ERR_INVALID_ARG;
+  std::vector<std::pair<int, int>> tiles;
+  for (const KernelEntry& e : registry())
+    if (e.dt == dtype_ab &&
+        std::find(tiles.begin(), tiles.end(), std::make_pair(e.bm, e.bn)) == tiles.end())
+      tiles.push_back({e.bm, e.bn});
+  std::sort(tiles.begin(), tiles.end());
+  *count = (int32_t)tiles.size();
+  if (out == nullptr) return SK_OK;
+  if (capacity < (int32_t)tiles.size()) return SK_ERR_CAPACITY;
+  for (size_t i = 0; i < tiles.size(); ++i) {
+    out[3 * i] = tiles[i].first;
+    out[3 * i + 1] = tiles[i].second;
+    out[3 * i + 2] = k_per_iter(dtype_ab);
+  }
+  return SK_OK;
+}
+
+sk_status sk_plan(const sk_problem* probs, int32_t nprobs, const sk_config* cfg,
+                  sk_plan_info* info) {
+  if (info == nullptr) return SK_ERR_INVALID_ARG;
+  Plan P;
+  sk_status st = plan_problems(probs, nprobs, cfg, &P);
+  if (st != SK_OK) return st;
+  info->T = P.T; info->S = P.S; info->W = P.W; info->g = P.g;
+  info->q = P.q; info->rho = P.rho;
+  info->workspace_bytes = P.ws_bytes;
+  info->max_iters = P.max_iters;
+  return SK_OK;
+}
+
+sk_status sk_schedule(const sk_problem* probs, int32_t nprobs, const sk_config* cfg,
+                      sk_segment* out, int64_t capacity, int64_t* count) {
+  if (count == nullptr) return SK_ERR_INVALID_ARG;
+  Plan P;
+  sk_status st = plan_problems(probs, nprobs, cfg, &P);
+  if (st != SK_OK) return st;
+  std::vector<sk_segment> segs;
+  host_segments(P, cfg, &segs);
+  *count = (int64_t)segs.size();
+  if (out == nullptr) return SK_OK;
+  if (capacity < (int64_t)segs.size()) return SK_ERR_CAPACITY;
+  if (!segs.empty()) memcpy(out, segs.data(), segs.size() * sizeof(sk_segment));
+  return SK_OK;
+}
+
+sk_status sk_workspace_size(const sk_problem* probs, int32_t nprobs, const sk_config* cfg,
+                            size_t* bytes) {
+  if (bytes == nullptr) return SK_ERR_INVALID_ARG;
+  Plan P;
+  sk_status st = plan_problems(probs, nprobs, cfg, &P);
+  if (st != SK_OK) return st;
+  *bytes = (size_t)P.ws_bytes;
+  return SK_OK;
+}
+
+sk_status sk_workspace_init(void* workspace, size_t bytes, void* stream) {
+  if (bytes == 0) return SK_OK;
+  if (workspace == nullptr || !aligned16(workspace) || bytes % 4 != 0) return SK_ERR_INVALID_ARG;
+  const int64_t words = (int64_t)(bytes / 4);
+  const int64_t blocks = std::min<int64_t>(1024, (words + 255) / 256);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     (hipStream_t)stream, (uint32_t*)workspace, words);
+  return hipGetLastError() == hipSuccess ? SK_OK : SK_ERR_HIP;
+}
+
+sk_status sk_gemm(const sk_problem* p, const void* A, const void* B, const void* C_in,
+                  void* C_out, void* workspace, size_t ws_bytes_, const sk_config* cfg,
+                  void* stream) {
+  return gemm_common(p, A, B, C_in, C_out, workspace, ws_bytes_, cfg, nullptr, stream);
+}
+
+sk_status sk_gemm_debug(const sk_problem* p, const void* A, const void* B, const void* C_in,
+                        void* C_out, void* workspace, size_t ws_bytes_, const sk_config* cfg,
+                        const sk_debug* dbg, void* stream) {
+  if (dbg == nullptr) return SK_ERR_INVALID_ARG;
+  return gemm_common(p, A, B, C_in, C_out, workspace, ws_bytes_, cfg, dbg, stream);
+}
+
+sk_status sk_check_device_error(void* workspace, size_t ws_bytes_, int32_t* code,
+                                void* stream) {
+  if (workspace == nullptr || ws_bytes_ < 4) return SK_ERR_INVALID_ARG;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SK_ERR_HIP;
+  int32_t v = 0;
+  if (hipMemcpy(&v, workspace, 4, hipMemcpyDeviceToHost) != hipSuccess) return SK_ERR_HIP;
+  if (v != 0) {
+    int32_t z = 0;
+    if (hipMemcpy(workspace, &z, 4, hipMemcpyHostToDevice) != hipSuccess) return SK_ERR_HIP;
+  }
+  if (code) *code = v;
+  return v != 0 ? SK_ERR_DEVICE_TIMEOUT : SK_OK;
+}
+
+sk_status sk_grouped_desc_size(int32_t nprobs, size_t* bytes) {
+  if (bytes == nullptr || nprobs <= 0) return SK_ERR_INVALID_ARG;
+  *bytes = (size_t)nprobs * sizeof(ProbDesc);
+  return SK_OK;
+}
+
+sk_status sk_grouped_prepare(const sk_problem* probs, const void* const* A,
+                             const void* const* B, const void* const* C_in, void* const* C_out,
+                             int32_t nprobs, const sk_config* cfg, void* dev_desc,
+                             size_t desc_bytes, sk_grouped_plan* plan, void* stream) {
+  if (plan == nullptr || A == nullptr || B == nullptr || C_out == nullptr || dev_desc == nullptr)
+    return SK_ERR_INVALID_ARG;
+  Plan P;
+  sk_status st = plan_problems(probs, nprobs, cfg, &P);
+  if (st != SK_OK) return st;
+  if (desc_bytes < (size_t)nprobs * sizeof(ProbDesc)) return SK_ERR_WORKSPACE;
+  const int eb = elem_bytes(probs[0].dtype_ab);
+  int32_t all_aligned = 1;
+  for (int32_t i = 0; i < nprobs; ++i) {
+    const sk_problem& p = probs[i];
+    ProbDesc& d = P.descs[i];
+    d.A = A[i]; d.B = B[i]; d.Cout = C_out[i];
+    d.Cin = C_in ? C_in[i] : nullptr;
+    const bool empty = p.M == 0 || p.N == 0;
+    if (!empty) {
+      if (d.Cout == nullptr) return SK_ERR_INVALID_ARG;
+      if (p.K > 0 && (d.A == nullptr || d.B == nullptr)) return SK_ERR_INVALID_ARG;
+      if (p.beta != 0.f && d.Cin == nullptr) return SK_ERR_INVALID_ARG;
+    }
+    d.aligned = aligned16(d.A) && aligned16(d.B) && (p.lda * eb) % 16 == 0 &&
+                (p.ldb * eb) % 16 == 0;
+    all_aligned &= d.aligned;
+  }
+  if (hipMemcpyAsync(dev_desc, P.descs.data(), (size_t)nprobs * sizeof(ProbDesc),
+                     hipMemcpyHostToDevice, (hipStream_t)stream) != hipSuccess)
+    return SK_ERR_HIP;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SK_ERR_HIP;
+  memset(plan, 0, sizeof(*plan));
+  plan->nprobs = nprobs;
+  plan->mode = cfg->mode;
+  plan->dtype_ab = probs[0].dtype_ab;
+  plan->dtype_c = probs[0].dtype_c;
+  plan->layout_a = probs[0].layout_a;
+  plan->layout_b = probs[0].layout_b;
+  plan->block_m = cfg->block_m;
+  plan->block_n = cfg->block_n;
+  plan->block_k = cfg->block_k;
+  plan->T = P.T; plan->S = P.S; plan->W = P.W; plan->g = P.g;
+  plan->q = P.q; plan->rho = P.rho;
+  plan->workspace_bytes = P.ws_bytes;
+  plan->xcd_remap = cfg->xcd_remap;
+  plan->group_m = cfg->group_m;
+  plan->spin_limit = cfg->spin_limit;
+  plan->all_aligned = all_aligned;
+  return SK_OK;
+}
+
+sk_status sk_gemm_grouped(const sk_grouped_plan* plan, const void* dev_desc, void* workspace,
+                          size_t ws_bytes_, void* stream) {
+  if (plan == nullptr || dev_desc == nullptr || plan->nprobs <= 0) return SK_ERR_INVALID_ARG;
+  Plan P;
+  P.T = plan->T; P.S = plan->S; P.W = plan->W; P.g = plan->g;
+  P.q = plan->q; P.rho = plan->rho;
+  P.ws_bytes = plan->workspace_bytes;
+  sk_config cfg;
+  memset(&cfg, 0, sizeof(cfg));
+  cfg.block_m = plan->block_m;
+  cfg.block_n = plan->block_n;
+  cfg.block_k = plan->block_k;
+  cfg.xcd_remap = plan->xcd_remap;
+  cfg.group_m = plan->group_m;
+  cfg.spin_limit = plan->spin_limit;
+  if (plan->mode < 0 || plan->mode > 2) return SK_ERR_INVALID_ARG;
+  cfg.mode = plan->mode;
+  return launch(P, &cfg, plan->dtype_ab, plan->layout_a, plan->layout_b, plan->dtype_c, nullptr,
+                (const ProbDesc*)dev_desc, plan->nprobs, workspace, ws_bytes_, nullptr,
+                (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,30 @@
+// Kernel instantiations for one (input type, A layout, B layout) triple,
+// selected by -DSK_DT / -DSK_LA / -DSK_LB at compile time.  The tile menu
+// per input type is listed here.
+#include "sk_kernel.hpp"
+#include "sk_registry.hpp"
+
+#ifndef SK_DT
+#error "SK_DT must be defined"
+#endif
+
+#define SK_CAT_(a, b) a##b
+#define SK_CAT(a, b) SK_CAT_(a, b)
+#define SK_INST(BM, BN, WGM)                                                          \
+  static const bool SK_CAT(reg_, __LINE__) = sk::register_kernel(                     \
+      {SK_DT, SK_LA, SK_LB, BM, BN, WGM,                                              \
+       (const void*)&sk::sk_gemm_kernel<sk::Cfg<SK_DT, SK_LA, SK_LB, BM, BN, WGM>>});
+
+#if SK_DT == 0
+// f32: 128x128x32 (the 512^3 Stream-K configuration)
+SK_INST(128, 128, 2)
+#else
+// f16 / bf16 / e4m3: large tiles for compute-bound shapes, smaller ones for
+// small or skinny problems
+SK_INST(256, 256, 2)
+SK_INST(256, 128, 2)
+SK_INST(128, 128, 2)
+#if SK_DT == 3
+SK_INST(64, 128, 2)
+#endif
+#endif

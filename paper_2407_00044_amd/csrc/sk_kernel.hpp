@@ -1,0 +1,765 @@
+// Stream-K GEMM kernel for gfx950 (CDNA4).
+//
+// One kernel template serves every mode:
+//  * persistent Stream-K / hybrid: g workgroups; logical workgroup x runs its
+//    even share [s_x, e_x) of the Stream-K tiles' MAC iterations (Background
+//    section: even work units over all cores), finishing or contributing to
+//    split tiles through the FP32 partial-tile workspace, then its
+//    data-parallel tiles S+x, S+x+g, ...;
+//  * baseline data-parallel grid: one workgroup per tile.
+//
+// Tile datapath (per MAC iteration = 128 bytes of K):
+//  * global -> registers with 16-byte loads, rows of 128 contiguous bytes of
+//    K; operands stored with M (or N) contiguous are transposed in registers
+//    so that LDS always holds K-contiguous rows;
+//  * LDS, double-buffered; the 16-byte chunk c of row r is stored at
+//    position c ^ ((r & 7) ^ ((r >> 3) & 3)), which keeps 8, 16 or 32
+//    consecutive rows reading the same chunk on distinct banks and repeats
+//    every 32 rows (so per-lane LDS addresses are shared by all 32-row
+//    blocks of a wave);
+//  * LDS -> MFMA operands with 16-byte reads; 32x32 MFMA blocks accumulate in
+//    FP32 (v_mfma_f32_32x32x2_f32, _32x32x16_f16/_bf16, and the block-scaled
+//    32x32x64 f8f6f4 form with unit scales for e4m3).
+//  A and B fragments are read with the same (lane, slot) -> k assignment, so
+//  the product is independent of how the matrix core orders k inside one
+//  instruction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sk_params.hpp"
+#include "sk_sched.hpp"
+
+namespace sk {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3 };
+enum { L_ROW = 0, L_COL = 1 };
+enum { R_FULL = 0, R_FINISH = 1, R_PARTIAL = 2, R_DP = 3 };
+constexpr int NT = 256;        // threads per workgroup (4 waves)
+
+// Values that are the same in every lane, moved to scalar registers (the
+// compiler cannot always prove it, and a buffer descriptor in vector
+// registers forces a loop over lanes around every load).
+__device__ __forceinline__ int32_t uniform32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ const char* uniform_ptr(const char* p) {
+  return (const char*)uniform64((int64_t)p);
+}
+
+__device__ __forceinline__ int swz(int r) { return (r & 7) ^ ((r >> 3) & 3); }
+
+__device__ __forceinline__ int lds_off(int row, int chunk) {
+  return row * 128 + ((chunk ^ swz(row)) << 4);
+}
+
+// ---------------------------------------------------------------------------
+// Operand staging, global memory -> LDS.
+//
+// Every operand tile is a block of R rows (m for A, n for B) by 128 bytes of
+// K.  Two paths fill it:
+//  * fast: 16-byte buffer loads (buffer_load_dwordx4).  A chunk that lies
+//    outside the matrix (rows past M or N, whole chunks past K) gets an
+//    offset beyond the buffer's size, for which the hardware returns zeros,
+//    so edges cost no branches.  Needs 16-byte-aligned rows and no chunk that
+//    straddles the end of a row (K or M/N not a multiple of the chunk).
+//  * slow: element-by-element copy with explicit bounds checks, any
+//    alignment; used only for the iterations/tiles where the fast path's
+//    conditions fail.
+// Offsets in a buffer are 32-bit; the host checks that a tile's furthest
+// element is below 2^31 bytes from its base.
+
+constexpr uint32_t kOOB = 0x80000000u;     // offset past any buffer size used
+constexpr int kRsrcWord3 = 0x00020000;     // buffer descriptor dword 3 (32-bit data format)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const char* base, int64_t bytes) {
+  const int32_t n = bytes <= 0 ? 0 : bytes >= (int64_t)kOOB ? (int32_t)kOOB : (int32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc((void*)uniform_ptr(base), (short)0, uniform32(n),
+                                           kRsrcWord3);
+}
+
+// Operand geometry for one tile.
+struct OpTile {
+  const char* X;       // matrix base
+  int64_t ld_b;        // leading dimension in bytes
+  int64_t row0;        // first tile row (m or n)
+  int64_t rows;        // M or N
+  int64_t K;
+  bool aligned;        // base and ld_b are multiples of 16 bytes
+};
+
+template <int EB>
+__device__ __forceinline__ void copy_elem_to_lds(char* L, int r, int kk, const char* src, bool ok) {
+  const int byte = kk * EB;
+  char* dst = L + lds_off(r, byte >> 4) + (byte & 15);
+  if constexpr (EB == 4) *(uint32_t*)dst = ok ? *(const uint32_t*)src : 0u;
+  else if constexpr (EB == 2) *(uint16_t*)dst = ok ? *(const uint16_t*)src : (uint16_t)0;
+  else *(uint8_t*)dst = ok ? *(const uint8_t*)src : (uint8_t)0;
+}
+
+// K-contiguous operand ("row-major A" / "column-major B"): element (r, k) at
+// X[(row0 + r) * ld + k]; tile row r is 8 chunks of 16 bytes.  The fast
+// path copies global memory straight into LDS (buffer_load_dwordx4 ... lds):
+// one wave instruction fills 1 KiB of LDS, i.e. 8 consecutive tile rows, and
+// lane i writes the 16 bytes at position i%8 of row i/8, so it fetches the
+// logical chunk that the swizzle puts there.  No registers hold the stage.
+template <int R, int EB>
+struct KMajorStage {
+  static constexpr int EPC = 16 / EB;        // elements per chunk
+  static constexpr int KE = 128 / EB;        // K elements per iteration
+  static constexpr int NI = R / 32;          // 1 KiB copies per wave (4 waves)
+  static_assert(R % 32 == 0, "tile rows");
+
+  __device__ __forceinline__ static bool slow(const OpTile& o, int64_t k0) {
+    return !o.aligned || ((o.K % EPC) != 0 && k0 + KE > o.K);
+  }
+
+  __device__ __forceinline__ void issue(char* L, const OpTile& o, int64_t k0, int tid) {
+    const char* base = o.X + o.row0 * o.ld_b;
+    const int64_t rows_left = o.rows - o.row0;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, (rows_left - 1) * o.ld_b + o.K * EB);
+    const int wave = uniform32(tid >> 6), lane = tid & 63;
+    const uint32_t ld32 = (uint32_t)o.ld_b;
+    const uint32_t kb32 = (uint32_t)(k0 * EB);
+    const int32_t rl = (int32_t)imin(rows_left, R);
+    const int32_t kleft = (int32_t)imin(o.K - k0, KE);   // K elements left in this slab
+    const int lr = lane >> 3;                             // row inside the 8-row copy
+    // Instruction j covers rows rbase..rbase+7, rbase = 8*(wave*NI + j); the
+    // swizzle of row rbase + lr is lr ^ ((wave*NI + j) & 3).
+    const uint32_t lane_row = (uint32_t)lr * ld32;
+    if (rl == R && kleft == KE) {
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        const int jj = wave * NI + j;
+        const int c = (lane & 7) ^ lr ^ (jj & 3);
+        const uint32_t off = lane_row + (uint32_t)(c * 16) + ((uint32_t)(jj * 8) * ld32 + kb32);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void*)(L + jj * 1024), 16, (int)off, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        const int jj = wave * NI + j;
+        const int c = (lane & 7) ^ lr ^ (jj & 3);
+        const bool ok = jj * 8 + lr < rl && c * EPC < kleft;
+        const uint32_t off = ok ? lane_row + (uint32_t)(c * 16) + ((uint32_t)(jj * 8) * ld32 + kb32)
+                                : kOOB;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void*)(L + jj * 1024), 16, (int)off, 0, 0, 0);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void commit(char*, int) const {}
+
+  __device__ static void copy_slow(char* L, const OpTile& o, int64_t k0, int tid) {
+    for (int idx = tid; idx < R * KE; idx += NT) {
+      const int r = idx / KE, kk = idx % KE;
+      const int64_t grow = o.row0 + r, k = k0 + kk;
+      const bool ok = grow < o.rows && k < o.K;
+      copy_elem_to_lds<EB>(L, r, kk, o.X + (ok ? grow * o.ld_b + k * EB : 0), ok);
+    }
+  }
+};
+
+// Register transpose of a block: in[j] holds 16/EB consecutive elements
+// (along M or N) of k-row j; out[i] holds the 16/EB k-values of element i.
+template <int EB>
+__device__ __forceinline__ void transpose_block(const u32x4 (&in)[16 / EB],
+                                                u32x4 (&out)[16 / EB]) {
+  constexpr int E = 16 / EB;
+  union U {
+    u32x4 v;
+    uint8_t b[16];
+    uint16_t h[8];
+    uint32_t w[4];
+  };
+  U a[E], o[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) a[j].v = in[j];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      if constexpr (EB == 4) o[i].w[j] = a[j].w[i];
+      else if constexpr (EB == 2) o[i].h[j] = a[j].h[i];
+      else o[i].b[j] = a[j].b[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < E; ++i) out[i] = o[i].v;
+}
+
+// M/N-contiguous operand ("column-major A" / "row-major B"): element (r, k)
+// at X[k * ld + row0 + r].  A thread loads a block of EPC k-rows x EPC tile
+// rows (one 16-byte chunk per k-row), transposes it in registers and writes
+// EPC K-contiguous chunks to LDS.
+template <int R, int EB>
+struct MNMajorStage {
+  static constexpr int EPC = 16 / EB;
+  static constexpr int KE = 128 / EB;
+  static constexpr int RB = R / EPC;          // row blocks
+  static constexpr int NBLK = RB * 8;         // x 8 chunk columns of K
+  static constexpr int BPT = (NBLK + NT - 1) / NT;
+  static_assert(R % EPC == 0, "tile rows");
+  u32x4 v[BPT][EPC];
+
+  __device__ __forceinline__ static bool slow(const OpTile& o, int64_t) {
+    return !o.aligned || ((o.rows % EPC) != 0 && o.row0 + R > o.rows);
+  }
+
+  __device__ __forceinline__ void issue(char*, const OpTile& o, int64_t k0, int tid) {
+    const char* base = o.X + o.row0 * EB;
+    const int64_t rows_left = o.rows - o.row0;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, (o.K - 1) * o.ld_b + rows_left * EB);
+    const uint32_t ld32 = (uint32_t)o.ld_b;
+    const int32_t rl = (int32_t)imin(rows_left, R);
+    const int32_t kleft = (int32_t)imin(o.K - k0, KE);
+    const uint32_t kb32 = (uint32_t)k0 * ld32;
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      const int bidx = tid + NT * b;
+      if (NBLK % NT != 0 && bidx >= NBLK) continue;
+      const int rb = bidx % RB;
+      const int kc = bidx / RB;
+      const bool rok = rb * EPC < rl;
+#pragma unroll
+      for (int j = 0; j < EPC; ++j) {
+        const int kk = kc * EPC + j;
+        const bool ok = rok && kk < kleft;
+        const uint32_t off = ok ? kb32 + (uint32_t)kk * ld32 + (uint32_t)(rb * 16) : kOOB;
+        v[b][j] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void commit(char* L, int tid) const {
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      const int bidx = tid + NT * b;
+      if (NBLK % NT != 0 && bidx >= NBLK) continue;
+      const int rb = bidx % RB;
+      const int kc = bidx / RB;
+      u32x4 w[EPC];
+      transpose_block<EB>(v[b], w);
+#pragma unroll
+      for (int i = 0; i < EPC; ++i) *(u32x4*)(L + lds_off(rb * EPC + i, kc)) = w[i];
+    }
+  }
+
+  __device__ static void copy_slow(char* L, const OpTile& o, int64_t k0, int tid) {
+    for (int idx = tid; idx < R * KE; idx += NT) {
+      const int kk = idx / R, r = idx % R;
+      const int64_t grow = o.row0 + r, k = k0 + kk;
+      const bool ok = grow < o.rows && k < o.K;
+      copy_elem_to_lds<EB>(L, r, kk, o.X + (ok ? k * o.ld_b + grow * EB : 0), ok);
+    }
+  }
+};
+
+template <bool KMAJOR, int R, int EB>
+struct StageSel;
+template <int R, int EB>
+struct StageSel<true, R, EB> { using type = KMajorStage<R, EB>; };
+template <int R, int EB>
+struct StageSel<false, R, EB> { using type = MNMajorStage<R, EB>; };
+
+// ---------------------------------------------------------------------------
+// Matrix-core step: one 32-byte (f32/f16/bf16) or 64-byte (e4m3) slice of K
+// for one 32x32 output block.  Lane l reads tile row (l mod 32); lanes
+// 0-31 and 32-63 read adjacent 16-byte (32-byte for e4m3) pieces of K.
+template <int DT>
+struct Frag { u32x4 c[DT == DT_F8 ? 2 : 1]; };
+
+// Per-lane LDS byte offset, inside a 32-row block, of the 16-byte piece
+// `chunk` of the lane's row (lane mod 32).  The swizzle repeats every 32
+// rows, so the same offset serves every 32-row block.
+__device__ __forceinline__ int frag_lane_off(int l32, int chunk) {
+  return l32 * 128 + ((chunk ^ swz(l32)) << 4);
+}
+
+template <int DT>
+__device__ __forceinline__ Frag<DT> read_frag(const char* L, const int (&lo)[2]) {
+  Frag<DT> f;
+  f.c[0] = *(const u32x4*)(L + lo[0]);
+  if constexpr (DT == DT_F8) f.c[1] = *(const u32x4*)(L + lo[1]);
+  return f;
+}
+
+template <int DT>
+__device__ __forceinline__ void mma(v16f& acc, const Frag<DT>& a, const Frag<DT>& b) {
+  if constexpr (DT == DT_F32) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a.c[0][e]),
+                                                 __builtin_bit_cast(float, b.c[0][e]), acc,
+                                                 0, 0, 0);
+  } else if constexpr (DT == DT_F16) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a.c[0]),
+                                                 __builtin_bit_cast(v8h, b.c[0]), acc, 0, 0, 0);
+  } else if constexpr (DT == DT_BF16) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a.c[0]),
+                                                  __builtin_bit_cast(v8bf, b.c[0]), acc, 0, 0,
+                                                  0);
+  } else {
+    v8i av = __builtin_bit_cast(v8i, a);
+    v8i bv = __builtin_bit_cast(v8i, b);
+    // operand format 0 (e4m3) for A and B; E8M0 scale 127 = 2^0
+    acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, 127, 0, 127);
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <int DT_, int LA_, int LB_, int BM_, int BN_, int WGM_>
+struct Cfg {
+  static constexpr int DT = DT_, LA = LA_, LB = LB_, BM = BM_, BN = BN_, WGM = WGM_;
+  static constexpr int EB = DT == DT_F32 ? 4 : DT == DT_F8 ? 1 : 2;
+  static constexpr int KE = 128 / EB;                // K elements per iteration
+  static constexpr int WGN = 4 / WGM;
+  static constexpr int WM = BM / WGM, WN = BN / WGN; // per-wave tile
+  static constexpr int FM = WM / 32, FN = WN / 32;   // 32x32 blocks per wave
+  static constexpr int STEPS = DT == DT_F8 ? 2 : 4;  // matrix-core steps per iteration
+  static constexpr int BOFF = BM * 128;              // B tile offset in a stage
+  static constexpr int STAGE = (BM + BN) * 128;      // LDS bytes per stage
+  static_assert(WGM * WGN == 4 && FM >= 1 && FN >= 1, "wave grid");
+  static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile");
+  using StageA = typename StageSel<LA == L_ROW, BM, EB>::type;
+  using StageB = typename StageSel<LB == L_COL, BN, EB>::type;
+};
+
+template <typename C>
+struct Acc { v16f a[C::FM][C::FN]; };
+
+template <typename C>
+__device__ __forceinline__ void zero_acc(Acc<C>& acc) {
+#pragma unroll
+  for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc.a[i][j][r] = 0.f;
+}
+
+// LDS stage -> matrix cores: acc += A_slab * B_slab for one iteration.
+// Lanes 0-31 and 32-63 read adjacent 16-byte (e4m3: 32-byte) pieces of K of
+// rows lane mod 32; step s covers pieces 2s, 2s+1 (e4m3: 4s .. 4s+3).
+template <typename C>
+__device__ __forceinline__ void compute_stage(Acc<C>& acc, const char* stage, int tid) {
+  const int wave = uniform32(tid >> 6);
+  const int lane = tid & 63;
+  const int half = lane >> 5;
+  const int l32 = lane & 31;
+  const char* LA_ = stage + ((wave / C::WGN) * C::WM) * 128;
+  const char* LB_ = stage + C::BOFF + ((wave % C::WGN) * C::WN) * 128;
+#pragma unroll
+  for (int s = 0; s < C::STEPS; ++s) {
+    int lo[2];
+    if constexpr (C::DT == DT_F8) {
+      lo[0] = frag_lane_off(l32, 4 * s + 2 * half);
+      lo[1] = frag_lane_off(l32, 4 * s + 2 * half + 1);
+    } else {
+      lo[0] = frag_lane_off(l32, 2 * s + half);
+      lo[1] = 0;
+    }
+    Frag<C::DT> fa[C::FM], fb[C::FN];
+#pragma unroll
+    for (int i = 0; i < C::FM; ++i) fa[i] = read_frag<C::DT>(LA_ + i * 32 * 128, lo);
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j) fb[j] = read_frag<C::DT>(LB_ + j * 32 * 128, lo);
+#pragma unroll
+    for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < C::FN; ++j) mma<C::DT>(acc.a[i][j], fa[i], fb[j]);
+  }
+}
+
+// Fast MAC loop over iterations [kb, ke), all of which satisfy the fast
+// staging conditions.  Double-buffered: the global loads of iteration k+1
+// are in flight while the matrix cores work on iteration k out of the other
+// LDS stage.  Starts and ends with a workgroup barrier.
+template <typename C>
+__device__ __forceinline__ void mac_loop_fast(Acc<C>& acc, const OpTile& oa, const OpTile& ob,
+                                              int kb, int ke, char* lds, int tid,
+                                              int32_t* cover_row) {
+  typename C::StageA sa;
+  typename C::StageB sb;
+  sa.issue(lds, oa, (int64_t)kb * C::KE, tid);
+  sb.issue(lds + C::BOFF, ob, (int64_t)kb * C::KE, tid);
+  sa.commit(lds, tid);
+  sb.commit(lds + C::BOFF, tid);
+  __syncthreads();
+  for (int k = kb; k < ke; ++k) {
+    const int cur = (k - kb) & 1;
+    const bool more = k + 1 < ke;
+    char* nxt = lds + (cur ^ 1) * C::STAGE;
+    if (more) {
+      sa.issue(nxt, oa, (int64_t)(k + 1) * C::KE, tid);
+      sb.issue(nxt + C::BOFF, ob, (int64_t)(k + 1) * C::KE, tid);
+    }
+    if (cover_row != nullptr && tid == 0) atomicAdd(cover_row + k, 1);
+    compute_stage<C>(acc, lds + cur * C::STAGE, tid);
+    if (more) {
+      sa.commit(nxt, tid);
+      sb.commit(nxt + C::BOFF, tid);
+    }
+    __syncthreads();   // waits for this iteration's copies into nxt
+  }
+}
+
+// One iteration through the element-wise path (edges the fast path cannot
+// take).  Called after a barrier; ends with one.
+template <typename C>
+__device__ __forceinline__ void stage_slow(const OpTile& oa, const OpTile& ob,
+                                                     int64_t k0, char* lds, int tid) {
+  if (C::StageA::slow(oa, k0)) C::StageA::copy_slow(lds, oa, k0, tid);
+  else {
+    typename C::StageA sa;
+    sa.issue(lds, oa, k0, tid);
+    sa.commit(lds, tid);
+  }
+  if (C::StageB::slow(ob, k0)) C::StageB::copy_slow(lds + C::BOFF, ob, k0, tid);
+  else {
+    typename C::StageB sb;
+    sb.issue(lds + C::BOFF, ob, k0, tid);
+    sb.commit(lds + C::BOFF, tid);
+  }
+}
+
+// MAC loop over iterations [kb, ke) of the tile whose first output element
+// is (m0, n0): acc += A[m0:, k-slab] * B[k-slab, n0:] for each iteration.
+template <typename C>
+__device__ __forceinline__ void mac_loop(Acc<C>& acc, const ProbDesc& pd, int64_t m0,
+                                         int64_t n0, int kb, int ke, char* lds, int tid,
+                                         int32_t* cover_row) {
+  constexpr int EB = C::EB;
+  const OpTile oa{(const char*)pd.A, pd.lda * EB, m0, pd.M, pd.K, pd.aligned != 0};
+  const OpTile ob{(const char*)pd.B, pd.ldb * EB, n0, pd.N, pd.K, pd.aligned != 0};
+  // Fast iterations are a prefix [kb, kf): an unaligned problem or a tile
+  // with a partial row chunk has none; a K that ends inside a chunk makes
+  // only the last iteration slow.
+  int kf = ke;
+  if (C::StageA::slow(oa, (int64_t)kb * C::KE) || C::StageB::slow(ob, (int64_t)kb * C::KE))
+    kf = kb;
+  else if (ke > kb && (C::StageA::slow(oa, (int64_t)(ke - 1) * C::KE) ||
+                       C::StageB::slow(ob, (int64_t)(ke - 1) * C::KE)))
+    kf = ke - 1;
+  if (kf > kb) mac_loop_fast<C>(acc, oa, ob, kb, kf, lds, tid, cover_row);
+  for (int k = kf; k < ke; ++k) {
+    stage_slow<C>(oa, ob, (int64_t)k * C::KE, lds, tid);
+    __syncthreads();
+    if (cover_row != nullptr && tid == 0) atomicAdd(cover_row + k, 1);
+    compute_stage<C>(acc, lds, tid);
+    __syncthreads();
+  }
+}
+
+// Accumulator layout of a 32x32 block: register r of lane l holds
+// row 8*(r/4) + 4*(l/32) + (r%4), column l%32.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <typename C, int DTC>
+__device__ __forceinline__ void epilogue_t(const Acc<C>& acc, const ProbDesc& pd, int64_t m0,
+                                           int64_t n0, int tid) {
+  constexpr int ES = DTC == DT_F32 ? 4 : 2;           // output element size
+  const int wave = uniform32(tid >> 6);
+  int lane = tid & 63;
+  // Keep the per-lane offsets below inside the epilogue (otherwise they are
+  // hoisted out of the work loop and occupy registers during the MAC loop).
+  asm volatile("" : "+v"(lane));
+  const int wr = (wave / C::WGN) * C::WM + 4 * (lane >> 5);
+  const int wc = (wave % C::WGN) * C::WN + (lane & 31);
+  const float alpha = pd.alpha_s, beta = pd.beta;
+  const int64_t rows_left = pd.M - m0, cols_left = pd.N - n0;
+  const int32_t rl = (int32_t)imin(rows_left, C::BM), cl = (int32_t)imin(cols_left, C::BN);
+  const int64_t tile_off = (m0 * pd.ldc + n0) * ES;
+  const int64_t extent = ((rows_left - 1) * pd.ldc + cols_left) * ES;
+  const __amdgpu_buffer_rsrc_t out = make_rsrc((const char*)pd.Cout + tile_off, extent);
+  const bool use_cin = beta != 0.f;
+  const __amdgpu_buffer_rsrc_t in =
+      make_rsrc((const char*)(use_cin ? pd.Cin : pd.Cout) + tile_off, extent);
+  const uint32_t ldc_b = (uint32_t)(pd.ldc * ES);
+  const uint32_t lane_off = (uint32_t)wr * ldc_b + (uint32_t)(wc * ES);
+#pragma unroll
+  for (int i = 0; i < C::FM; ++i) {
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int dr = i * 32 + 8 * (r >> 2) + (r & 3);   // row offset from wr
+        const bool ok = wr + dr < rl && wc + j * 32 < cl;
+        const int off =
+            (int)(ok ? lane_off + ((uint32_t)dr * ldc_b + (uint32_t)(j * 32 * ES)) : kOOB);
+        float v = alpha * acc.a[i][j][r];
+        if (use_cin) {
+          float cin;
+          if constexpr (DTC == DT_F32)
+            cin = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(in, off, 0, 0));
+          else if constexpr (DTC == DT_F16)
+            cin = (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(in, off, 0, 0));
+          else
+            cin = __builtin_bit_cast(float, (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(in, off, 0, 0) << 16);
+          v = __builtin_fmaf(alpha, acc.a[i][j][r], beta * cin);
+        }
+        if constexpr (DTC == DT_F32)
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), out, off, 0, 0);
+        else if constexpr (DTC == DT_F16)
+          __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (_Float16)v), out, off, 0, 0);
+        else
+          __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16_rne(v), out, off, 0, 0);
+      }
+      // one 32x32 block at a time: keeps the scheduler from gathering all
+      // loads/stores of the tile and the registers they would need
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// Epilogue: out = alpha_s * acc + beta * Cin (one FP32 fma when beta != 0),
+// rounded to nearest-even in the output type; out-of-range elements get an
+// offset past the buffer and are dropped by the hardware.
+template <typename C>
+__device__ __forceinline__ void epilogue(const Acc<C>& acc, const ProbDesc& pd, int dtype_c,
+                                         int64_t m0, int64_t n0, int tid) {
+  if (dtype_c == DT_F32) epilogue_t<C, DT_F32>(acc, pd, m0, n0, tid);
+  else if (dtype_c == DT_F16) epilogue_t<C, DT_F16>(acc, pd, m0, n0, tid);
+  else epilogue_t<C, DT_BF16>(acc, pd, m0, n0, tid);
+}
+
+// Partial tile <-> workspace slot.  Thread t owns the same accumulator
+// registers in every workgroup, so the slot is laid out
+// [block (i,j)][register quad][thread] x float4: each store or load
+// instruction of a wave touches 1 KiB of contiguous memory.
+template <typename C>
+__device__ __forceinline__ void store_partial(const Acc<C>& acc, float* slot, int tid) {
+  asm volatile("" : "+v"(tid));   // addresses are formed here, not hoisted
+#pragma unroll
+  for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        v4f v = {acc.a[i][j][4 * q], acc.a[i][j][4 * q + 1], acc.a[i][j][4 * q + 2],
+                 acc.a[i][j][4 * q + 3]};
+        ((v4f*)((char*)slot + ((i * C::FN + j) * 4 + q) * NT * 16))[tid] = v;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+}
+
+template <typename C>
+__device__ __forceinline__ void add_partial(Acc<C>& acc, const float* slot, int tid) {
+  asm volatile("" : "+v"(tid));   // addresses are formed here, not hoisted
+#pragma unroll
+  for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        v4f v = ((const v4f*)((const char*)slot + ((i * C::FN + j) * 4 + q) * NT * 16))[tid];
+        acc.a[i][j][4 * q] += v[0];
+        acc.a[i][j][4 * q + 1] += v[1];
+        acc.a[i][j][4 * q + 2] += v[2];
+        acc.a[i][j][4 * q + 3] += v[3];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Tile lookup.
+struct TileRef {
+  int32_t p;          // problem
+  int64_t t;          // global tile
+  int64_t J;          // first global Stream-K iteration of the tile
+  int32_t tr, tc;     // tile row / column inside the problem
+};
+
+__device__ __forceinline__ int32_t find_problem(const KParams& P, int64_t key, bool by_iter) {
+  // largest p with start[p] <= key
+  int32_t lo = 0, hi = P.nprobs - 1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    int64_t s = by_iter ? P.group[mid].iter_start : P.group[mid].tile_start;
+    if (s <= key) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ const ProbDesc& prob_of(const KParams& P, int32_t p) {
+  return P.group ? P.group[p] : P.prob;
+}
+
+// Global Stream-K iteration -> tile containing it.
+__device__ __forceinline__ TileRef tile_of_iter(const KParams& P, int64_t it) {
+  TileRef r;
+  r.p = P.group ? find_problem(P, it, true) : 0;
+  const ProbDesc& pd = prob_of(P, r.p);
+  int64_t u = (it - pd.iter_start) / pd.I;
+  r.t = pd.tile_start + u;
+  r.J = pd.iter_start + u * pd.I;
+  tile_coords(u, pd.tm, pd.tn, P.group_m, &r.tr, &r.tc);
+  return r;
+}
+
+// Global tile index -> tile.
+__device__ __forceinline__ TileRef tile_of_index(const KParams& P, int64_t t) {
+  TileRef r;
+  r.p = P.group ? find_problem(P, t, false) : 0;
+  const ProbDesc& pd = prob_of(P, r.p);
+  int64_t u = t - pd.tile_start;
+  r.t = t;
+  r.J = 0;
+  tile_coords(u, pd.tm, pd.tn, P.group_m, &r.tr, &r.tc);
+  return r;
+}
+
+__device__ __forceinline__ void trace_segment(const KParams& P, int64_t x, const TileRef& tr,
+                                              int kb, int ke, int role, int npeers) {
+  if (P.trace == nullptr || threadIdx.x != 0) return;
+  int64_t idx = atomicAdd((unsigned long long*)P.trace_count, 1ull);
+  if (idx < P.trace_cap) {
+    sk_segment s;
+    s.wg = (int32_t)x;
+    s.problem = tr.p;
+    s.tile = (int32_t)tr.t;
+    s.tile_m = tr.tr;
+    s.tile_n = tr.tc;
+    s.k_begin = kb;
+    s.k_end = ke;
+    s.role = role;
+    s.npeers = npeers;
+    P.trace[idx] = s;
+  }
+}
+
+// Fixup wait: one wavefront (lane 0 of wave 0) polls the tile's arrival
+// counter with agent-scope loads and backs off with s_sleep; after the
+// counter reaches `target` it performs an agent-scope acquire, and the
+// workgroup barrier orders every other wave's reads of the partial slots
+// after it.  The poll is bounded: past spin_limit it raises the error word
+// instead of hanging.
+__device__ __forceinline__ void wait_arrivals(const KParams& P, int32_t* flag, int32_t target) {
+  if (threadIdx.x == 0) {
+    int64_t n = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++n > P.spin_limit) {
+        __hip_atomic_store(P.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// Publish a partial tile: every thread's stores are released at agent scope
+// before the workgroup barrier; then one thread bumps the arrival counter.
+__device__ __forceinline__ void signal_arrival(int32_t* flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One work item of a workgroup: a Stream-K segment or a data-parallel tile.
+struct Item {
+  TileRef tr;
+  int kb, ke, role, npeers;
+};
+
+template <typename C>
+__global__ __launch_bounds__(NT, 1) void sk_gemm_kernel(KParams P) {
+  __shared__ __attribute__((aligned(16))) char lds[2 * C::STAGE];
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.x;
+
+  // Work of this workgroup: Stream-K iterations [it, e), then data-parallel
+  // tiles dp_t, dp_t + dp_step, ... below T.  The baseline grid runs exactly
+  // one data-parallel tile per workgroup.
+  int64_t x, it, e, dp_t, dp_step;
+  if (P.dp_grid) {
+    x = logical_id(b, P.T, P.xcd_remap, 0);
+    it = e = 0;
+    dp_t = x;
+    dp_step = P.T;
+  } else {
+    x = logical_id(b, P.g, P.xcd_remap, P.reverse_ids);
+    it = range_begin(x, P.q, P.rho);
+    e = it + P.q + (x < P.rho ? 1 : 0);
+    dp_t = P.S + x;
+    dp_step = P.g;
+  }
+
+  while (true) {
+    Item w;
+    ProbDesc pd;
+    if (it < e) {
+      // Stream-K segment: PARTIAL (first only), FULL*, FINISH (last only).
+      w.tr = tile_of_iter(P, it);
+      pd = prob_of(P, w.tr.p);
+      w.kb = (int)(it - w.tr.J);
+      w.ke = (int)(imin(e, w.tr.J + pd.I) - w.tr.J);
+      w.npeers = 0;
+      if (w.kb > 0) w.role = R_PARTIAL;
+      else if (w.ke == pd.I) w.role = R_FULL;
+      else {
+        w.role = R_FINISH;
+        w.npeers = (int)(iter_owner(w.tr.J + pd.I - 1, P.q, P.rho) - x);
+      }
+      it = w.tr.J + w.ke;
+    } else if (dp_t < P.T) {
+      w.tr = tile_of_index(P, dp_t);
+      pd = prob_of(P, w.tr.p);
+      w.kb = 0;
+      w.ke = pd.I;
+      w.role = R_DP;
+      w.npeers = 0;
+      dp_t += dp_step;
+    } else {
+      break;
+    }
+    trace_segment(P, x, w.tr, w.kb, w.ke, w.role, w.npeers);
+
+    const int64_t m0 = (int64_t)w.tr.tr * C::BM, n0 = (int64_t)w.tr.tc * C::BN;
+    Acc<C> acc;
+    zero_acc(acc);
+    int32_t* cover = P.cover ? P.cover + w.tr.t * P.cover_stride : nullptr;
+    mac_loop<C>(acc, pd, m0, n0, w.kb, w.ke, lds, tid, cover);
+
+    if (w.role == R_PARTIAL) {
+      store_partial<C>(acc, P.slots + x * (int64_t)(C::BM * C::BN), tid);
+      if (P.partial_delay > 0) {
+        if (tid == 0)
+          for (int d = 0; d < P.partial_delay; ++d) __builtin_amdgcn_s_sleep(1);
+        __syncthreads();
+      }
+      signal_arrival(P.flags + w.tr.t);
+      continue;
+    }
+    if (w.role == R_FINISH) {
+      wait_arrivals(P, P.flags + w.tr.t, w.npeers);
+      for (int y = 1; y <= w.npeers; ++y)
+        add_partial<C>(acc, P.slots + (x + y) * (int64_t)(C::BM * C::BN), tid);
+      if (tid == 0)
+        __hip_atomic_store(P.flags + w.tr.t, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    epilogue<C>(acc, pd, P.dtype_c, m0, n0, tid);
+  }
+}
+
+}  // namespace sk

@@ -1,0 +1,117 @@
+"""Seeded synthetic inputs shared by the tests and the benchmark.
+
+Holds no GEMM arithmetic: it only draws numbers (numpy PCG64 streams in
+float64), rounds them to the input type with torch's round-to-nearest-even
+conversions, and places matrices in memory with a requested layout and
+leading dimension.  Both the GPU path and the oracle consume what this
+module produces; neither is imported here.
+"""
+import math
+
+import numpy as np
+import torch
+
+E4M3_MAX = 448.0   # largest finite OCP e4m3fn value
+
+TORCH_DTYPES = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16,
+                "e4m3": torch.float8_e4m3fn}
+CODE_VIEW = {"f32": (torch.int32, np.uint32), "f16": (torch.int16, np.uint16),
+             "bf16": (torch.int16, np.uint16), "e4m3": (torch.uint8, np.uint8)}
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def uniform(shape, seed, lo=-1.0, hi=1.0):
+    return rng(seed).uniform(lo, hi, size=shape)
+
+
+def normal(shape, seed):
+    return rng(seed).standard_normal(size=shape)
+
+
+def integers(shape, seed, lo=-4, hi=4):
+    """Uniform over the integers lo..hi inclusive, as float64."""
+    return rng(seed).integers(lo, hi + 1, size=shape).astype(np.float64)
+
+
+def round_to(x64, dtype):
+    """float64 array -> CPU torch tensor of `dtype` ('f32','f16','bf16')."""
+    return torch.from_numpy(np.ascontiguousarray(x64)).to(TORCH_DTYPES[dtype])
+
+
+def fp8_scaled(x64):
+    """Per-tensor amax scaling into the e4m3fn range.
+
+    scale = max|x| / 448 (as a float32), q = RNE_e4m3fn(x / scale); |q| <= 448
+    by construction, so nothing saturates.  Returns (q tensor, scale float)."""
+    amax = float(np.max(np.abs(x64))) if x64.size else 0.0
+    scale = float(np.float32(amax / E4M3_MAX)) if amax > 0 else 1.0
+    q = torch.from_numpy(np.ascontiguousarray(x64 / scale)).to(torch.float8_e4m3fn)
+    return q, scale
+
+
+def codes(t):
+    """Raw bit patterns of a CPU tensor (uint32/uint16/uint8 numpy array)."""
+    dt = {v: k for k, v in TORCH_DTYPES.items()}[t.dtype]
+    tv, nv = CODE_VIEW[dt]
+    return t.contiguous().view(tv).numpy().view(nv)
+
+
+def place(t, col_major=False, ld=None, device=None, fill=0):
+    """Put logical matrix t (rows x cols) in storage with the given layout.
+
+    Row-major: storage (rows, ld), ld >= cols, element (i, j) at i*ld + j.
+    Column-major: storage (cols, ld), ld >= rows, element (i, j) at j*ld + i.
+    Returns (view, storage, ld): `view` has t's shape and the layout's
+    strides; padding elements of the storage hold `fill` (as codes 0 unless
+    given)."""
+    rows, cols = t.shape
+    inner = rows if col_major else cols
+    ld = max(1, inner) if ld is None else ld
+    if ld < inner:
+        raise ValueError("leading dimension smaller than the matrix extent")
+    outer = cols if col_major else rows
+    store = torch.full((outer, ld), fill, dtype=t.dtype) if t.dtype != torch.float8_e4m3fn \
+        else torch.zeros((outer, ld), dtype=torch.uint8).view(torch.float8_e4m3fn)
+    if col_major:
+        store[:, :rows] = t.t()
+    else:
+        store[:, :cols] = t
+    if device is not None:
+        store = store.to(device)
+    view = store[:, :rows].t() if col_major else store[:, :cols]
+    return view, store, ld
+
+
+def ld_aligned(extent, elem_bytes, align=16):
+    """Smallest leading dimension >= extent whose row is a multiple of
+    `align` bytes (storage padding only; the problem keeps its size)."""
+    per = align // math.gcd(align, elem_bytes)
+    return max(per, -(-extent // per) * per)
+
+
+def log_uniform_int(r, lo, hi):
+    return int(round(math.exp(r.uniform(math.log(lo), math.log(hi)))))
+
+
+def sweep_shapes(seed=3, n=64):
+    """64 shapes, M,N log-uniform in [128, 8192], K log-uniform in
+    [128, 16384] (BF16 shape sweep)."""
+    r = rng(seed)
+    return [(log_uniform_int(r, 128, 8192), log_uniform_int(r, 128, 8192),
+             log_uniform_int(r, 128, 16384)) for _ in range(n)]
+
+
+def grouped_shapes(seed=5, n=48):
+    """48 problems, M log-uniform in [16, 4096], N in {1024, 2048, 4096},
+    K in {2048, 4096, 8192} (grouped FP8 set)."""
+    r = rng(seed)
+    out = []
+    for _ in range(n):
+        m = log_uniform_int(r, 16, 4096)
+        nn = int(r.choice([1024, 2048, 4096]))
+        k = int(r.choice([2048, 4096, 8192]))
+        out.append((m, nn, k))
+    return out

@@ -1,0 +1,134 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/streamk.h declares, and its host-only entry points validate
+arguments and report capacity as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+import torch
+
+import paper_2407_00044_amd as sk
+from paper_2407_00044_amd import _abi
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "streamk.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sk_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = sk.load()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _abi.PROTOTYPES, f"{n} has no Python prototype"
+
+
+def test_status_strings():
+    for code in range(-7, 1):
+        assert _abi.status_string(code)
+    assert "unknown" in _abi.status_string(-99)
+
+
+def _plan(M, N, K, dtype=torch.bfloat16, **kw):
+    return sk.plan([(M, N, K)], dtype, sk.Config(**kw))
+
+
+def _status(fn):
+    with pytest.raises(_abi.StreamKError) as e:
+        fn()
+    return e.value.status
+
+
+def test_plan_closed_forms():
+    p = _plan(3840, 4096, 4096, dtype=torch.float16, tile=(256, 128), num_cu=256)
+    assert (p["T"], p["S"], p["W"], p["q"], p["rho"]) == (480, 480, 30720, 120, 0)
+    p = _plan(512, 512, 512, dtype=torch.float32, tile=(128, 128), mode="sk", num_cu=256)
+    assert (p["T"], p["W"], p["q"]) == (16, 256, 1)
+    assert p["workspace_bytes"] == 256 + 256 + 256 * 128 * 128 * 4
+    p = _plan(384, 384, 128, dtype=torch.float32, tile=(128, 128), mode="dp", num_cu=4)
+    assert (p["T"], p["S"], p["g"], p["workspace_bytes"]) == (9, 0, 9, 0)
+    p = _plan(8192, 4096, 11008, tile=(256, 128), num_cu=256)   # T mod g == 0: pure DP
+    assert (p["T"], p["S"]) == (1024, 0)
+
+
+def test_k_zero_keeps_one_iteration():
+    p = _plan(256, 256, 0, tile=(128, 128), mode="sk", num_cu=4)
+    assert p["T"] == 4 and p["W"] == 4 and p["max_iters"] == 1
+
+
+def test_invalid_arguments():
+    lib = sk.load()
+    cfg = sk.Config(tile=(128, 128), num_cu=8).c_struct(_abi.SK_BF16)
+    info = _abi.SkPlanInfo()
+
+    def call(p, c=cfg):
+        return lib.sk_plan(ctypes.byref(p), 1, ctypes.byref(c), ctypes.byref(info))
+
+    good = _abi.SkProblem(64, 64, 64, 0, 1, 64, 64, 64, _abi.SK_BF16, 0, 1, 0, 1, 1)
+    assert call(good) == _abi.SK_OK
+    bad = _abi.SkProblem(*[getattr(good, f) for f, _ in _abi.SkProblem._fields_])
+    bad.M = -1
+    assert call(bad) == _abi.SK_ERR_INVALID_ARG
+    bad.M = 64
+    bad.lda = 63                                  # row-major A needs lda >= K
+    assert call(bad) == _abi.SK_ERR_INVALID_ARG
+    bad.lda = 64
+    bad.ldc = 10
+    assert call(bad) == _abi.SK_ERR_INVALID_ARG
+    bad.ldc = 64
+    bad.dtype_c = _abi.SK_F8E4M3                  # no e4m3 output
+    assert call(bad) == _abi.SK_ERR_UNSUPPORTED
+    bad.dtype_c = 0
+    bad.layout_a = 7
+    assert call(bad) == _abi.SK_ERR_INVALID_ARG
+    c2 = sk.Config(tile=(96, 128), num_cu=8).c_struct(_abi.SK_BF16)
+    assert call(good, c2) == _abi.SK_ERR_UNSUPPORTED          # tile not built
+    c3 = sk.Config(tile=(128, 128), num_cu=8).c_struct(_abi.SK_BF16)
+    c3.block_k = 32
+    assert call(good, c3) == _abi.SK_ERR_UNSUPPORTED          # wrong k per iteration
+    c4 = sk.Config(tile=(128, 128), num_cu=8).c_struct(_abi.SK_BF16)
+    c4.mode = 9
+    assert call(good, c4) == _abi.SK_ERR_INVALID_ARG
+    c5 = sk.Config(tile=(128, 128), num_cu=8, dp_tiles=-5).c_struct(_abi.SK_BF16)
+    assert call(good, c5) == _abi.SK_ERR_INVALID_ARG
+
+
+def test_schedule_capacity():
+    lib = sk.load()
+    p = _abi.SkProblem(384, 384, 128, 0, 0, 128, 384, 384, _abi.SK_F32, 0, 1, 0, 1, 1)
+    c = sk.Config(tile=(128, 128), mode="sk", num_cu=4).c_struct(_abi.SK_F32)
+    n = ctypes.c_int64()
+    assert lib.sk_schedule(ctypes.byref(p), 1, ctypes.byref(c), None, 0, ctypes.byref(n)) == 0
+    assert n.value == 12
+    segs = (_abi.SkSegment * 5)()
+    assert lib.sk_schedule(ctypes.byref(p), 1, ctypes.byref(c), segs, 5,
+                           ctypes.byref(n)) == _abi.SK_ERR_CAPACITY
+
+
+def test_tile_menu():
+    assert sk.supported_tiles(torch.float32) == [(128, 128, 32)]
+    for dt in (torch.float16, torch.bfloat16):
+        assert sk.supported_tiles(dt) == [(128, 128, 64), (256, 128, 64), (256, 256, 64)]
+    assert (64, 128, 128) in sk.supported_tiles(torch.float8_e4m3fn)
+
+
+def test_operand_layout_inference():
+    from paper_2407_00044_amd.api import operand_layout
+    x = torch.zeros(6, 10)
+    assert operand_layout(x) == (0, 10)
+    assert operand_layout(x.t()) == (1, 10)
+    assert operand_layout(torch.zeros(6, 16)[:, :10]) == (0, 16)
+    with pytest.raises(ValueError):
+        operand_layout(torch.zeros(6, 10)[:, ::2])
+
+
+def test_workspace_init_rejects_bad_args():
+    lib = sk.load()
+    assert lib.sk_workspace_init(None, 64, None) == _abi.SK_ERR_INVALID_ARG
+    assert lib.sk_workspace_init(None, 0, None) == _abi.SK_OK

@@ -1,0 +1,87 @@
+"""GPU schedule and fixup checks through sk_gemm_debug.
+
+* the segments the workgroups actually ran equal the oracle's simulator;
+* every MAC iteration of every tile ran exactly once;
+* results are bitwise identical across repeats, with contributors delayed
+  before publishing, and with hardware workgroups mapped to logical ids in
+  reverse (fixup ordering stress).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2407_00044_amd as sk
+from gpu_util import as64, gpu, make_inputs, oracle, rel_err, run
+from oracle import schedule as sch
+
+pytestmark = gpu
+
+MODES = {"sk": sch.MODE_SK, "hybrid": sch.MODE_HYBRID, "dp": sch.MODE_DP}
+BK = {"f32": 32, "f16": 64, "bf16": 64, "e4m3": 128}
+
+CASES = [
+    (512, 512, 512, "f32", (128, 128), "sk", 256),
+    (384, 384, 128, "f32", (128, 128), "sk", 4),
+    (384, 384, 128, "f32", (128, 128), "hybrid", 4),
+    (1000, 700, 900, "bf16", (256, 128), "hybrid", 13),
+    (1000, 700, 900, "bf16", (128, 128), "sk", 256),
+    (480, 512, 512, "f16", (256, 128), "sk", 120),
+    (700, 300, 2000, "e4m3", (64, 128), "hybrid", 64),
+    (640, 640, 300, "bf16", (128, 128), "dp", 0),
+]
+
+
+@pytest.mark.parametrize("M,N,K,dtype,tile,mode,g", CASES)
+def test_device_trace_matches_simulator(M, N, K, dtype, tile, mode, g):
+    print(f"case {M}x{N}x{K} {dtype} {tile} {mode} g={g}", flush=True)
+    A, B = make_inputs(M, N, K, dtype, False, True, seed=3)
+    cfg = sk.Config(tile=tile, mode=mode, num_cu=g)
+    out, segs, cover = sk.gemm_debug(A.view, B.view, config=cfg, scale_a=A.scale,
+                                     scale_b=B.scale)
+    _, sim = sch.simulate([(M, N, K)], tile[0], tile[1], BK[dtype], g, MODES[mode])
+    assert segs == [s.as_tuple() for s in sim]
+    plan = sk.plan([(M, N, K)], out.dtype if dtype == "f32" else A.view.dtype, cfg)
+    T, I = plan["T"], plan["max_iters"]
+    assert torch.equal(cover[:T, :I], torch.ones((T, I), dtype=torch.int32))
+    assert rel_err(as64(out), oracle(A, B, M, N, K)) <= (1e-5 if dtype == "f32" else 1e-4)
+
+
+def test_repeats_delays_and_reversed_ids_are_bitwise_identical():
+    M, N, K = 512, 512, 512
+    A, B = make_inputs(M, N, K, "f32", False, False, seed=1)
+    cfg = sk.Config(tile=(128, 128), mode="sk", num_cu=256)
+    first = run(A, B, cfg)
+    for _ in range(20):
+        assert torch.equal(run(A, B, cfg), first)
+    for delay, rev in [(2000, 0), (0, 1), (2000, 1)]:
+        out, segs, cover = sk.gemm_debug(A.view, B.view, config=cfg, partial_delay=delay,
+                                         reverse_ids=rev)
+        assert torch.equal(out, first)
+
+
+def test_bf16_many_contributors_bitwise_repeatable():
+    # K long relative to the tile count: every tile split across many WGs
+    M, N, K = 256, 512, 16384
+    A, B = make_inputs(M, N, K, "bf16", False, True, seed=8)
+    cfg = sk.Config(tile=(256, 128), mode="sk", num_cu=256)
+    first = run(A, B, cfg)
+    assert rel_err(as64(first), oracle(A, B, M, N, K)) <= 1e-4
+    for _ in range(10):
+        assert torch.equal(run(A, B, cfg), first)
+    out, _, _ = sk.gemm_debug(A.view, B.view, config=cfg, partial_delay=3000, reverse_ids=1)
+    assert torch.equal(out, first)
+
+
+def test_spin_limit_reports_timeout_without_hanging():
+    # Force the bounded fixup wait to give up: a limit of one poll, with
+    # contributors that sleep before publishing.  Every wave still exits;
+    # the device error word is raised and reported as a timeout.
+    from paper_2407_00044_amd import _abi
+    M, N, K = 512, 512, 512
+    A, B = make_inputs(M, N, K, "f32", False, False, seed=1)
+    cfg = sk.Config(tile=(128, 128), mode="sk", num_cu=256, spin_limit=1)
+    with pytest.raises(_abi.StreamKError) as e:
+        sk.gemm_debug(A.view, B.view, config=cfg, partial_delay=20000)
+    assert e.value.status == _abi.SK_ERR_DEVICE_TIMEOUT
+    good = run(A, B, sk.Config(tile=(128, 128), mode="sk", num_cu=256))
+    assert rel_err(as64(good), oracle(A, B, M, N, K)) <= 1e-5

@@ -1,0 +1,65 @@
+"""The library's host schedule (C++, sk_schedule) equals the oracle's
+simulator bit for bit (CPU only)."""
+import random
+
+import pytest
+import torch
+
+import paper_2407_00044_amd as sk
+from oracle import schedule as sch
+from paper_2407_00044_amd import synth
+
+MODES = {"sk": sch.MODE_SK, "hybrid": sch.MODE_HYBRID, "dp": sch.MODE_DP}
+BK = {torch.float32: 32, torch.float16: 64, torch.bfloat16: 64, torch.float8_e4m3fn: 128}
+
+
+def compare(shapes, dtype, tile, g, mode, dp_tiles=-1, group_m=0):
+    cfg = sk.Config(tile=tile, mode=mode, num_cu=g, dp_tiles=dp_tiles, group_m=group_m)
+    lib_segs = sk.schedule(shapes, dtype, cfg)
+    _, sim = sch.simulate(shapes, tile[0], tile[1], BK[dtype], g, MODES[mode], dp_tiles,
+                          group_m)
+    assert lib_segs == [s.as_tuple() for s in sim]
+
+
+@pytest.mark.parametrize("mode", ["sk", "hybrid", "dp"])
+def test_random_small_shapes(mode):
+    r = random.Random(7)
+    sizes = [1, 5, 31, 32, 33, 64, 127, 128, 129, 200, 255, 256, 257, 300]
+    tiles = {torch.float32: [(128, 128)], torch.bfloat16: [(128, 128), (256, 128), (256, 256)],
+             torch.float8_e4m3fn: [(64, 128), (128, 128)]}
+    for _ in range(150):
+        dt = r.choice(list(tiles))
+        shape = (r.choice(sizes), r.choice(sizes), r.choice(sizes + [0, 1000]))
+        g = r.choice([1, 2, 3, 7, 8, 16, 64, 120, 255, 256])
+        dp = r.choice([-1, -1, 0, 3]) if mode != "dp" else -1
+        gm = r.choice([0, 0, 2, 5])
+        compare([shape], dt, r.choice(tiles[dt]), g, mode, dp, gm)
+
+
+def test_paper_configurations():
+    compare([(512, 512, 512)], torch.float32, (128, 128), 256, "sk")
+    compare([(3840, 4096, 4096)], torch.float16, (256, 128), 256, "hybrid")
+    compare([(3840, 4096, 4096)], torch.bfloat16, (256, 256), 256, "hybrid")
+    compare([(3840, 4096, 4096)], torch.float16, (256, 128), 256, "dp")
+    compare([(480, 512, 512)], torch.float16, (256, 128), 120, "sk")
+    compare([(1920, 2000, 2000)], torch.float16, (256, 128), 120, "hybrid")
+    for M, N, K in [(8192, 11008, 4096), (8192, 4096, 11008), (11008, 4096, 8192)]:
+        compare([(M, N, K)], torch.bfloat16, (256, 128), 256, "hybrid")
+
+
+def test_sweep_shapes():
+    for M, N, K in synth.sweep_shapes()[:24]:
+        compare([(M, N, K)], torch.bfloat16, (256, 128), 256, "hybrid")
+
+
+def test_grouped_sets():
+    shapes = synth.grouped_shapes()
+    for tile in [(128, 128), (64, 128), (256, 128)]:
+        for mode in ["sk", "hybrid", "dp"]:
+            compare(shapes, torch.float8_e4m3fn, tile, 256, mode)
+    r = random.Random(3)
+    for _ in range(40):
+        shapes = [(r.choice([0, 16, 100, 300]), r.choice([0, 64, 129, 500]),
+                   r.choice([0, 64, 1000])) for _ in range(r.randint(1, 7))]
+        compare(shapes, torch.bfloat16, (128, 128), r.choice([4, 64, 256]),
+                r.choice(["sk", "hybrid", "dp"]))
