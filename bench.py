@@ -70,8 +70,8 @@ def cpu_baseline(host, M, N, K, rows=24):
     from oracle import gemm as og
     from paper_2407_00044_amd import synth
     sa, lda, sb, ldb = host
-    a = og.decode_f16(synth.codes(sa))
-    b = og.decode_f16(synth.codes(sb))
+    a = og.decode_f16(synth.codes(sa.cpu()))
+    b = og.decode_f16(synth.codes(sb.cpu()))
     sel = np.arange(rows, dtype=np.int64) * (M // rows)
     og.gemm(M, N, K, a, lda, False, b, ldb, True, rows=sel[:2])   # warm
     t0 = time.perf_counter()

@@ -10,6 +10,7 @@ is its Python binding.  Importing it does not load the library; the first
 call does, and fails loudly if the library has not been built.
 """
 from ._abi import LIB_PATH, StreamKError, load  # noqa: F401
+from . import tune  # noqa: F401
 from .api import (Config, GroupedGemm, StreamKLinearFn, Workspace,  # noqa: F401
                   check_device_error, default_tile, device_query, gemm, gemm_debug,
                   linear, plan, schedule, supported_tiles)

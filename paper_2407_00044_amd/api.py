@@ -63,11 +63,16 @@ def default_tile(M, N, K, dtype):
     return (128, 128)
 
 
-def operand_layout(t):
-    """(layout, ld) of a 2-D tensor with unit stride in one dimension."""
+def operand_layout(t, prefer=None):
+    """(layout, ld) of a 2-D tensor with unit stride in one dimension.
+
+    An empty matrix has no layout of its own: with `prefer` given it takes
+    that layout (with the smallest valid leading dimension)."""
     if t.dim() != 2:
         raise ValueError("operands must be 2-D")
     r, c = t.shape
+    if t.numel() == 0 and prefer is not None:
+        return prefer, max(1, c if prefer == SK_ROW_MAJOR else r)
     s0, s1 = t.stride()
     if (s1 == 1 or c <= 1) and s0 >= max(1, c):
         return SK_ROW_MAJOR, max(s0, 1)
@@ -76,7 +81,7 @@ def operand_layout(t):
     raise ValueError(f"operand with strides {t.stride()} is neither row- nor column-major")
 
 
-def _problem(A, B, C, alpha, beta, scale_a, scale_b):
+def _problem(A, B, C, alpha, beta, scale_a, scale_b, prefer=(None, None)):
     M, K = A.shape
     K2, N = B.shape
     if K != K2 or tuple(C.shape) != (M, N):
@@ -86,8 +91,8 @@ def _problem(A, B, C, alpha, beta, scale_a, scale_b):
         raise TypeError(f"A and B must share one of {list(DTYPE_CODES)}")
     if C.dtype not in OUT_CODES:
         raise TypeError(f"C must be one of {list(OUT_CODES)}")
-    la, lda = operand_layout(A)
-    lb, ldb = operand_layout(B)
+    la, lda = operand_layout(A, prefer[0])
+    lb, ldb = operand_layout(B, prefer[1])
     if C.stride(1) != 1 and N > 1:
         raise ValueError("C must be row-major")
     ldc = max(C.stride(0), N, 1)
@@ -305,12 +310,17 @@ class GroupedGemm:
         self.problems = problems
         probs = (SkProblem * n)()
         ptrs = {k: (ctypes.c_void_p * n)() for k in ("A", "B", "Cin", "Cout")}
+        # the group's operand layouts, taken from its first non-empty operands
+        nonempty_a = [p[0] for p in problems if p[0].numel() > 0]
+        nonempty_b = [p[1] for p in problems if p[1].numel() > 0]
+        prefer = (operand_layout(nonempty_a[0])[0] if nonempty_a else SK_ROW_MAJOR,
+                  operand_layout(nonempty_b[0])[0] if nonempty_b else SK_COL_MAJOR)
         for i, pr in enumerate(problems):
             A, B, out = pr[:3]
             Cin = pr[3] if len(pr) > 3 else None
             beta = pr[4] if len(pr) > 4 else 0.0
             sa, sb = scales[i] if scales is not None else (1.0, 1.0)
-            probs[i] = _problem(A, B, out, alpha, beta, sa, sb)
+            probs[i] = _problem(A, B, out, alpha, beta, sa, sb, prefer)
             ptrs["A"][i] = A.data_ptr()
             ptrs["B"][i] = B.data_ptr()
             ptrs["Cin"][i] = Cin.data_ptr() if (Cin is not None and beta != 0.0) else None

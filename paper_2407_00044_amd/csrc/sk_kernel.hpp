@@ -173,6 +173,57 @@ struct KMajorStage {
   }
 };
 
+// Register-staged variant of the K-contiguous path (16-byte buffer loads
+// into registers, then 16-byte LDS writes); selected at build time.
+template <int R, int EB>
+struct KMajorStageReg {
+  static constexpr int EPC = 16 / EB;
+  static constexpr int KE = 128 / EB;
+  static constexpr int NCH = R * 8 / NT;     // chunks per thread
+  static_assert(NCH >= 1 && (R * 8) % NT == 0, "tile rows");
+  u32x4 v[NCH];
+
+  __device__ __forceinline__ static bool slow(const OpTile& o, int64_t k0) {
+    return KMajorStage<R, EB>::slow(o, k0);
+  }
+
+  __device__ __forceinline__ void issue(char*, const OpTile& o, int64_t k0, int tid) {
+    const char* base = o.X + o.row0 * o.ld_b;
+    const int64_t rows_left = o.rows - o.row0;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, (rows_left - 1) * o.ld_b + o.K * EB);
+    const uint32_t ld32 = (uint32_t)o.ld_b;
+    const uint32_t kb32 = (uint32_t)(k0 * EB);
+    const int32_t rl = (int32_t)imin(rows_left, R);
+    const int32_t kleft = (int32_t)imin(o.K - k0, KE);
+    const int c = tid & 7;
+    const bool kok = c * EPC < kleft;
+    const uint32_t lane_off = (uint32_t)(tid >> 3) * ld32 + kb32 + (uint32_t)(c * 16);
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) {
+      const int r = (tid >> 3) + j * (NT / 8);
+      const bool ok = kok && r < rl;
+      const uint32_t off = ok ? lane_off + (uint32_t)(j * (NT / 8)) * ld32 : kOOB;
+      v[j] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+    }
+  }
+
+  __device__ __forceinline__ void commit(char* L, int tid) const {
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) {
+      const int r = (tid >> 3) + j * (NT / 8);
+      *(u32x4*)(L + lds_off(r, tid & 7)) = v[j];
+    }
+  }
+
+  __device__ static void copy_slow(char* L, const OpTile& o, int64_t k0, int tid) {
+    KMajorStage<R, EB>::copy_slow(L, o, k0, tid);
+  }
+};
+
+#ifndef SK_KMAJOR_DMA
+#define SK_KMAJOR_DMA 1
+#endif
+
 // Register transpose of a block: in[j] holds 16/EB consecutive elements
 // (along M or N) of k-row j; out[i] holds the 16/EB k-values of element i.
 template <int EB>
@@ -271,7 +322,13 @@ struct MNMajorStage {
 template <bool KMAJOR, int R, int EB>
 struct StageSel;
 template <int R, int EB>
-struct StageSel<true, R, EB> { using type = KMajorStage<R, EB>; };
+struct StageSel<true, R, EB> {
+#if SK_KMAJOR_DMA
+  using type = KMajorStage<R, EB>;
+#else
+  using type = KMajorStageReg<R, EB>;
+#endif
+};
 template <int R, int EB>
 struct StageSel<false, R, EB> { using type = MNMajorStage<R, EB>; };
 
@@ -300,11 +357,15 @@ __device__ __forceinline__ Frag<DT> read_frag(const char* L, const int (&lo)[2])
 template <int DT>
 __device__ __forceinline__ void mma(v16f& acc, const Frag<DT>& a, const Frag<DT>& b) {
   if constexpr (DT == DT_F32) {
+    // element-wise copy: a bit cast of a vector-element expression reads
+    // element 0, so each element is first moved into a scalar
+    const v4f af = __builtin_bit_cast(v4f, a.c[0]);
+    const v4f bf = __builtin_bit_cast(v4f, b.c[0]);
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a.c[0][e]),
-                                                 __builtin_bit_cast(float, b.c[0][e]), acc,
-                                                 0, 0, 0);
+    for (int e = 0; e < 4; ++e) {
+      const float x = af[e], y = bf[e];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, acc, 0, 0, 0);
+    }
   } else if constexpr (DT == DT_F16) {
     acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a.c[0]),
                                                  __builtin_bit_cast(v8h, b.c[0]), acc, 0, 0, 0);
@@ -354,6 +415,27 @@ __device__ __forceinline__ void zero_acc(Acc<C>& acc) {
 // LDS stage -> matrix cores: acc += A_slab * B_slab for one iteration.
 // Lanes 0-31 and 32-63 read adjacent 16-byte (e4m3: 32-byte) pieces of K of
 // rows lane mod 32; step s covers pieces 2s, 2s+1 (e4m3: 4s .. 4s+3).
+// Software-pipelined: the fragments of step s+1 are read from LDS before the
+// matrix-core instructions of step s are issued, so LDS latency overlaps
+// with the previous step's MFMAs.
+template <typename C>
+__device__ __forceinline__ void read_step(Frag<C::DT> (&fa)[C::FM], Frag<C::DT> (&fb)[C::FN],
+                                          const char* LA_, const char* LB_, int l32, int half,
+                                          int s) {
+  int lo[2];
+  if constexpr (C::DT == DT_F8) {
+    lo[0] = frag_lane_off(l32, 4 * s + 2 * half);
+    lo[1] = frag_lane_off(l32, 4 * s + 2 * half + 1);
+  } else {
+    lo[0] = frag_lane_off(l32, 2 * s + half);
+    lo[1] = 0;
+  }
+#pragma unroll
+  for (int i = 0; i < C::FM; ++i) fa[i] = read_frag<C::DT>(LA_ + i * 32 * 128, lo);
+#pragma unroll
+  for (int j = 0; j < C::FN; ++j) fb[j] = read_frag<C::DT>(LB_ + j * 32 * 128, lo);
+}
+
 template <typename C>
 __device__ __forceinline__ void compute_stage(Acc<C>& acc, const char* stage, int tid) {
   const int wave = uniform32(tid >> 6);
@@ -362,25 +444,19 @@ __device__ __forceinline__ void compute_stage(Acc<C>& acc, const char* stage, in
   const int l32 = lane & 31;
   const char* LA_ = stage + ((wave / C::WGN) * C::WM) * 128;
   const char* LB_ = stage + C::BOFF + ((wave % C::WGN) * C::WN) * 128;
+  Frag<C::DT> fa[2][C::FM], fb[2][C::FN];
+  read_step<C>(fa[0], fb[0], LA_, LB_, l32, half, 0);
 #pragma unroll
   for (int s = 0; s < C::STEPS; ++s) {
-    int lo[2];
-    if constexpr (C::DT == DT_F8) {
-      lo[0] = frag_lane_off(l32, 4 * s + 2 * half);
-      lo[1] = frag_lane_off(l32, 4 * s + 2 * half + 1);
-    } else {
-      lo[0] = frag_lane_off(l32, 2 * s + half);
-      lo[1] = 0;
-    }
-    Frag<C::DT> fa[C::FM], fb[C::FN];
-#pragma unroll
-    for (int i = 0; i < C::FM; ++i) fa[i] = read_frag<C::DT>(LA_ + i * 32 * 128, lo);
-#pragma unroll
-    for (int j = 0; j < C::FN; ++j) fb[j] = read_frag<C::DT>(LB_ + j * 32 * 128, lo);
+    if (s + 1 < C::STEPS) read_step<C>(fa[(s + 1) & 1], fb[(s + 1) & 1], LA_, LB_, l32, half, s + 1);
+    // keep the next step's LDS reads ahead of this step's MFMAs (the
+    // scheduler would otherwise sink each read to its first use)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int i = 0; i < C::FM; ++i)
 #pragma unroll
-      for (int j = 0; j < C::FN; ++j) mma<C::DT>(acc.a[i][j], fa[i], fb[j]);
+      for (int j = 0; j < C::FN; ++j) mma<C::DT>(acc.a[i][j], fa[s & 1][i], fb[s & 1][j]);
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 

@@ -1,0 +1,147 @@
+"""Autotuner: picks the tile shape and the data-parallel / Stream-K split.
+
+Candidates are every built tile for the input type crossed with a small set
+of schedules: the two-tile hybrid rule, all tiles Stream-K, a one-tile
+Stream-K remainder (dp_tiles = T - T mod g), and the plain data-parallel
+grid.  Each candidate is timed with HIP events over a few back-to-back
+launches on the caller's buffers; the fastest is cached in a JSON file keyed
+by device, CU count, input/output types, layouts and shape, so a shape is
+measured once per machine.
+"""
+import json
+import os
+import threading
+
+import torch
+
+from . import api
+
+_lock = threading.Lock()
+
+
+def cache_path():
+    return os.environ.get("SK_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "streamk_tune.json"))
+
+
+def _load_cache():
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(c):
+    p = cache_path()
+    os.makedirs(os.path.dirname(p), exist_ok=True)
+    tmp = p + f".tmp{os.getpid()}"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def _device_key():
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return f"{getattr(props, 'gcnArchName', props.name)}/{props.multi_processor_count}cu"
+
+
+def candidates(shapes, dtype, num_cu=0, tiles=None):
+    """Candidate configs for problems `shapes` [(M, N, K), ...]."""
+    tiles = tiles or [(bm, bn) for bm, bn, _ in api.supported_tiles(dtype)]
+    out = []
+    for t in tiles:
+        base = api.Config(tile=t, num_cu=num_cu)
+        p = api.plan(shapes, dtype, base)
+        T, g = p["T"], p["g"]
+        if T == 0:
+            continue
+        out.append(base)                                       # two-tile hybrid rule
+        out.append(api.Config(tile=t, mode="sk", num_cu=num_cu))
+        one = T - T % g if T % g else T                        # one-tile SK remainder
+        if one not in (0, T):
+            out.append(api.Config(tile=t, num_cu=num_cu, dp_tiles=one))
+        out.append(api.Config(tile=t, mode="dp", num_cu=num_cu))
+    return out
+
+
+def _time(fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def _key(kind, shapes, A, B, out_dtype, num_cu):
+    la, _ = api.operand_layout(A)
+    lb, _ = api.operand_layout(B)
+    shp = ";".join(f"{m}x{n}x{k}" for m, n, k in shapes)
+    return f"{_device_key()}|{kind}|{A.dtype}|{out_dtype}|{la}{lb}|g{num_cu}|{shp}"
+
+
+def _cfg_to_dict(c):
+    return {"tile": list(c.tile), "mode": c.mode, "num_cu": c.num_cu, "dp_tiles": c.dp_tiles}
+
+
+def _cfg_from_dict(d):
+    return api.Config(tile=tuple(d["tile"]), mode=d["mode"], num_cu=d["num_cu"],
+                      dp_tiles=d["dp_tiles"])
+
+
+def tune_gemm(A, B, out_dtype=torch.float32, num_cu=0, reps=10, use_cache=True,
+              report=None):
+    """Best Config for out = A @ B on these operands (timed on them)."""
+    M, K = A.shape
+    N = B.shape[1]
+    key = _key("gemm", [(M, N, K)], A, B, out_dtype, num_cu)
+    if use_cache:
+        hit = _load_cache().get(key)
+        if hit:
+            return _cfg_from_dict(hit["config"])
+    out = torch.empty((M, N), dtype=out_dtype, device=A.device)
+    results = []
+    for c in candidates([(M, N, K)], A.dtype, num_cu):
+        ms = _time(lambda: api.gemm(A, B, out=out, config=c), reps)
+        results.append((ms, c))
+    results.sort(key=lambda r: r[0])
+    best_ms, best = results[0]
+    if report is not None:
+        report.extend(results)
+    if use_cache:
+        with _lock:
+            c = _load_cache()
+            c[key] = {"config": _cfg_to_dict(best), "ms": best_ms}
+            _store_cache(c)
+    return best
+
+
+def tune_grouped(problems, scales=None, num_cu=0, reps=10, use_cache=True, report=None):
+    """Best Config for a grouped launch over `problems` (see GroupedGemm)."""
+    shapes = [(p[0].shape[0], p[1].shape[1], p[0].shape[1]) for p in problems]
+    A0, B0, O0 = problems[0][:3]
+    key = _key("grouped", shapes, A0, B0, O0.dtype, num_cu)
+    if use_cache:
+        hit = _load_cache().get(key)
+        if hit:
+            return _cfg_from_dict(hit["config"])
+    results = []
+    for c in candidates(shapes, A0.dtype, num_cu):
+        gg = api.GroupedGemm(problems, config=c, scales=scales)
+        ms = _time(gg.run, reps)
+        results.append((ms, c))
+    results.sort(key=lambda r: r[0])
+    best_ms, best = results[0]
+    if report is not None:
+        report.extend(results)
+    if use_cache:
+        with _lock:
+            c = _load_cache()
+            c[key] = {"config": _cfg_to_dict(best), "ms": best_ms}
+            _store_cache(c)
+    return best

@@ -19,14 +19,21 @@ def dev():
     return torch.device("cuda", 0)
 
 
+def x64_to_e4m3(x64):
+    return torch.from_numpy(np.ascontiguousarray(x64)).to(torch.float8_e4m3fn)
+
+
 class Operand:
     """A seeded operand: rounded CPU tensor, its GPU placement and codes."""
 
-    def __init__(self, x64, dtype, col_major, ld=None, pad_align=True):
+    def __init__(self, x64, dtype, col_major, ld=None, pad_align=True, scaled=True):
         self.dtype = dtype
         self.col_major = col_major
-        if dtype == "e4m3":
+        if dtype == "e4m3" and scaled:
             self.t, self.scale = synth.fp8_scaled(x64)
+        elif dtype == "e4m3":
+            # small integers are exact e4m3 values: no per-tensor scaling
+            self.t, self.scale = x64_to_e4m3(x64), 1.0
         else:
             self.t, self.scale = synth.round_to(x64, dtype), 1.0
         rows, cols = x64.shape
@@ -55,7 +62,9 @@ def make_inputs(M, N, K, dtype, a_col=False, b_col=True, seed=1, dist="uniform",
         b64 = synth.integers((K, N), seed + 1000)
     else:
         raise ValueError(dist)
-    return Operand(a64, dtype, a_col, lda), Operand(b64, dtype, b_col, ldb)
+    scaled = dist != "int"
+    return (Operand(a64, dtype, a_col, lda, scaled=scaled),
+            Operand(b64, dtype, b_col, ldb, scaled=scaled))
 
 
 def oracle(A, B, M, N, K, alpha=1.0, beta=0.0, cin=None, rows=None):

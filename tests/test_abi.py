@@ -132,3 +132,13 @@ def test_workspace_init_rejects_bad_args():
     lib = sk.load()
     assert lib.sk_workspace_init(None, 64, None) == _abi.SK_ERR_INVALID_ARG
     assert lib.sk_workspace_init(None, 0, None) == _abi.SK_OK
+
+
+def test_tuner_candidates():
+    from paper_2407_00044_amd import tune
+    c = tune.candidates([(3840, 4096, 4096)], torch.bfloat16, num_cu=256)
+    modes = {(x.tile, x.mode, x.dp_tiles) for x in c}
+    assert ((256, 128), "hybrid", -1) in modes and ((256, 256), "dp", -1) in modes
+    assert ((128, 128), "sk", -1) in modes
+    # T = 480 tiles of 256x128 on 256 workgroups: one-tile remainder keeps 256 DP tiles
+    assert ((256, 128), "hybrid", 256) in modes
