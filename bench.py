@@ -28,7 +28,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--only", default="", help="run only this leg (sk|dp|bf16)")
+    ap.add_argument("--only", default="",
+                    help="run only this leg: sk | dp | bf16 | copy (plain device copy of "
+                         "512 MiB, used to calibrate byte counters)")
     return ap.parse_args()
 
 
@@ -64,24 +66,62 @@ def time_gemm(A, B, cfg, steps, warmup):
     return start.elapsed_time(end) / steps, out
 
 
-def cpu_baseline(host, M, N, K, rows=24):
-    """The FP64 oracle on a bounded row sample of the same product."""
-    import numpy as np
+def cpu_baseline(host, M, N, K, min_seconds=10.0, max_reps=4):
+    """The FP64 oracle (as it stands) on the same product: the full
+    M x N x K GEMM, repeated until about `min_seconds` of wall time."""
     from oracle import gemm as og
     from paper_2407_00044_amd import synth
     sa, lda, sb, ldb = host
     a = og.decode_f16(synth.codes(sa.cpu()))
     b = og.decode_f16(synth.codes(sb.cpu()))
-    sel = np.arange(rows, dtype=np.int64) * (M // rows)
-    og.gemm(M, N, K, a, lda, False, b, ldb, True, rows=sel[:2])   # warm
+    reps = 0
     t0 = time.perf_counter()
-    og.gemm(M, N, K, a, lda, False, b, ldb, True, rows=sel)
+    while reps < max_reps and (reps == 0 or time.perf_counter() - t0 < min_seconds):
+        og.gemm(M, N, K, a, lda, False, b, ldb, True)
+        reps += 1
     dt = time.perf_counter() - t0
-    flops = 2.0 * rows * N * K
+    flops = 2.0 * M * N * K * reps
     return {"value": round(flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": og.num_threads(),
             "kind": "oracle",
-            "sample": f"{rows} of {M} output rows ({rows}x{N}x{K} MACs), FP64 triple loop, "
-                      f"{dt:.2f} s wall"}
+            "sample": f"full {M}x{N}x{K} FP64 product of the same rounded inputs, {reps} "
+                      f"repetition(s), {dt:.1f} s wall"}
+
+
+def kernel_source_hash():
+    """Hash of the sources the measured kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2407_00044_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_key):
+    """HBM bytes per launch of `kernel_key` from the committed counter
+    summary, or None when absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    e = d.get("kernels", {}).get(kernel_key)
+    return None if e is None else e.get("hbm_bytes_per_launch")
+
+
+def copy_leg():
+    """A plain device copy of known size (calibrates FETCH_SIZE/WRITE_SIZE)."""
+    import torch
+    n = 512 * 1024 * 1024
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n}))
 
 
 def main():
@@ -90,6 +130,9 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(every run of this build uses a single MI355X)", file=sys.stderr)
         sys.exit(2)
+    if args.only == "copy":
+        copy_leg()
+        return
     import torch
     import paper_2407_00044_amd as sk
 
@@ -147,7 +190,8 @@ def main():
         "pct_mfma_peak": round(100 * tflops / PEAK_TFLOPS["f16"], 2),
         "roofline": {"bound": "mfma", "achieved": round(tflops, 2),
                      "peak": PEAK_TFLOPS["f16"], "unit": "TFLOP/s",
-                     "frac": round(tflops / PEAK_TFLOPS["f16"], 4), "traffic": None},
+                     "frac": round(tflops / PEAK_TFLOPS["f16"], 4),
+                     "traffic": traffic_from_profile("sk_f16_rc_256x128_hybrid")},
     }
     if "dp" in result:
         dtf = flops / result["dp"] / 1e9

@@ -33,7 +33,7 @@ class Config:
     num_cu: compute units (0 = all); wg_per_cu: persistent workgroups per CU.
     dp_tiles: -1 = two-tile hybrid rule, else number of data-parallel tiles.
     """
-    tile: tuple = (256, 256)
+    tile: tuple = (256, 128)
     mode: str = "hybrid"
     num_cu: int = 0
     wg_per_cu: int = 1
@@ -54,8 +54,6 @@ def default_tile(M, N, K, dtype):
     code = DTYPE_CODES[dtype]
     if code == _abi.SK_F32:
         return (128, 128)
-    if M >= 2048 and N >= 2048:
-        return (256, 256)
     if M >= 256 and N >= 128:
         return (256, 128)
     if code == _abi.SK_F8E4M3 and M <= 64:

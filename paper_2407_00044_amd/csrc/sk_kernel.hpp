@@ -99,13 +99,27 @@ struct OpTile {
   bool aligned;        // base and ld_b are multiples of 16 bytes
 };
 
+// One element of EB bytes through a buffer resource; an out-of-range offset
+// (kOOB) reads as zero.
 template <int EB>
-__device__ __forceinline__ void copy_elem_to_lds(char* L, int r, int kk, const char* src, bool ok) {
-  const int byte = kk * EB;
-  char* dst = L + lds_off(r, byte >> 4) + (byte & 15);
-  if constexpr (EB == 4) *(uint32_t*)dst = ok ? *(const uint32_t*)src : 0u;
-  else if constexpr (EB == 2) *(uint16_t*)dst = ok ? *(const uint16_t*)src : (uint16_t)0;
-  else *(uint8_t*)dst = ok ? *(const uint8_t*)src : (uint8_t)0;
+__device__ __forceinline__ uint32_t buf_elem(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  if constexpr (EB == 4) return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+  else if constexpr (EB == 2) return __builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, 0, 0);
+  else return __builtin_amdgcn_raw_buffer_load_b8(rs, (int)off, 0, 0);
+}
+
+// Packs 16/EB elements (each in the low EB bytes of a word) into a chunk.
+template <int EB>
+__device__ __forceinline__ u32x4 pack_chunk(const uint32_t (&e)[16 / EB]) {
+  u32x4 v;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    if constexpr (EB == 4) v[w] = e[w];
+    else if constexpr (EB == 2) v[w] = (e[2 * w] & 0xffffu) | (e[2 * w + 1] << 16);
+    else v[w] = (e[4 * w] & 0xffu) | ((e[4 * w + 1] & 0xffu) << 8) |
+                ((e[4 * w + 2] & 0xffu) << 16) | (e[4 * w + 3] << 24);
+  }
+  return v;
 }
 
 // K-contiguous operand ("row-major A" / "column-major B"): element (r, k) at
@@ -163,12 +177,35 @@ struct KMajorStage {
 
   __device__ __forceinline__ void commit(char*, int) const {}
 
+  // Element-wise path (any alignment, any K): every element of the thread's
+  // chunks is loaded on its own with an out-of-range offset where it lies
+  // outside the matrix; all loads are issued before the chunks are packed
+  // and written to LDS.
   __device__ static void copy_slow(char* L, const OpTile& o, int64_t k0, int tid) {
-    for (int idx = tid; idx < R * KE; idx += NT) {
-      const int r = idx / KE, kk = idx % KE;
-      const int64_t grow = o.row0 + r, k = k0 + kk;
-      const bool ok = grow < o.rows && k < o.K;
-      copy_elem_to_lds<EB>(L, r, kk, o.X + (ok ? grow * o.ld_b + k * EB : 0), ok);
+    constexpr int NCH = R * 8 / NT;
+    const char* base = o.X + o.row0 * o.ld_b;
+    const int64_t rows_left = o.rows - o.row0;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, (rows_left - 1) * o.ld_b + o.K * EB);
+    const int32_t rl = (int32_t)imin(rows_left, R);
+    const int32_t kleft = (int32_t)imin(o.K - k0, KE);
+    const uint32_t ld32 = (uint32_t)o.ld_b;
+    const uint32_t kb32 = (uint32_t)(k0 * EB);
+    const int c = tid & 7;
+    uint32_t e[NCH][EPC];
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) {
+      const int r = (tid >> 3) + j * (NT / 8);
+#pragma unroll
+      for (int i = 0; i < EPC; ++i) {
+        const int kk = c * EPC + i;
+        const bool ok = r < rl && kk < kleft;
+        e[j][i] = buf_elem<EB>(rs, ok ? (uint32_t)r * ld32 + kb32 + (uint32_t)(kk * EB) : kOOB);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) {
+      const int r = (tid >> 3) + j * (NT / 8);
+      *(u32x4*)(L + lds_off(r, c)) = pack_chunk<EB>(e[j]);
     }
   }
 };
@@ -309,12 +346,41 @@ struct MNMajorStage {
     }
   }
 
+  // Element-wise path: like issue()/commit() but every element is loaded on
+  // its own (any alignment, partial row chunks).
   __device__ static void copy_slow(char* L, const OpTile& o, int64_t k0, int tid) {
-    for (int idx = tid; idx < R * KE; idx += NT) {
-      const int kk = idx / R, r = idx % R;
-      const int64_t grow = o.row0 + r, k = k0 + kk;
-      const bool ok = grow < o.rows && k < o.K;
-      copy_elem_to_lds<EB>(L, r, kk, o.X + (ok ? k * o.ld_b + grow * EB : 0), ok);
+    const char* base = o.X + o.row0 * EB;
+    const int64_t rows_left = o.rows - o.row0;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, (o.K - 1) * o.ld_b + rows_left * EB);
+    const uint32_t ld32 = (uint32_t)o.ld_b;
+    const int32_t rl = (int32_t)imin(rows_left, R);
+    const int32_t kleft = (int32_t)imin(o.K - k0, KE);
+    const uint32_t kb32 = (uint32_t)k0 * ld32;
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      const int bidx = tid + NT * b;
+      if (NBLK % NT != 0 && bidx >= NBLK) continue;
+      const int rb = bidx % RB;
+      const int kc = bidx / RB;
+      uint32_t e[EPC][EPC];     // [k-row j][element i]
+#pragma unroll
+      for (int j = 0; j < EPC; ++j) {
+        const int kk = kc * EPC + j;
+#pragma unroll
+        for (int i = 0; i < EPC; ++i) {
+          const int r = rb * EPC + i;
+          const bool ok = r < rl && kk < kleft;
+          e[j][i] = buf_elem<EB>(rs, ok ? kb32 + (uint32_t)kk * ld32 + (uint32_t)(r * EB) : kOOB);
+        }
+      }
+      // element i of the chunk for tile row rb*EPC+i holds k-row j: transpose
+#pragma unroll
+      for (int i = 0; i < EPC; ++i) {
+        uint32_t t[EPC];
+#pragma unroll
+        for (int j = 0; j < EPC; ++j) t[j] = e[j][i];
+        *(u32x4*)(L + lds_off(rb * EPC + i, kc)) = pack_chunk<EB>(t);
+      }
     }
   }
 };
@@ -393,6 +459,13 @@ struct Cfg {
   static constexpr int STEPS = DT == DT_F8 ? 2 : 4;  // matrix-core steps per iteration
   static constexpr int BOFF = BM * 128;              // B tile offset in a stage
   static constexpr int STAGE = (BM + BN) * 128;      // LDS bytes per stage
+  // Both operands K-contiguous: LDS-direct copies, as many stages as fit in
+  // 160 KiB (at most 4); otherwise double-buffered register staging.
+  static constexpr bool DMA = (LA == L_ROW) && (LB == L_COL) && SK_KMAJOR_DMA;
+  static constexpr int NS_FIT = (160 * 1024) / STAGE;
+  static constexpr int NSTAGE = DMA ? (NS_FIT > 4 ? 4 : NS_FIT) : 2;
+  // LDS-direct copies issued per wave for one iteration
+  static constexpr int NLOADS = BM / 32 + BN / 32;
   static_assert(WGM * WGN == 4 && FM >= 1 && FN >= 1, "wave grid");
   static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile");
   using StageA = typename StageSel<LA == L_ROW, BM, EB>::type;
@@ -436,26 +509,42 @@ __device__ __forceinline__ void read_step(Frag<C::DT> (&fa)[C::FM], Frag<C::DT> 
   for (int j = 0; j < C::FN; ++j) fb[j] = read_frag<C::DT>(LB_ + j * 32 * 128, lo);
 }
 
+// Fragment registers are triple-buffered: the reads for step s+2 go to the
+// set that step s-1 used, so they never overwrite registers that in-flight
+// MFMAs of step s are still reading, and they are interleaved between the
+// MFMAs of step s (one LDS read, then a couple of MFMAs).
 template <typename C>
 __device__ __forceinline__ void compute_stage(Acc<C>& acc, const char* stage, int tid) {
+  constexpr int NR = C::FM + C::FN;              // LDS reads per step (per piece)
+  constexpr int NM = C::FM * C::FN;              // MFMAs per step
   const int wave = uniform32(tid >> 6);
   const int lane = tid & 63;
   const int half = lane >> 5;
   const int l32 = lane & 31;
   const char* LA_ = stage + ((wave / C::WGN) * C::WM) * 128;
   const char* LB_ = stage + C::BOFF + ((wave % C::WGN) * C::WN) * 128;
-  Frag<C::DT> fa[2][C::FM], fb[2][C::FN];
+  Frag<C::DT> fa[3][C::FM], fb[3][C::FN];
   read_step<C>(fa[0], fb[0], LA_, LB_, l32, half, 0);
+  if (C::STEPS > 1) read_step<C>(fa[1], fb[1], LA_, LB_, l32, half, 1);
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int s = 0; s < C::STEPS; ++s) {
-    if (s + 1 < C::STEPS) read_step<C>(fa[(s + 1) & 1], fb[(s + 1) & 1], LA_, LB_, l32, half, s + 1);
-    // keep the next step's LDS reads ahead of this step's MFMAs (the
-    // scheduler would otherwise sink each read to its first use)
-    __builtin_amdgcn_sched_barrier(0);
+    const int cur = s % 3;
+    if (s + 2 < C::STEPS) read_step<C>(fa[(s + 2) % 3], fb[(s + 2) % 3], LA_, LB_, l32, half, s + 2);
 #pragma unroll
     for (int i = 0; i < C::FM; ++i)
 #pragma unroll
-      for (int j = 0; j < C::FN; ++j) mma<C::DT>(acc.a[i][j], fa[s & 1][i], fb[s & 1][j]);
+      for (int j = 0; j < C::FN; ++j) mma<C::DT>(acc.a[i][j], fa[cur][i], fb[cur][j]);
+    if (s + 2 < C::STEPS) {
+      // interleave: each LDS read followed by its share of the MFMAs
+      constexpr int PER = NM / NR > 0 ? NM / NR : 1;
+#pragma unroll
+      for (int r = 0; r < NR * (C::DT == DT_F8 ? 2 : 1); ++r) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one DS read
+        __builtin_amdgcn_sched_group_barrier(0x008, PER, 0); // MFMAs
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, NM, 0);    // the rest
+    }
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -491,6 +580,140 @@ __device__ __forceinline__ void mac_loop_fast(Acc<C>& acc, const OpTile& oa, con
     }
     __syncthreads();   // waits for this iteration's copies into nxt
   }
+}
+
+// Waits until at most `n` vector-memory operations of this wave are
+// outstanding (n <= 63); other counters are not waited for.
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Multi-stage MAC loop for LDS-direct copies (both operands K-contiguous).
+//
+// Iteration k works on LDS stage k mod NSTAGE in two halves of its
+// matrix-core steps.  During the first half the fragments of the second
+// half are read; then, in the middle of the iteration, each wave waits until
+// its copies for iteration k+1 have landed and the workgroup barrier makes
+// every wave's copies visible (the MFMAs issued before it keep the matrix
+// cores busy through the wait); the copies of iteration k+NSTAGE-1 are issued
+// into the stage of iteration k-1, which every wave has finished reading;
+// during the second half the fragments of iteration k+1's first half are
+// read.  So no LDS latency is exposed at iteration boundaries, and
+// NSTAGE-2 iterations plus half of one cover the copy latency.
+// One matrix-core step with the LDS reads of another step woven in: the
+// t-th read is issued right before the t-th MFMA, and nothing is allowed to
+// move across the pairs, so reads always trail far enough behind the MFMAs
+// that consume earlier fragments.
+template <typename C>
+__device__ __forceinline__ void step_with_reads(Acc<C>& acc, const Frag<C::DT> (&fa)[C::FM],
+                                                const Frag<C::DT> (&fb)[C::FN],
+                                                Frag<C::DT> (&ra)[C::FM], Frag<C::DT> (&rb)[C::FN],
+                                                const char* LA_, const char* LB_, int l32,
+                                                int half, int rs) {
+  constexpr int NR = C::FM + C::FN;
+  constexpr int NM = C::FM * C::FN;
+  constexpr int NT_ = NR > NM ? NR : NM;
+  int lo[2];
+  if constexpr (C::DT == DT_F8) {
+    lo[0] = frag_lane_off(l32, 4 * rs + 2 * half);
+    lo[1] = frag_lane_off(l32, 4 * rs + 2 * half + 1);
+  } else {
+    lo[0] = frag_lane_off(l32, 2 * rs + half);
+    lo[1] = 0;
+  }
+#pragma unroll
+  for (int i = 0; i < C::FM; ++i) ra[i] = read_frag<C::DT>(LA_ + i * 32 * 128, lo);
+#pragma unroll
+  for (int j = 0; j < C::FN; ++j) rb[j] = read_frag<C::DT>(LB_ + j * 32 * 128, lo);
+#pragma unroll
+  for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j) mma<C::DT>(acc.a[i][j], fa[i], fb[j]);
+  // pattern for the scheduler: (one DS read, one MFMA) pairs, then the rest
+  constexpr int NRD = NR * (C::DT == DT_F8 ? 2 : 1);
+#pragma unroll
+  for (int t = 0; t < NT_; ++t) {
+    if (t < NRD) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    if (t < NM) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt_le(int ahead_iters) {
+  // wait until at most `ahead_iters` iterations' copies (N each) are in
+  // flight; ahead_iters is 0, 1 or 2
+  if (ahead_iters >= 2) wait_vmcnt<2 * N < 64 ? 2 * N : 63>();
+  else if (ahead_iters == 1) wait_vmcnt<N>();
+  else wait_vmcnt<0>();
+}
+
+template <typename C>
+__device__ __forceinline__ void mac_loop_dma(Acc<C>& acc, const OpTile& oa, const OpTile& ob,
+                                             int kb, int ke, char* lds, int tid,
+                                             int32_t* cover_row) {
+  constexpr int NS = C::NSTAGE;
+  constexpr int ST = C::STEPS;
+  constexpr int HALF = ST / 2;
+  typename C::StageA sa;
+  typename C::StageB sb;
+  const int wave = uniform32(tid >> 6);
+  const int lane = tid & 63;
+  const int half = lane >> 5;
+  const int l32 = lane & 31;
+  const int aoff = ((wave / C::WGN) * C::WM) * 128;
+  const int boff = C::BOFF + ((wave % C::WGN) * C::WN) * 128;
+
+#pragma unroll
+  for (int j = 0; j < NS - 1; ++j) {
+    if (kb + j < ke) {
+      sa.issue(lds + j * C::STAGE, oa, (int64_t)(kb + j) * C::KE, tid);
+      sb.issue(lds + j * C::STAGE + C::BOFF, ob, (int64_t)(kb + j) * C::KE, tid);
+    }
+  }
+  // copies of iteration kb landed (later ones may still be in flight)
+  wait_vmcnt_le<C::NLOADS>((int)imin(NS - 2, ke - 1 - kb));
+  __builtin_amdgcn_s_barrier();
+
+  Frag<C::DT> fa[ST][C::FM], fb[ST][C::FN];
+#pragma unroll
+  for (int s = 0; s < HALF; ++s)
+    read_step<C>(fa[s], fb[s], lds + aoff, lds + boff, l32, half, s);
+
+  int slot = 0;
+  for (int k = kb; k < ke; ++k) {
+    const char* cur = lds + slot * C::STAGE;
+    const bool more = k + 1 < ke;
+    const int nslot = more ? (slot == NS - 1 ? 0 : slot + 1) : slot;
+    const char* nxt = lds + nslot * C::STAGE;   // last iteration: harmless re-read
+    if (cover_row != nullptr && tid == 0) atomicAdd(cover_row + k, 1);
+    // first half: MFMAs of steps [0, HALF), reads of steps [HALF, ST)
+#pragma unroll
+    for (int s = 0; s < HALF; ++s)
+      step_with_reads<C>(acc, fa[s], fb[s], fa[s + HALF], fb[s + HALF], cur + aoff, cur + boff,
+                         l32, half, s + HALF);
+    // copies of k+1 landed in every wave; the stage of k-1 is free
+    wait_vmcnt_le<C::NLOADS>((int)imin(NS - 3, imax(ke - 2 - k, 0)));
+    __builtin_amdgcn_s_barrier();
+    if (k + NS - 1 < ke) {
+      const int fill = slot == 0 ? NS - 1 : slot - 1;
+      char* dst = lds + fill * C::STAGE;
+      sa.issue(dst, oa, (int64_t)(k + NS - 1) * C::KE, tid);
+      sb.issue(dst + C::BOFF, ob, (int64_t)(k + NS - 1) * C::KE, tid);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // second half: MFMAs of steps [HALF, ST), reads of the next iteration's
+    // steps [0, HALF)
+#pragma unroll
+    for (int s = HALF; s < ST; ++s)
+      step_with_reads<C>(acc, fa[s], fb[s], fa[s - HALF], fb[s - HALF], nxt + aoff, nxt + boff,
+                         l32, half, s - HALF);
+    slot = nslot;
+  }
+  __syncthreads();   // the stages are reused by the next segment
 }
 
 // One iteration through the element-wise path (edges the fast path cannot
@@ -530,7 +753,10 @@ __device__ __forceinline__ void mac_loop(Acc<C>& acc, const ProbDesc& pd, int64_
   else if (ke > kb && (C::StageA::slow(oa, (int64_t)(ke - 1) * C::KE) ||
                        C::StageB::slow(ob, (int64_t)(ke - 1) * C::KE)))
     kf = ke - 1;
-  if (kf > kb) mac_loop_fast<C>(acc, oa, ob, kb, kf, lds, tid, cover_row);
+  if (kf > kb) {
+    if constexpr (C::DMA && C::NSTAGE >= 3) mac_loop_dma<C>(acc, oa, ob, kb, kf, lds, tid, cover_row);
+    else mac_loop_fast<C>(acc, oa, ob, kb, kf, lds, tid, cover_row);
+  }
   for (int k = kf; k < ke; ++k) {
     stage_slow<C>(oa, ob, (int64_t)k * C::KE, lds, tid);
     __syncthreads();
@@ -760,7 +986,7 @@ struct Item {
 
 template <typename C>
 __global__ __launch_bounds__(NT, 1) void sk_gemm_kernel(KParams P) {
-  __shared__ __attribute__((aligned(16))) char lds[2 * C::STAGE];
+  __shared__ __attribute__((aligned(16))) char lds[C::NSTAGE * C::STAGE];
   const int tid = threadIdx.x;
   const int64_t b = blockIdx.x;
 

@@ -32,6 +32,7 @@ namespace sk {
 
 SK_HD int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 SK_HD int64_t imin(int64_t a, int64_t b) { return a < b ? a : b; }
+SK_HD int64_t imax(int64_t a, int64_t b) { return a > b ? a : b; }
 
 // Local tile index u -> (tile row, tile column).
 SK_HD void tile_coords(int64_t u, int32_t tm, int32_t tn, int32_t group_m,

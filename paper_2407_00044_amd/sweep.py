@@ -1,0 +1,107 @@
+"""BF16 shape sweep: Stream-K vs equal-tile data-parallel tiling.
+
+64 shapes with M, N log-uniform in [128, 8192] and K log-uniform in
+[128, 16384] (seeded); A row-major, B column-major with leading dimensions
+rounded up to 16 bytes, N(0,1) entries, FP32 C_in uniform in [-1, 1],
+alpha = 1, beta = 0.5.  For each shape both schedules use the same tile;
+the report lists TFLOP/s = 2*M*N*K / t per shape, the min and geometric mean
+of each schedule, the predicted quantization loss of one-tile-per-workgroup
+tiling 1 - T / (ceil(T/g) * g) and the measured ratio t_DP / t_SK.
+
+    python -m paper_2407_00044_amd.sweep [--n 64] [--reps 10] [--tune]
+"""
+import argparse
+import json
+import math
+import sys
+import time
+
+import torch
+
+from . import api, synth, tune
+
+
+def _time(fn, reps, warm=2):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def gmean(xs):
+    return math.exp(sum(math.log(x) for x in xs) / len(xs))
+
+
+def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout):
+    dev = torch.device("cuda", torch.cuda.current_device())
+    cus, _ = api.device_query(api.Config(tile=(256, 128)), torch.bfloat16)
+    rows = []
+    for idx, (M, N, K) in enumerate(synth.sweep_shapes(seed, n)):
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(300 + idx)
+        lda = synth.ld_aligned(K, 2)
+        ldb = synth.ld_aligned(K, 2)
+        A = torch.randn((M, lda), generator=gen, device=dev).to(torch.bfloat16)[:, :K]
+        B = torch.randn((N, ldb), generator=gen, device=dev).to(torch.bfloat16)[:, :K].t()
+        C = (torch.rand((M, N), generator=gen, device=dev) * 2 - 1)
+        outC = torch.empty_like(C)
+        tile = api.default_tile(M, N, K, torch.bfloat16)
+        cfg_sk = api.Config(tile=tile, mode="hybrid")
+        cfg_dp = api.Config(tile=tile, mode="dp")
+
+        def go(cfg):
+            return lambda: api.gemm(A, B, C, beta=0.5, out=outC, config=cfg)
+        t_sk = _time(go(cfg_sk), reps)
+        t_dp = _time(go(cfg_dp), reps)
+        p = api.plan([(M, N, K)], torch.bfloat16, cfg_sk)
+        T = p["T"]
+        q_eff = T / (math.ceil(T / cus) * cus)
+        flops = 2.0 * M * N * K
+        row = {"M": M, "N": N, "K": K, "tile": list(tile), "T": T, "S": p["S"],
+               "sk_tflops": flops / t_sk / 1e9, "dp_tflops": flops / t_dp / 1e9,
+               "dp_quant_eff": q_eff, "t_dp_over_t_sk": t_dp / t_sk}
+        if use_tuner:
+            best = tune.tune_gemm(A, B, torch.float32, reps=max(3, reps // 2))
+            t_best = _time(go(best), reps)
+            row["tuned"] = {"config": [list(best.tile), best.mode, best.dp_tiles],
+                            "tflops": flops / t_best / 1e9}
+        rows.append(row)
+        print(f"# {idx:2d} {M}x{N}x{K} tile {tile} T={T}: SK {row['sk_tflops']:.1f} "
+              f"DP {row['dp_tflops']:.1f} TFLOP/s  (DP quant eff {q_eff:.3f})",
+              file=sys.stderr, flush=True)
+        del A, B, C, outC
+    sk = [r["sk_tflops"] for r in rows]
+    dp = [r["dp_tflops"] for r in rows]
+    summary = {"shapes": len(rows), "sk_min": min(sk), "sk_geomean": gmean(sk),
+               "dp_min": min(dp), "dp_geomean": gmean(dp),
+               "sk_beats_dp_geomean": gmean(sk) > gmean(dp), "sk_beats_dp_min": min(sk) > min(dp),
+               "mean_predicted_quant_loss": sum(1 - r["dp_quant_eff"] for r in rows) / len(rows),
+               "geomean_t_dp_over_t_sk": gmean([r["t_dp_over_t_sk"] for r in rows])}
+    if use_tuner:
+        tb = [r["tuned"]["tflops"] for r in rows]
+        summary.update({"tuned_min": min(tb), "tuned_geomean": gmean(tb)})
+    json.dump({"summary": summary, "rows": rows}, out)
+    out.write("\n")
+    return summary
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--tune", action="store_true")
+    a = ap.parse_args()
+    t0 = time.time()
+    run(a.n, a.reps, a.tune)
+    print(f"# sweep done in {time.time() - t0:.1f} s", file=sys.stderr)
+
+
+if __name__ == "__main__":
+    main()

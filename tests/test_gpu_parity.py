@@ -159,3 +159,22 @@ def test_bf16_headline_shape_256x256_sampled_rows():
         cfg = sk.Config(tile=(256, 256), mode=mode, num_cu=256)
         got, ref = _sampled(3840, 4096, 4096, "bf16", cfg, "uniform", 4)
         assert rel_err(got, ref) <= 1e-4
+
+
+def test_bf16_sweep_shapes_beta_sampled():
+    # the BF16 shape sweep's recipe (A row-major, B column-major, ld rounded
+    # to 16 bytes, N(0,1), beta = 0.5 with C_in uniform [-1,1]) on a subset of
+    # its shapes, sampled rows against the oracle
+    shapes = synth.sweep_shapes()
+    for i in [0, 5, 11, 17, 23, 42, 63]:
+        M, N, K = shapes[i]
+        A, B = make_inputs(M, N, K, "bf16", False, True, 300 + i, "normal")
+        cin64 = synth.uniform((M, N), 900 + i)
+        Cin = torch.from_numpy(cin64).float().to(dev())
+        tile = sk.default_tile(M, N, K, torch.bfloat16)
+        rows = np.unique(np.concatenate([np.random.default_rng(i).integers(0, M, 24),
+                                         [0, M - 1]]))
+        ref = oracle(A, B, M, N, K, beta=0.5, cin=cin64, rows=rows)
+        for mode in ["hybrid", "dp"]:
+            C = run(A, B, sk.Config(tile=tile, mode=mode), beta=0.5, C=Cin.clone())
+            assert rel_err(as64(C)[rows], ref) <= 1e-4, (i, mode)
