@@ -131,6 +131,13 @@ typedef struct {
   int64_t spin_limit;  /* polls a fixup wait makes before giving up and
                           raising SK_ERR_DEVICE_TIMEOUT; 0 = default (about
                           four seconds) */
+  int32_t min_iters;   /* grid floor m for SK_MODE_SK and SK_MODE_HYBRID: the
+                          launch uses g' = min(g, max(1, W_all / m))
+                          workgroups, W_all = MAC iterations of all tiles, so
+                          that a split tile has few contributors when the
+                          problem is small.  0 = automatic,
+                          m = ceil(sqrt(2 * ceil(W_all / T))); 1 = keep g.
+                          sk_plan_info.g reports g'. */
 } sk_config;
 
 /* One schedule segment (sk_schedule output, and the device trace). */

@@ -19,6 +19,15 @@ applied):
   (2) Tiles are numbered problem-major; inside a problem tile u maps to
       (tm, tn) row-major, or, with group_m > 0, band-wise: bands of group_m
       tile rows, walked down the rows first, then across the columns.
+  (2b) Grid floor (not in the report; a reading that keeps split tiles from
+      having dozens of contributors when the problem is small): with
+      min_iters = m > 1 a Stream-K or hybrid launch uses
+      g' = min(g, max(1, W_all // m)) workgroups, W_all = sum of I over all T
+      tiles, so that no workgroup gets much less than m iterations.  m = 0
+      selects m = ceil(sqrt(2 * ceil(W_all / T))): if adding one partial tile
+      costs the finishing workgroup about two MAC iterations, a tile of I
+      iterations split into c pieces takes about I/c + 2(c - 1) iteration
+      times, least at I/c = sqrt(2 I).  m = 1 keeps g.  Steps (3)-(5) use g'.
   (3) Split point S over the T = sum T_p tiles: tiles [0,S) are Stream-K
       tiles, [S,T) data-parallel tiles.  SK mode: S = T.  DP mode: S = 0 with
       one workgroup per tile.  Hybrid ("two-tile SK + DP"): S = 0 when
@@ -92,8 +101,30 @@ class Plan:
     dp_grid: bool        # DP mode: one workgroup per tile
 
 
+def isqrt_ceil(n):
+    """Smallest m >= 0 with m*m >= n (n >= 0), by plain search."""
+    m = 0
+    while m * m < n:
+        m += 1
+    return m
+
+
+def grid_floor(g, iters, min_iters):
+    """Step (2b): workgroups actually launched for Stream-K/hybrid."""
+    T = len(iters)
+    W_all = sum(iters)
+    if T == 0 or W_all == 0:
+        return g
+    m = min_iters
+    if m == 0:
+        m = isqrt_ceil(2 * cdiv(W_all, T))
+    if m <= 1:
+        return g
+    return min(g, max(1, W_all // m))
+
+
 def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
-              dp_tiles=-1, group_m=0):
+              dp_tiles=-1, group_m=0, min_iters=1):
     """Steps (1)-(5) for a list of (M, N, K) problems."""
     tiles, iters = [], []
     for p, (M, N, K) in enumerate(problems):
@@ -105,6 +136,8 @@ def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
             tiles.append((p, r, c))
             iters.append(I)
     T = len(tiles)
+    if mode != MODE_DP:
+        g = grid_floor(g, iters, min_iters)
     if mode == MODE_DP:
         S = 0
         g = T
@@ -139,11 +172,11 @@ def owner(plan, it):
 
 
 def simulate(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
-             dp_tiles=-1, group_m=0):
+             dp_tiles=-1, group_m=0, min_iters=1):
     """Segments of every workgroup, in workgroup order and, inside a
     workgroup, in processing order (steps (6)-(8))."""
     plan = make_plan(problems, block_m, block_n, block_k, g, mode, dp_tiles,
-                     group_m)
+                     group_m, min_iters)
     segs = []
     if plan.dp_grid:
         for t, (p, r, c) in enumerate(plan.tiles):

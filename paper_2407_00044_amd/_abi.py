@@ -47,7 +47,7 @@ class SkConfig(ctypes.Structure):
     _fields_ = [("block_m", c_i32), ("block_n", c_i32), ("block_k", c_i32),
                 ("num_cu", c_i32), ("wg_per_cu", c_i32), ("mode", c_i32),
                 ("dp_tiles", c_i64), ("group_m", c_i32), ("xcd_remap", c_i32),
-                ("spin_limit", c_i64)]
+                ("spin_limit", c_i64), ("min_iters", c_i32)]
 
 
 class SkSegment(ctypes.Structure):

@@ -32,6 +32,7 @@ class Config:
     mode: 'hybrid' (data-parallel + Stream-K), 'sk' or 'dp' (baseline grid).
     num_cu: compute units (0 = all); wg_per_cu: persistent workgroups per CU.
     dp_tiles: -1 = two-tile hybrid rule, else number of data-parallel tiles.
+    min_iters: Stream-K grid floor (0 = automatic, 1 = always g workgroups).
     """
     tile: tuple = (256, 128)
     mode: str = "hybrid"
@@ -41,11 +42,12 @@ class Config:
     group_m: int = 0
     xcd_remap: int = 1
     spin_limit: int = 0
+    min_iters: int = 0
 
     def c_struct(self, dtype_code):
         return SkConfig(self.tile[0], self.tile[1], K_PER_ITER[dtype_code], self.num_cu,
                         self.wg_per_cu, _abi.MODES[self.mode], self.dp_tiles, self.group_m,
-                        self.xcd_remap, self.spin_limit)
+                        self.xcd_remap, self.spin_limit, self.min_iters)
 
 
 def default_tile(M, N, K, dtype):

@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <cmath>
 #include <mutex>
 #include <vector>
 
@@ -49,13 +51,51 @@ struct Plan {
   std::vector<ProbDesc> descs;   // pointers left null by plan_problems
 };
 
+// Per-device facts are queried once and cached (these runtime queries cost
+// microseconds, more than a small GEMM).
+static std::mutex g_cache_mu;
+static std::map<int, int> g_cus;                                   // device -> CUs
+static std::map<std::pair<int, const void*>, int> g_resident;      // (device, kernel) -> WGs/CU
+
 static sk_status device_cus(int32_t* n) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return SK_ERR_HIP;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cus.find(dev);
+    if (it != g_cus.end()) {
+      *n = it->second;
+      return SK_OK;
+    }
+  }
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return SK_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cus[dev] = v;
   *n = v;
+  return SK_OK;
+}
+
+// Workgroups of kernel `ke` that fit on one CU at once.
+static sk_status resident_per_cu(const KernelEntry* ke, int* per_cu) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SK_ERR_HIP;
+  const auto key = std::make_pair(dev, ke->fn);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_resident.find(key);
+    if (it != g_resident.end()) {
+      *per_cu = it->second;
+      return SK_OK;
+    }
+  }
+  int v = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, ke->fn, ke->nt, 0) != hipSuccess)
+    return SK_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_resident[key] = v;
+  *per_cu = v;
   return SK_OK;
 }
 
@@ -83,7 +123,7 @@ static sk_status resolve_config(const sk_config* cfg, int32_t dtype_ab, int64_t*
   if (!tile_built(dtype_ab, cfg->block_m, cfg->block_n)) return SK_ERR_UNSUPPORTED;
   if (cfg->group_m < 0 || cfg->wg_per_cu < 0 || cfg->num_cu < 0) return SK_ERR_INVALID_ARG;
   if (cfg->dp_tiles < -1) return SK_ERR_INVALID_ARG;
-  if (cfg->spin_limit < 0) return SK_ERR_INVALID_ARG;
+  if (cfg->spin_limit < 0 || cfg->min_iters < 0) return SK_ERR_INVALID_ARG;
   int32_t cus = cfg->num_cu;
   if (cus == 0) {
     sk_status st = device_cus(&cus);
@@ -92,6 +132,39 @@ static sk_status resolve_config(const sk_config* cfg, int32_t dtype_ab, int64_t*
   const int64_t wpc = cfg->wg_per_cu == 0 ? 1 : cfg->wg_per_cu;
   *g_out = (int64_t)cus * wpc;
   return SK_OK;
+}
+
+// The kernels address a tile's operands and output with 32-bit byte offsets
+// from the tile's first element (buffer instructions); every offset a tile
+// can form must stay below 2^31.
+static bool offsets_fit(const sk_problem& p, int64_t bm, int64_t bn) {
+  const int64_t eb = elem_bytes(p.dtype_ab), ec = p.dtype_c == SK_F32 ? 4 : 2;
+  const int64_t rm = std::min<int64_t>(std::max<int64_t>(p.M, 1), bm);
+  const int64_t rn = std::min<int64_t>(std::max<int64_t>(p.N, 1), bn);
+  const int64_t k = std::max<int64_t>(p.K, 1);
+  const int64_t span_a = p.layout_a == SK_ROW_MAJOR ? ((rm - 1) * p.lda + k) * eb
+                                                    : ((k - 1) * p.lda + bm) * eb;
+  const int64_t span_b = p.layout_b == SK_COL_MAJOR ? ((rn - 1) * p.ldb + k) * eb
+                                                    : ((k - 1) * p.ldb + bn) * eb;
+  const int64_t span_c = ((rm - 1) * p.ldc + bn) * ec;
+  return span_a <= kMaxIndex && span_b <= kMaxIndex && span_c <= kMaxIndex;
+}
+
+// Grid floor: with m = min_iters > 1 (0: m = ceil(sqrt(2 ceil(W_all/T))),
+// the point where the finisher's extra work for more contributors, about
+// two MAC iterations per partial tile, balances the shorter pieces), a
+// Stream-K launch of a small problem uses max(1, W_all / m) < g workgroups.
+static int64_t grid_floor(int64_t g, int64_t T, int64_t W_all, int32_t min_iters) {
+  if (T == 0 || W_all == 0) return g;
+  int64_t m = min_iters;
+  if (m == 0) {
+    const int64_t target = 2 * cdiv(W_all, T);
+    m = (int64_t)std::sqrt((double)target);
+    while (m * m < target) ++m;
+    while (m > 1 && (m - 1) * (m - 1) >= target) --m;
+  }
+  if (m <= 1) return g;
+  return std::min<int64_t>(g, std::max<int64_t>(1, W_all / m));
 }
 
 // Tile counts, split point, iteration space and per-problem offsets.
@@ -109,6 +182,8 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
   sk_status st = resolve_config(cfg, probs[0].dtype_ab, &g);
   if (st != SK_OK) return st;
   const int64_t bm = cfg->block_m, bn = cfg->block_n, bk = cfg->block_k;
+  for (int32_t i = 0; i < n; ++i)
+    if (!offsets_fit(probs[i], bm, bn)) return SK_ERR_UNSUPPORTED;
 
   Plan P;
   P.descs.resize(n);
@@ -134,8 +209,10 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
     P.S = 0;
     P.g = T;
   } else {
-    P.g = g;
-    P.S = split_point(T, g, cfg->mode, cfg->dp_tiles);
+    int64_t W_all = 0;
+    for (int32_t i = 0; i < n; ++i) W_all += (int64_t)P.descs[i].tm * P.descs[i].tn * P.descs[i].I;
+    P.g = grid_floor(g, T, W_all, cfg->min_iters);
+    P.S = split_point(T, P.g, cfg->mode, cfg->dp_tiles);
   }
   // Stream-K iteration offsets (problem-major, so J is monotone in p).
   int64_t J = 0;
@@ -242,8 +319,8 @@ static sk_status launch(const Plan& P, const sk_config* cfg, int32_t dt, int32_t
     if (st != SK_OK) return st;
     if (cfg->num_cu > cus) return SK_ERR_INVALID_ARG;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ke->fn, 256, 0) != hipSuccess)
-      return SK_ERR_HIP;
+    st = resident_per_cu(ke, &per_cu);
+    if (st != SK_OK) return st;
     // Stream-K workgroups wait for each other: all must be resident at once.
     if (P.g > (int64_t)cus * per_cu) return SK_ERR_OCCUPANCY;
   }
@@ -277,7 +354,7 @@ static sk_status launch(const Plan& P, const sk_config* cfg, int32_t dt, int32_t
   }
   void* args[] = {&kp};
   const int64_t grid = cfg->mode == SK_MODE_DP ? P.T : P.g;
-  if (hipLaunchKernel(ke->fn, dim3((unsigned)grid), dim3(256), args, 0, stream) != hipSuccess)
+  if (hipLaunchKernel(ke->fn, dim3((unsigned)grid), dim3((unsigned)ke->nt), args, 0, stream) != hipSuccess)
     return SK_ERR_HIP;
   return SK_OK;
 }
@@ -335,8 +412,8 @@ sk_status sk_device_query(int32_t* num_cu, int32_t* max_wg_per_cu, const sk_conf
         ke = find_kernel(dtype_ab, la, lb, cfg->block_m, cfg->block_n);
     if (ke == nullptr) return SK_ERR_UNSUPPORTED;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ke->fn, 256, 0) != hipSuccess)
-      return SK_ERR_HIP;
+    st = resident_per_cu(ke, &per_cu);
+    if (st != SK_OK) return st;
     *max_wg_per_cu = per_cu;
   }
   return SK_OK;

@@ -10,21 +10,22 @@
 
 #define SK_CAT_(a, b) a##b
 #define SK_CAT(a, b) SK_CAT_(a, b)
-#define SK_INST(BM, BN, WGM)                                                          \
+#define SK_INST(BM, BN, WGM, NW)                                                      \
   static const bool SK_CAT(reg_, __LINE__) = sk::register_kernel(                     \
-      {SK_DT, SK_LA, SK_LB, BM, BN, WGM,                                              \
-       (const void*)&sk::sk_gemm_kernel<sk::Cfg<SK_DT, SK_LA, SK_LB, BM, BN, WGM>>});
+      {SK_DT, SK_LA, SK_LB, BM, BN, WGM, 64 * NW,                                     \
+       (const void*)&sk::sk_gemm_kernel<sk::Cfg<SK_DT, SK_LA, SK_LB, BM, BN, WGM, NW>>});
 
 #if SK_DT == 0
 // f32: 128x128x32 (the 512^3 Stream-K configuration)
-SK_INST(128, 128, 2)
+SK_INST(128, 128, 2, 4)
 #else
 // f16 / bf16 / e4m3: large tiles for compute-bound shapes, smaller ones for
-// small or skinny problems
-SK_INST(256, 256, 2)
-SK_INST(256, 128, 2)
-SK_INST(128, 128, 2)
+// small or skinny problems.  256x256 runs 8 waves (two per SIMD, 128x64
+// each); the others 4 waves.
+SK_INST(256, 256, 2, 8)
+SK_INST(256, 128, 2, 4)
+SK_INST(128, 128, 2, 4)
 #if SK_DT == 3
-SK_INST(64, 128, 2)
+SK_INST(64, 128, 2, 4)
 #endif
 #endif

@@ -43,7 +43,6 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3 };
 enum { L_ROW = 0, L_COL = 1 };
 enum { R_FULL = 0, R_FINISH = 1, R_PARTIAL = 2, R_DP = 3 };
-constexpr int NT = 256;        // threads per workgroup (4 waves)
 
 // Values that are the same in every lane, moved to scalar registers (the
 // compiler cannot always prove it, and a buffer descriptor in vector
@@ -128,12 +127,12 @@ __device__ __forceinline__ u32x4 pack_chunk(const uint32_t (&e)[16 / EB]) {
 // one wave instruction fills 1 KiB of LDS, i.e. 8 consecutive tile rows, and
 // lane i writes the 16 bytes at position i%8 of row i/8, so it fetches the
 // logical chunk that the swizzle puts there.  No registers hold the stage.
-template <int R, int EB>
+template <int R, int EB, int NT>
 struct KMajorStage {
   static constexpr int EPC = 16 / EB;        // elements per chunk
   static constexpr int KE = 128 / EB;        // K elements per iteration
-  static constexpr int NI = R / 32;          // 1 KiB copies per wave (4 waves)
-  static_assert(R % 32 == 0, "tile rows");
+  static constexpr int NI = R / (NT / 8);    // 1 KiB copies per wave
+  static_assert(R % (NT / 8) == 0, "tile rows");
 
   __device__ __forceinline__ static bool slow(const OpTile& o, int64_t k0) {
     return !o.aligned || ((o.K % EPC) != 0 && k0 + KE > o.K);
@@ -212,7 +211,7 @@ struct KMajorStage {
 
 // Register-staged variant of the K-contiguous path (16-byte buffer loads
 // into registers, then 16-byte LDS writes); selected at build time.
-template <int R, int EB>
+template <int R, int EB, int NT>
 struct KMajorStageReg {
   static constexpr int EPC = 16 / EB;
   static constexpr int KE = 128 / EB;
@@ -221,7 +220,7 @@ struct KMajorStageReg {
   u32x4 v[NCH];
 
   __device__ __forceinline__ static bool slow(const OpTile& o, int64_t k0) {
-    return KMajorStage<R, EB>::slow(o, k0);
+    return KMajorStage<R, EB, NT>::slow(o, k0);
   }
 
   __device__ __forceinline__ void issue(char*, const OpTile& o, int64_t k0, int tid) {
@@ -253,7 +252,7 @@ struct KMajorStageReg {
   }
 
   __device__ static void copy_slow(char* L, const OpTile& o, int64_t k0, int tid) {
-    KMajorStage<R, EB>::copy_slow(L, o, k0, tid);
+    KMajorStage<R, EB, NT>::copy_slow(L, o, k0, tid);
   }
 };
 
@@ -293,7 +292,7 @@ __device__ __forceinline__ void transpose_block(const u32x4 (&in)[16 / EB],
 // at X[k * ld + row0 + r].  A thread loads a block of EPC k-rows x EPC tile
 // rows (one 16-byte chunk per k-row), transposes it in registers and writes
 // EPC K-contiguous chunks to LDS.
-template <int R, int EB>
+template <int R, int EB, int NT>
 struct MNMajorStage {
   static constexpr int EPC = 16 / EB;
   static constexpr int KE = 128 / EB;
@@ -385,18 +384,18 @@ struct MNMajorStage {
   }
 };
 
-template <bool KMAJOR, int R, int EB>
+template <bool KMAJOR, int R, int EB, int NT>
 struct StageSel;
-template <int R, int EB>
-struct StageSel<true, R, EB> {
+template <int R, int EB, int NT>
+struct StageSel<true, R, EB, NT> {
 #if SK_KMAJOR_DMA
-  using type = KMajorStage<R, EB>;
+  using type = KMajorStage<R, EB, NT>;
 #else
-  using type = KMajorStageReg<R, EB>;
+  using type = KMajorStageReg<R, EB, NT>;
 #endif
 };
-template <int R, int EB>
-struct StageSel<false, R, EB> { using type = MNMajorStage<R, EB>; };
+template <int R, int EB, int NT>
+struct StageSel<false, R, EB, NT> { using type = MNMajorStage<R, EB, NT>; };
 
 // ---------------------------------------------------------------------------
 // Matrix-core step: one 32-byte (f32/f16/bf16) or 64-byte (e4m3) slice of K
@@ -448,12 +447,13 @@ __device__ __forceinline__ void mma(v16f& acc, const Frag<DT>& a, const Frag<DT>
 }
 
 // ---------------------------------------------------------------------------
-template <int DT_, int LA_, int LB_, int BM_, int BN_, int WGM_>
+template <int DT_, int LA_, int LB_, int BM_, int BN_, int WGM_, int NW_>
 struct Cfg {
   static constexpr int DT = DT_, LA = LA_, LB = LB_, BM = BM_, BN = BN_, WGM = WGM_;
+  static constexpr int NW = NW_, NT = 64 * NW_;     // waves, threads per workgroup
   static constexpr int EB = DT == DT_F32 ? 4 : DT == DT_F8 ? 1 : 2;
   static constexpr int KE = 128 / EB;                // K elements per iteration
-  static constexpr int WGN = 4 / WGM;
+  static constexpr int WGN = NW / WGM;
   static constexpr int WM = BM / WGM, WN = BN / WGN; // per-wave tile
   static constexpr int FM = WM / 32, FN = WN / 32;   // 32x32 blocks per wave
   static constexpr int STEPS = DT == DT_F8 ? 2 : 4;  // matrix-core steps per iteration
@@ -465,11 +465,11 @@ struct Cfg {
   static constexpr int NS_FIT = (160 * 1024) / STAGE;
   static constexpr int NSTAGE = DMA ? (NS_FIT > 4 ? 4 : NS_FIT) : 2;
   // LDS-direct copies issued per wave for one iteration
-  static constexpr int NLOADS = BM / 32 + BN / 32;
-  static_assert(WGM * WGN == 4 && FM >= 1 && FN >= 1, "wave grid");
+  static constexpr int NLOADS = (BM + BN) / (NT / 8);
+  static_assert(WGM * WGN == NW && FM >= 1 && FN >= 1, "wave grid");
   static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile");
-  using StageA = typename StageSel<LA == L_ROW, BM, EB>::type;
-  using StageB = typename StageSel<LB == L_COL, BN, EB>::type;
+  using StageA = typename StageSel<LA == L_ROW, BM, EB, NT>::type;
+  using StageB = typename StageSel<LB == L_COL, BN, EB, NT>::type;
 };
 
 template <typename C>
@@ -847,9 +847,20 @@ __device__ __forceinline__ void epilogue(const Acc<C>& acc, const ProbDesc& pd, 
 // registers in every workgroup, so the slot is laid out
 // [block (i,j)][register quad][thread] x float4: each store or load
 // instruction of a wave touches 1 KiB of contiguous memory.
+//
+// Partial tiles move at device scope (the sc1 cache-policy bit): such
+// stores are acknowledged only once they are visible to every XCD, and such
+// loads never return a stale line of the reader's own L2.  Publishing and
+// consuming a partial therefore needs no cache-wide operation; an
+// agent-scope fence would instead write back and invalidate the L2 of the
+// workgroup's XCD, dropping the A/B panels that the other workgroups there
+// are streaming.
+constexpr int kCpolDevice = 16;   // sc1
+
 template <typename C>
 __device__ __forceinline__ void store_partial(const Acc<C>& acc, float* slot, int tid) {
   asm volatile("" : "+v"(tid));   // addresses are formed here, not hoisted
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc((const char*)slot, (int64_t)C::BM * C::BN * 4);
 #pragma unroll
   for (int i = 0; i < C::FM; ++i)
 #pragma unroll
@@ -858,7 +869,9 @@ __device__ __forceinline__ void store_partial(const Acc<C>& acc, float* slot, in
       for (int q = 0; q < 4; ++q) {
         v4f v = {acc.a[i][j][4 * q], acc.a[i][j][4 * q + 1], acc.a[i][j][4 * q + 2],
                  acc.a[i][j][4 * q + 3]};
-        ((v4f*)((char*)slot + ((i * C::FN + j) * 4 + q) * NT * 16))[tid] = v;
+        const int off = (((i * C::FN + j) * 4 + q) * C::NT + tid) * 16;
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rs, off, 0,
+                                               kCpolDevice);
         __builtin_amdgcn_sched_barrier(0);
       }
 }
@@ -866,13 +879,16 @@ __device__ __forceinline__ void store_partial(const Acc<C>& acc, float* slot, in
 template <typename C>
 __device__ __forceinline__ void add_partial(Acc<C>& acc, const float* slot, int tid) {
   asm volatile("" : "+v"(tid));   // addresses are formed here, not hoisted
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc((const char*)slot, (int64_t)C::BM * C::BN * 4);
 #pragma unroll
   for (int i = 0; i < C::FM; ++i)
 #pragma unroll
     for (int j = 0; j < C::FN; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        v4f v = ((const v4f*)((const char*)slot + ((i * C::FN + j) * 4 + q) * NT * 16))[tid];
+        const int off = (((i * C::FN + j) * 4 + q) * C::NT + tid) * 16;
+        const v4f v = __builtin_bit_cast(
+            v4f, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kCpolDevice));
         acc.a[i][j][4 * q] += v[0];
         acc.a[i][j][4 * q + 1] += v[1];
         acc.a[i][j][4 * q + 2] += v[2];
@@ -950,11 +966,10 @@ __device__ __forceinline__ void trace_segment(const KParams& P, int64_t x, const
 }
 
 // Fixup wait: one wavefront (lane 0 of wave 0) polls the tile's arrival
-// counter with agent-scope loads and backs off with s_sleep; after the
-// counter reaches `target` it performs an agent-scope acquire, and the
-// workgroup barrier orders every other wave's reads of the partial slots
-// after it.  The poll is bounded: past spin_limit it raises the error word
-// instead of hanging.
+// counter with device-scope loads and backs off with s_sleep; the workgroup
+// barrier then orders every wave's (device-scope) reads of the partial
+// slots after the poll that saw all contributions.  The poll is bounded:
+// past spin_limit it raises the error word instead of hanging.
 __device__ __forceinline__ void wait_arrivals(const KParams& P, int32_t* flag, int32_t target) {
   if (threadIdx.x == 0) {
     int64_t n = 0;
@@ -965,17 +980,17 @@ __device__ __forceinline__ void wait_arrivals(const KParams& P, int32_t* flag, i
         break;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }
 
-// Publish a partial tile: every thread's stores are released at agent scope
-// before the workgroup barrier; then one thread bumps the arrival counter.
+// Publish a partial tile: each thread waits until its device-scope stores
+// are acknowledged (visible on every XCD), the workgroup barrier collects
+// all threads, then one thread bumps the arrival counter.
 __device__ __forceinline__ void signal_arrival(int32_t* flag) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  wait_vmcnt<0>();
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // One work item of a workgroup: a Stream-K segment or a data-parallel tile.
@@ -985,7 +1000,7 @@ struct Item {
 };
 
 template <typename C>
-__global__ __launch_bounds__(NT, 1) void sk_gemm_kernel(KParams P) {
+__global__ __launch_bounds__(C::NT, 1) void sk_gemm_kernel(KParams P) {
   __shared__ __attribute__((aligned(16))) char lds[C::NSTAGE * C::STAGE];
   const int tid = threadIdx.x;
   const int64_t b = blockIdx.x;

@@ -6,6 +6,7 @@ namespace sk {
 
 struct KernelEntry {
   int dt, la, lb, bm, bn, wgm;
+  int nt;           // threads per workgroup
   const void* fn;   // host handle of the __global__ function
 };
 

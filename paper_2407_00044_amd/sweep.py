@@ -3,12 +3,18 @@
 64 shapes with M, N log-uniform in [128, 8192] and K log-uniform in
 [128, 16384] (seeded); A row-major, B column-major with leading dimensions
 rounded up to 16 bytes, N(0,1) entries, FP32 C_in uniform in [-1, 1],
-alpha = 1, beta = 0.5.  For each shape both schedules use the same tile;
+alpha = 1, beta = 0.5.  Times are GPU times: `reps` launches are captured in
+one HIP graph and replayed, so host-side call overhead (which exceeds the
+kernel time of the smallest shapes) is not counted.  For each shape both
+schedules use the same tile;
 the report lists TFLOP/s = 2*M*N*K / t per shape, the min and geometric mean
 of each schedule, the predicted quantization loss of one-tile-per-workgroup
 tiling 1 - T / (ceil(T/g) * g) and the measured ratio t_DP / t_SK.
 
-    python -m paper_2407_00044_amd.sweep [--n 64] [--reps 10] [--tune]
+    python -m paper_2407_00044_amd.sweep [--n 64] [--reps 10] [--tune] [--all-tiles]
+
+--all-tiles also times every f16/bf16 tile of the menu under both schedules
+(per-shape "tiles" entries), the data behind the default-tile rule.
 """
 import argparse
 import json
@@ -21,28 +27,39 @@ import torch
 from . import api, synth, tune
 
 
-def _time(fn, reps, warm=2):
-    for _ in range(warm):
-        fn()
+def _time(fn, reps, replays=3):
+    """Milliseconds per call of fn, from replays of a graph of `reps` calls."""
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fn()
+    g.replay()
     torch.cuda.synchronize()
     s = torch.cuda.Event(enable_timing=True)
     e = torch.cuda.Event(enable_timing=True)
     s.record()
-    for _ in range(reps):
-        fn()
+    for _ in range(replays):
+        g.replay()
     e.record()
     torch.cuda.synchronize()
-    return s.elapsed_time(e) / reps
+    return s.elapsed_time(e) / (reps * replays)
 
 
 def gmean(xs):
     return math.exp(sum(math.log(x) for x in xs) / len(xs))
 
 
-def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout):
+ALL_TILES = [(256, 256), (256, 128), (128, 128)]
+
+
+def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False):
     dev = torch.device("cuda", torch.cuda.current_device())
     cus, _ = api.device_query(api.Config(tile=(256, 128)), torch.bfloat16)
     rows = []
+    ws = api.Workspace(dev)
+    ws.get(96 << 20, torch.cuda.current_stream().cuda_stream)   # before any capture
     for idx, (M, N, K) in enumerate(synth.sweep_shapes(seed, n)):
         gen = torch.Generator(device=dev)
         gen.manual_seed(300 + idx)
@@ -57,7 +74,7 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout):
         cfg_dp = api.Config(tile=tile, mode="dp")
 
         def go(cfg):
-            return lambda: api.gemm(A, B, C, beta=0.5, out=outC, config=cfg)
+            return lambda: api.gemm(A, B, C, beta=0.5, out=outC, config=cfg, workspace=ws)
         t_sk = _time(go(cfg_sk), reps)
         t_dp = _time(go(cfg_dp), reps)
         p = api.plan([(M, N, K)], torch.bfloat16, cfg_sk)
@@ -67,6 +84,13 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout):
         row = {"M": M, "N": N, "K": K, "tile": list(tile), "T": T, "S": p["S"],
                "sk_tflops": flops / t_sk / 1e9, "dp_tflops": flops / t_dp / 1e9,
                "dp_quant_eff": q_eff, "t_dp_over_t_sk": t_dp / t_sk}
+        if all_tiles:
+            row["tiles"] = {}
+            for t in ALL_TILES:
+                key = f"{t[0]}x{t[1]}"
+                row["tiles"][key] = {
+                    "sk": flops / _time(go(api.Config(tile=t, mode="hybrid")), reps) / 1e9,
+                    "dp": flops / _time(go(api.Config(tile=t, mode="dp")), reps) / 1e9}
         if use_tuner:
             best = tune.tune_gemm(A, B, torch.float32, reps=max(3, reps // 2))
             t_best = _time(go(best), reps)
@@ -97,9 +121,10 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--tune", action="store_true")
+    ap.add_argument("--all-tiles", action="store_true")
     a = ap.parse_args()
     t0 = time.time()
-    run(a.n, a.reps, a.tune)
+    run(a.n, a.reps, a.tune, all_tiles=a.all_tiles)
     print(f"# sweep done in {time.time() - t0:.1f} s", file=sys.stderr)
 
 

@@ -48,13 +48,19 @@ def _status(fn):
 def test_plan_closed_forms():
     p = _plan(3840, 4096, 4096, dtype=torch.float16, tile=(256, 128), num_cu=256)
     assert (p["T"], p["S"], p["W"], p["q"], p["rho"]) == (480, 480, 30720, 120, 0)
-    p = _plan(512, 512, 512, dtype=torch.float32, tile=(128, 128), mode="sk", num_cu=256)
+    p = _plan(512, 512, 512, dtype=torch.float32, tile=(128, 128), mode="sk", num_cu=256,
+              min_iters=1)
     assert (p["T"], p["W"], p["q"]) == (16, 256, 1)
     assert p["workspace_bytes"] == 256 + 256 + 256 * 128 * 128 * 4
     p = _plan(384, 384, 128, dtype=torch.float32, tile=(128, 128), mode="dp", num_cu=4)
     assert (p["T"], p["S"], p["g"], p["workspace_bytes"]) == (9, 0, 9, 0)
     p = _plan(8192, 4096, 11008, tile=(256, 128), num_cu=256)   # T mod g == 0: pure DP
     assert (p["T"], p["S"]) == (1024, 0)
+    # automatic grid floor: 6 tiles x 50 iterations -> m = 10, 30 workgroups
+    p = _plan(607, 187, 3155, tile=(256, 128), num_cu=256)
+    assert (p["T"], p["g"], p["q"], p["rho"]) == (6, 30, 10, 0)
+    p = _plan(607, 187, 3155, tile=(256, 128), num_cu=256, min_iters=1)
+    assert (p["g"], p["q"], p["rho"]) == (256, 1, 44)
 
 
 def test_k_zero_keeps_one_iteration():

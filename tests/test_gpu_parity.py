@@ -39,7 +39,7 @@ def check(M, N, K, dtype, a_col, b_col, cfg, seed=1, dist="uniform", **kw):
 
 def test_c1_fp32_512_cube_all_stream_k():
     # FP32 512^3, 128x128x32 tiles, 256 workgroups: 16 tiles x 16 contributors
-    cfg = sk.Config(tile=(128, 128), mode="sk", num_cu=256)
+    cfg = sk.Config(tile=(128, 128), mode="sk", num_cu=256, min_iters=1)
     A, B = make_inputs(512, 512, 512, "f32", False, False, seed=1)
     C = run(A, B, cfg)
     err = rel_err(as64(C), oracle(A, B, 512, 512, 512))
@@ -116,7 +116,7 @@ def test_every_workgroup_count():
     ref = oracle(A, B, 480, 512, 512)
     for g in list(range(1, 33)) + [60, 64, 100, 119, 120, 121, 128, 200, 255, 256]:
         for tile in [(128, 128), (256, 128)]:
-            C = run(A, B, sk.Config(tile=tile, mode="sk", num_cu=g))
+            C = run(A, B, sk.Config(tile=tile, mode="sk", num_cu=g, min_iters=1))
             assert rel_err(as64(C), ref) <= 1e-4, (g, tile)
 
 

@@ -19,26 +19,32 @@ pytestmark = gpu
 MODES = {"sk": sch.MODE_SK, "hybrid": sch.MODE_HYBRID, "dp": sch.MODE_DP}
 BK = {"f32": 32, "f16": 64, "bf16": 64, "e4m3": 128}
 
+# (M, N, K, dtype, tile, mode, g, min_iters): min_iters = 1 keeps all g
+# workgroups (many contributors per tile); 0 applies the automatic floor
 CASES = [
-    (512, 512, 512, "f32", (128, 128), "sk", 256),
-    (384, 384, 128, "f32", (128, 128), "sk", 4),
-    (384, 384, 128, "f32", (128, 128), "hybrid", 4),
-    (1000, 700, 900, "bf16", (256, 128), "hybrid", 13),
-    (1000, 700, 900, "bf16", (128, 128), "sk", 256),
-    (480, 512, 512, "f16", (256, 128), "sk", 120),
-    (700, 300, 2000, "e4m3", (64, 128), "hybrid", 64),
-    (640, 640, 300, "bf16", (128, 128), "dp", 0),
+    (512, 512, 512, "f32", (128, 128), "sk", 256, 1),
+    (384, 384, 128, "f32", (128, 128), "sk", 4, 1),
+    (384, 384, 128, "f32", (128, 128), "hybrid", 4, 1),
+    (1000, 700, 900, "bf16", (256, 128), "hybrid", 13, 1),
+    (1000, 700, 900, "bf16", (128, 128), "sk", 256, 1),
+    (480, 512, 512, "f16", (256, 128), "sk", 120, 1),
+    (700, 300, 2000, "e4m3", (64, 128), "hybrid", 64, 1),
+    (640, 640, 300, "bf16", (128, 128), "dp", 0, 1),
+    (607, 187, 3155, "bf16", (256, 128), "hybrid", 256, 0),
+    (235, 2337, 528, "bf16", (128, 128), "sk", 256, 0),
+    (1000, 700, 900, "f16", (128, 128), "hybrid", 256, 7),
 ]
 
 
-@pytest.mark.parametrize("M,N,K,dtype,tile,mode,g", CASES)
-def test_device_trace_matches_simulator(M, N, K, dtype, tile, mode, g):
-    print(f"case {M}x{N}x{K} {dtype} {tile} {mode} g={g}", flush=True)
+@pytest.mark.parametrize("M,N,K,dtype,tile,mode,g,mi", CASES)
+def test_device_trace_matches_simulator(M, N, K, dtype, tile, mode, g, mi):
+    print(f"case {M}x{N}x{K} {dtype} {tile} {mode} g={g} min_iters={mi}", flush=True)
     A, B = make_inputs(M, N, K, dtype, False, True, seed=3)
-    cfg = sk.Config(tile=tile, mode=mode, num_cu=g)
+    cfg = sk.Config(tile=tile, mode=mode, num_cu=g, min_iters=mi)
     out, segs, cover = sk.gemm_debug(A.view, B.view, config=cfg, scale_a=A.scale,
                                      scale_b=B.scale)
-    _, sim = sch.simulate([(M, N, K)], tile[0], tile[1], BK[dtype], g, MODES[mode])
+    _, sim = sch.simulate([(M, N, K)], tile[0], tile[1], BK[dtype], g, MODES[mode],
+                          min_iters=mi)
     assert segs == [s.as_tuple() for s in sim]
     plan = sk.plan([(M, N, K)], out.dtype if dtype == "f32" else A.view.dtype, cfg)
     T, I = plan["T"], plan["max_iters"]
@@ -49,7 +55,7 @@ def test_device_trace_matches_simulator(M, N, K, dtype, tile, mode, g):
 def test_repeats_delays_and_reversed_ids_are_bitwise_identical():
     M, N, K = 512, 512, 512
     A, B = make_inputs(M, N, K, "f32", False, False, seed=1)
-    cfg = sk.Config(tile=(128, 128), mode="sk", num_cu=256)
+    cfg = sk.Config(tile=(128, 128), mode="sk", num_cu=256, min_iters=1)
     first = run(A, B, cfg)
     for _ in range(20):
         assert torch.equal(run(A, B, cfg), first)
@@ -63,7 +69,7 @@ def test_bf16_many_contributors_bitwise_repeatable():
     # K long relative to the tile count: every tile split across many WGs
     M, N, K = 256, 512, 16384
     A, B = make_inputs(M, N, K, "bf16", False, True, seed=8)
-    cfg = sk.Config(tile=(256, 128), mode="sk", num_cu=256)
+    cfg = sk.Config(tile=(256, 128), mode="sk", num_cu=256, min_iters=1)
     first = run(A, B, cfg)
     assert rel_err(as64(first), oracle(A, B, M, N, K)) <= 1e-4
     for _ in range(10):
@@ -79,7 +85,7 @@ def test_spin_limit_reports_timeout_without_hanging():
     from paper_2407_00044_amd import _abi
     M, N, K = 512, 512, 512
     A, B = make_inputs(M, N, K, "f32", False, False, seed=1)
-    cfg = sk.Config(tile=(128, 128), mode="sk", num_cu=256, spin_limit=1)
+    cfg = sk.Config(tile=(128, 128), mode="sk", num_cu=256, spin_limit=1, min_iters=1)
     with pytest.raises(_abi.StreamKError) as e:
         sk.gemm_debug(A.view, B.view, config=cfg, partial_delay=20000)
     assert e.value.status == _abi.SK_ERR_DEVICE_TIMEOUT

@@ -78,6 +78,46 @@ def test_hybrid_split_rule():
     assert plan.S == 0
 
 
+def test_grid_floor_hand_values():
+    # 607x187x3155 on 256x128x64 tiles: 3x2 = 6 tiles of ceil(3155/64) = 50
+    # iterations, W_all = 300; automatic m = ceil(sqrt(2*50)) = 10, so the
+    # grid shrinks from 256 to 300 // 10 = 30 workgroups of 10 iterations.
+    plan = sch.make_plan([(607, 187, 3155)], 256, 128, 64, 256, sch.MODE_HYBRID, min_iters=0)
+    assert (plan.T, plan.g, plan.S, plan.W, plan.q, plan.rho) == (6, 30, 6, 300, 10, 0)
+    # m = 1 keeps the grid: 300 iterations over 256 workgroups
+    plan = sch.make_plan([(607, 187, 3155)], 256, 128, 64, 256, sch.MODE_HYBRID, min_iters=1)
+    assert (plan.g, plan.q, plan.rho) == (256, 1, 44)
+    # the headline shape on 256x256 tiles is large enough: m = ceil(sqrt(128))
+    # = 12, 15360 // 12 = 1280 > 256
+    plan = sch.make_plan([(3840, 4096, 4096)], 256, 256, 64, 256, sch.MODE_SK, min_iters=0)
+    assert (plan.T, plan.g, plan.W, plan.q) == (240, 256, 15360, 60)
+    # explicit m; a floor above W_all leaves one workgroup; DP mode ignores it
+    plan = sch.make_plan([(512, 512, 512)], 128, 128, 32, 256, sch.MODE_SK, min_iters=40)
+    assert (plan.g, plan.q, plan.rho) == (6, 42, 4)      # 256 iterations // 40
+    plan = sch.make_plan([(100, 100, 100)], 128, 128, 32, 256, sch.MODE_SK, min_iters=9)
+    assert (plan.g, plan.q) == (1, 4)
+    plan = sch.make_plan([(512, 512, 512)], 128, 128, 32, 256, sch.MODE_DP, min_iters=40)
+    assert plan.g == 16
+    # the floor feeds the hybrid rule: 20 tiles x 8 iterations, m = 4 ->
+    # g' = 40; 20 mod 40 = 20 -> S = min(20, 60) = 20
+    plan = sch.make_plan([(20, 1, 8)], 1, 1, 1, 256, sch.MODE_HYBRID, min_iters=0)
+    assert (plan.g, plan.S, plan.q) == (40, 20, 4)
+    assert [sch.isqrt_ceil(n) for n in (0, 1, 2, 4, 5, 100, 101, 128)] == [0, 1, 2, 2, 3, 10, 11, 12]
+
+
+def test_grid_floor_invariants():
+    for shape, (bm, bn, bk), g in _cases(77, 300):
+        for mode in (sch.MODE_SK, sch.MODE_HYBRID):
+            for m in (0, 3, 50):
+                plan, segs = sch.simulate([shape], bm, bn, bk, g, mode, -1, 0, m)
+                assert 1 <= plan.g <= g
+                sch.check([shape], bm, bn, bk, plan.g, mode, segs)
+                if plan.T and plan.W:
+                    # no workgroup below the floor unless the grid is one WG
+                    mm = m or sch.isqrt_ceil(2 * -(-sum(plan.iters) // plan.T))
+                    assert plan.g == g or plan.g == 1 or sum(plan.iters) // plan.g >= mm
+
+
 def test_group_m_tile_order_is_a_bijection():
     for tm, tn, gm in [(5, 3, 2), (7, 4, 3), (8, 8, 4), (1, 9, 4), (6, 1, 8)]:
         coords = [sch.tile_coords(u, tm, tn, gm) for u in range(tm * tn)]

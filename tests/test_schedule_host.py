@@ -13,12 +13,14 @@ MODES = {"sk": sch.MODE_SK, "hybrid": sch.MODE_HYBRID, "dp": sch.MODE_DP}
 BK = {torch.float32: 32, torch.float16: 64, torch.bfloat16: 64, torch.float8_e4m3fn: 128}
 
 
-def compare(shapes, dtype, tile, g, mode, dp_tiles=-1, group_m=0):
-    cfg = sk.Config(tile=tile, mode=mode, num_cu=g, dp_tiles=dp_tiles, group_m=group_m)
+def compare(shapes, dtype, tile, g, mode, dp_tiles=-1, group_m=0, min_iters=0):
+    cfg = sk.Config(tile=tile, mode=mode, num_cu=g, dp_tiles=dp_tiles, group_m=group_m,
+                    min_iters=min_iters)
     lib_segs = sk.schedule(shapes, dtype, cfg)
-    _, sim = sch.simulate(shapes, tile[0], tile[1], BK[dtype], g, MODES[mode], dp_tiles,
-                          group_m)
+    plan, sim = sch.simulate(shapes, tile[0], tile[1], BK[dtype], g, MODES[mode], dp_tiles,
+                             group_m, min_iters)
     assert lib_segs == [s.as_tuple() for s in sim]
+    assert sk.plan(shapes, dtype, cfg)["g"] == plan.g
 
 
 @pytest.mark.parametrize("mode", ["sk", "hybrid", "dp"])
@@ -33,7 +35,7 @@ def test_random_small_shapes(mode):
         g = r.choice([1, 2, 3, 7, 8, 16, 64, 120, 255, 256])
         dp = r.choice([-1, -1, 0, 3]) if mode != "dp" else -1
         gm = r.choice([0, 0, 2, 5])
-        compare([shape], dt, r.choice(tiles[dt]), g, mode, dp, gm)
+        compare([shape], dt, r.choice(tiles[dt]), g, mode, dp, gm, r.choice([0, 0, 1, 3, 40]))
 
 
 def test_paper_configurations():
