@@ -779,6 +779,7 @@ template <typename C, int DTC>
 __device__ __forceinline__ void epilogue_t(const Acc<C>& acc, const ProbDesc& pd, int64_t m0,
                                            int64_t n0, int tid) {
   constexpr int ES = DTC == DT_F32 ? 4 : 2;           // output element size
+  constexpr int NB = C::FM * C::FN;                   // 32x32 blocks per wave
   const int wave = uniform32(tid >> 6);
   int lane = tid & 63;
   // Keep the per-lane offsets below inside the epilogue (otherwise they are
@@ -797,38 +798,49 @@ __device__ __forceinline__ void epilogue_t(const Acc<C>& acc, const ProbDesc& pd
       make_rsrc((const char*)(use_cin ? pd.Cin : pd.Cout) + tile_off, extent);
   const uint32_t ldc_b = (uint32_t)(pd.ldc * ES);
   const uint32_t lane_off = (uint32_t)wr * ldc_b + (uint32_t)(wc * ES);
+  // byte offset of register r of block b (kOOB outside the matrix)
+  auto elem_off = [&](int b, int r) -> int {
+    const int i = b / C::FN, j = b % C::FN;
+    const int dr = i * 32 + 8 * (r >> 2) + (r & 3);   // row offset from wr
+    const bool ok = wr + dr < rl && wc + j * 32 < cl;
+    return (int)(ok ? lane_off + ((uint32_t)dr * ldc_b + (uint32_t)(j * 32 * ES)) : kOOB);
+  };
+  auto load_cin = [&](int b, float (&dst)[16]) {
 #pragma unroll
-  for (int i = 0; i < C::FM; ++i) {
-#pragma unroll
-    for (int j = 0; j < C::FN; ++j) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int dr = i * 32 + 8 * (r >> 2) + (r & 3);   // row offset from wr
-        const bool ok = wr + dr < rl && wc + j * 32 < cl;
-        const int off =
-            (int)(ok ? lane_off + ((uint32_t)dr * ldc_b + (uint32_t)(j * 32 * ES)) : kOOB);
-        float v = alpha * acc.a[i][j][r];
-        if (use_cin) {
-          float cin;
-          if constexpr (DTC == DT_F32)
-            cin = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(in, off, 0, 0));
-          else if constexpr (DTC == DT_F16)
-            cin = (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(in, off, 0, 0));
-          else
-            cin = __builtin_bit_cast(float, (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(in, off, 0, 0) << 16);
-          v = __builtin_fmaf(alpha, acc.a[i][j][r], beta * cin);
-        }
-        if constexpr (DTC == DT_F32)
-          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), out, off, 0, 0);
-        else if constexpr (DTC == DT_F16)
-          __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (_Float16)v), out, off, 0, 0);
-        else
-          __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16_rne(v), out, off, 0, 0);
-      }
-      // one 32x32 block at a time: keeps the scheduler from gathering all
-      // loads/stores of the tile and the registers they would need
-      __builtin_amdgcn_sched_barrier(0);
+    for (int r = 0; r < 16; ++r) {
+      const int off = elem_off(b, r);
+      if constexpr (DTC == DT_F32)
+        dst[r] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(in, off, 0, 0));
+      else if constexpr (DTC == DT_F16)
+        dst[r] = (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(in, off, 0, 0));
+      else
+        dst[r] = __builtin_bit_cast(float, (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(in, off, 0, 0) << 16);
     }
+  };
+  // C_in of block b+1 is loaded while block b is finished, so only the first
+  // block's load latency is exposed.
+  float cin[2][16];
+  if (use_cin) load_cin(0, cin[0]);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    if (use_cin && b + 1 < NB) load_cin(b + 1, cin[(b + 1) & 1]);
+    __builtin_amdgcn_sched_barrier(0);
+    const int i = b / C::FN, j = b % C::FN;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int off = elem_off(b, r);
+      const float v = use_cin ? __builtin_fmaf(alpha, acc.a[i][j][r], beta * cin[b & 1][r])
+                              : alpha * acc.a[i][j][r];
+      if constexpr (DTC == DT_F32)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), out, off, 0, 0);
+      else if constexpr (DTC == DT_F16)
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (_Float16)v), out, off, 0, 0);
+      else
+        __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16_rne(v), out, off, 0, 0);
+    }
+    // one block at a time: keeps the scheduler from gathering all loads and
+    // stores of the tile and the registers they would need
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -878,23 +890,31 @@ __device__ __forceinline__ void store_partial(const Acc<C>& acc, float* slot, in
 
 template <typename C>
 __device__ __forceinline__ void add_partial(Acc<C>& acc, const float* slot, int tid) {
+  constexpr int NB = C::FM * C::FN;
   asm volatile("" : "+v"(tid));   // addresses are formed here, not hoisted
   const __amdgpu_buffer_rsrc_t rs = make_rsrc((const char*)slot, (int64_t)C::BM * C::BN * 4);
+  auto load_blk = [&](int b, u32x4 (&dst)[4]) {
 #pragma unroll
-  for (int i = 0; i < C::FM; ++i)
+    for (int q = 0; q < 4; ++q)
+      dst[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, ((b * 4 + q) * C::NT + tid) * 16, 0,
+                                                     kCpolDevice);
+  };
+  // block b+1 is in flight while block b is added
+  u32x4 buf[2][4];
+  load_blk(0, buf[0]);
 #pragma unroll
-    for (int j = 0; j < C::FN; ++j)
+  for (int b = 0; b < NB; ++b) {
+    if (b + 1 < NB) load_blk(b + 1, buf[(b + 1) & 1]);
+    __builtin_amdgcn_sched_barrier(0);
+    const int i = b / C::FN, j = b % C::FN;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int off = (((i * C::FN + j) * 4 + q) * C::NT + tid) * 16;
-        const v4f v = __builtin_bit_cast(
-            v4f, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kCpolDevice));
-        acc.a[i][j][4 * q] += v[0];
-        acc.a[i][j][4 * q + 1] += v[1];
-        acc.a[i][j][4 * q + 2] += v[2];
-        acc.a[i][j][4 * q + 3] += v[3];
-        __builtin_amdgcn_sched_barrier(0);
-      }
+    for (int q = 0; q < 4; ++q) {
+      const v4f v = __builtin_bit_cast(v4f, buf[b & 1][q]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc.a[i][j][4 * q + e] += v[e];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 // ---------------------------------------------------------------------------
