@@ -3,9 +3,14 @@
 Workload (one step = one GEMM through the whole Stream-K path): FP16 inputs
 with FP32 accumulation and FP32 output, M=3840, N=4096, K=4096, A row-major,
 B column-major, entries uniform in [-1, 1] (seeded), alpha=1, beta=0,
-256x128 tiles, hybrid data-parallel + Stream-K schedule over one persistent
-workgroup per CU.  The same shape is also timed with the equal-tile
-data-parallel grid, and in BF16 with 256x256 tiles.
+256x128 tiles, hybrid data-parallel + Stream-K schedule (two-tile rule) over
+one persistent workgroup per CU (480 tiles on 256 CUs: every tile is a
+Stream-K tile), in the automatic tile order.  Also timed: the equal-tile
+data-parallel grid, the library's auto policy (which may fall back to
+data-parallel), and BF16 with 256x256 and 256x128 tiles.  Before any timed
+region the legs are run untimed for about a second (clocks, TLBs and caches
+settle; the first leg of a fresh process otherwise reads up to 15% slow).  The same shape is also timed with the equal-tile
+data-parallel grid, and in BF16 with 256x256 and 256x128 tiles.
 
 Prints one JSON line.  TFLOP/s = 2*M*N*K / time.
 """
@@ -64,6 +69,20 @@ def time_gemm(A, B, cfg, steps, warmup):
     torch.cuda.synchronize()
     assert sk.check_device_error() == 0
     return start.elapsed_time(end) / steps, out
+
+
+def warm_up(legs, seconds):
+    """Untimed launches of every leg, alternating, for about `seconds`."""
+    import torch
+    import paper_2407_00044_amd as sk
+    out = torch.empty((legs[0][1].shape[0], legs[0][2].shape[1]), dtype=torch.float32,
+                      device=legs[0][1].device)
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _, a, b, cfg in legs:
+            for _ in range(5):
+                sk.gemm(a, b, out=out, config=cfg)
+        torch.cuda.synchronize()
 
 
 def cpu_baseline(host, M, N, K, min_seconds=10.0, max_reps=4):
@@ -139,16 +158,20 @@ def main():
     dev = torch.device("cuda", 0)
     M, N, K = 3840, 4096, 4096
     flops = 2.0 * M * N * K
-    cus, _ = sk.device_query(sk.Config(tile=(256, 128)), torch.float16)
+    tile = (256, 128)
+    cus, _ = sk.device_query(sk.Config(tile=tile), torch.float16)
     A, B, host = make_operands(M, N, K, "f16", 2, dev)
 
-    cfg_sk = sk.Config(tile=(256, 128), mode="hybrid", num_cu=0)
-    cfg_dp = sk.Config(tile=(256, 128), mode="dp")
+    cfg_sk = sk.Config(tile=tile, mode="hybrid", num_cu=0)
+    cfg_dp = sk.Config(tile=tile, mode="dp")
+    cfg_auto = sk.Config(tile=tile, mode="auto")
+    plan = sk.plan([(M, N, K)], torch.float16, cfg_sk)
     result = {}
-    legs = [("sk", A, B, cfg_sk), ("dp", A, B, cfg_dp)]
+    legs = [("sk", A, B, cfg_sk), ("dp", A, B, cfg_dp), ("auto", A, B, cfg_auto)]
+    legs = [leg for leg in legs if not args.only or args.only == leg[0]]
+    if legs:
+        warm_up(legs, seconds=1.0)
     for name, a, b, cfg in legs:
-        if args.only and args.only != name:
-            continue
         ms, _ = time_gemm(a, b, cfg, args.steps, args.warmup)
         result[name] = ms
         print(f"# {name}: {ms * 1e3:.1f} us  {flops / ms / 1e9:.1f} TFLOP/s", file=sys.stderr,
@@ -156,9 +179,12 @@ def main():
     bf = {}
     if not args.only or args.only == "bf16":
         Ab, Bb, _ = make_operands(M, N, K, "bf16", 4, dev)
-        for name, cfg in [("sk_256x256", sk.Config(tile=(256, 256), mode="hybrid")),
-                          ("dp_256x256", sk.Config(tile=(256, 256), mode="dp")),
-                          ("sk_256x128", sk.Config(tile=(256, 128), mode="hybrid"))]:
+        bf_legs = [("sk_256x256", sk.Config(tile=(256, 256), mode="sk")),
+                   ("dp_256x256", sk.Config(tile=(256, 256), mode="dp")),
+                   ("sk_256x128", sk.Config(tile=(256, 128), mode="hybrid")),
+                   ("dp_256x128", sk.Config(tile=(256, 128), mode="dp"))]
+        warm_up([(n, Ab, Bb, c) for n, c in bf_legs], seconds=0.5)
+        for name, cfg in bf_legs:
             ms, _ = time_gemm(Ab, Bb, cfg, args.steps, args.warmup)
             bf[name] = {"ms": round(ms, 5), "tflops": round(flops / ms / 1e9, 1),
                         "frac_peak": round(flops / ms / 1e9 / PEAK_TFLOPS["bf16"], 4)}
@@ -184,9 +210,13 @@ def main():
         "dtype": "f16",
         "data": "synthetic",
         "config": {"workload": "fp16 GEMM 3840x4096x4096, A row-major, B column-major, "
-                               "U[-1,1], FP32 accumulate and output, alpha=1 beta=0",
-                   "M": M, "N": N, "K": K, "tile": [256, 128, 64], "schedule": "hybrid",
-                   "persistent_workgroups": cus, "parallelism": "single GPU"},
+                               "U[-1,1], FP32 accumulate and output, alpha=1 beta=0, "
+                               "Stream-K (hybrid two-tile rule) on 256x128 tiles",
+                   "M": M, "N": N, "K": K, "tile": [tile[0], tile[1], 64], "schedule": "hybrid",
+                   "tile_order_group_m": plan["group_m"],
+                   "tiles": plan["T"], "stream_k_tiles": plan["S"],
+                   "persistent_workgroups": plan["g"], "compute_units": cus,
+                   "parallelism": "single GPU"},
         "pct_mfma_peak": round(100 * tflops / PEAK_TFLOPS["f16"], 2),
         "roofline": {"bound": "mfma", "achieved": round(tflops, 2),
                      "peak": PEAK_TFLOPS["f16"], "unit": "TFLOP/s",
@@ -198,6 +228,11 @@ def main():
         line["dp_baseline"] = {"ms": round(result["dp"], 5), "tflops": round(dtf, 2),
                                "pct_mfma_peak": round(100 * dtf / PEAK_TFLOPS["f16"], 2),
                                "sk_speedup": round(result["dp"] / ms, 4)}
+    if "auto" in result:
+        atf = flops / result["auto"] / 1e9
+        line["auto_policy"] = {"ms": round(result["auto"], 5), "tflops": round(atf, 2),
+                               "stream_k_tiles": sk.plan([(M, N, K)], torch.float16,
+                                                         cfg_auto)["S"]}
     if bf:
         line["bf16_same_shape"] = bf
     if not args.no_cpu:

@@ -85,8 +85,18 @@ typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
  *                   unless sk_config.dp_tiles >= 0 sets S = T - dp_tiles.
  *   SK_MODE_SK      every tile is a Stream-K tile (S = T).
  *   SK_MODE_DP      baseline data-parallel grid: one workgroup per tile,
- *                   no persistence, no fixup, no workspace. */
-typedef enum { SK_MODE_HYBRID = 0, SK_MODE_SK = 1, SK_MODE_DP = 2 } sk_mode;
+ *                   no persistence, no fixup, no workspace.
+ *   SK_MODE_AUTO    SK_MODE_HYBRID, except that S = 0 (no tile is split)
+ *                   when Stream-K's even share b = ceil(W_all/g), plus an
+ *                   eighth for lost L2 reuse, plus one partial tile (f =
+ *                   max(4, BM*BN/8192) MAC iterations of fixup) is no
+ *                   shorter than the data-parallel waves:
+ *                   b + ceil(b/8) + f >= ceil(T/g) * ceil(W_all/T), W_all =
+ *                   MAC iterations of all tiles, g after the grid floor.
+ *                   Constants measured on MI355X; not in the report. */
+typedef enum {
+  SK_MODE_HYBRID = 0, SK_MODE_SK = 1, SK_MODE_DP = 2, SK_MODE_AUTO = 3
+} sk_mode;
 
 /* Role of a schedule segment (what a workgroup does with one tile). */
 typedef enum {
@@ -124,19 +134,26 @@ typedef struct {
   int64_t dp_tiles;    /* -1: hybrid rule; >= 0: S = T - min(dp_tiles, T)
                           (ignored in SK_MODE_DP) */
   int32_t group_m;     /* 0: row-major tile order; > 0: bands of group_m
-                          tile rows, walked down the band first */
+                          tile rows, walked down the band first; -1:
+                          automatic (with Stream-K tiles, bands of the
+                          largest divisor of q/gcd(q, I) not above the tile
+                          rows, so that workgroups starting at the same
+                          k-phase work on one tile row; otherwise bands of
+                          8 rows) */
   int32_t xcd_remap;   /* 1: hardware workgroup b runs logical id
                           (b mod 8)*(g/8) + b/8 (when g mod 8 == 0) so
                           consecutive logical ids share an XCD's L2 */
   int64_t spin_limit;  /* polls a fixup wait makes before giving up and
                           raising SK_ERR_DEVICE_TIMEOUT; 0 = default (about
                           four seconds) */
-  int32_t min_iters;   /* grid floor m for SK_MODE_SK and SK_MODE_HYBRID: the
+  int32_t min_iters;   /* grid floor m for every mode but SK_MODE_DP: the
                           launch uses g' = min(g, max(1, W_all / m))
                           workgroups, W_all = MAC iterations of all tiles, so
                           that a split tile has few contributors when the
-                          problem is small.  0 = automatic,
-                          m = ceil(sqrt(2 * ceil(W_all / T))); 1 = keep g.
+                          problem is small.  0 = automatic: m =
+                          ceil(I / c), I = ceil(W_all / T), c the largest
+                          integer >= 1 with f c^2 <= I, f = max(4,
+                          BM*BN/8192); 1 = keep g.
                           sk_plan_info.g reports g'. */
 } sk_config;
 
@@ -160,6 +177,7 @@ typedef struct {
   int64_t q, rho;    /* workgroup x owns q + (x < rho) iterations */
   int64_t workspace_bytes;
   int64_t max_iters; /* largest per-tile iteration count */
+  int64_t group_m;   /* tile order used (group_m = -1 resolved) */
 } sk_plan_info;
 
 /* Returns a static English description of a status code. */

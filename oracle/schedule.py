@@ -19,20 +19,34 @@ applied):
   (2) Tiles are numbered problem-major; inside a problem tile u maps to
       (tm, tn) row-major, or, with group_m > 0, band-wise: bands of group_m
       tile rows, walked down the rows first, then across the columns.
+      group_m = -1 (automatic; a locality reading, not in the report) is
+      resolved after step (5): with Stream-K tiles, D = q / gcd(q, I) for the
+      first problem that has tiles (I iterations, tm tile rows) and group_m
+      is the largest divisor of D not above tm (workgroups whose ranges start
+      at the same k-phase of their tiles then sit in one tile row); otherwise
+      group_m = 8.
   (2b) Grid floor (not in the report; a reading that keeps split tiles from
       having dozens of contributors when the problem is small): with
       min_iters = m > 1 a Stream-K or hybrid launch uses
       g' = min(g, max(1, W_all // m)) workgroups, W_all = sum of I over all T
       tiles, so that no workgroup gets much less than m iterations.  m = 0
-      selects m = ceil(sqrt(2 * ceil(W_all / T))): if adding one partial tile
-      costs the finishing workgroup about two MAC iterations, a tile of I
-      iterations split into c pieces takes about I/c + 2(c - 1) iteration
-      times, least at I/c = sqrt(2 I).  m = 1 keeps g.  Steps (3)-(5) use g'.
+      selects m = ceil(I_mean / c) with I_mean = ceil(W_all / T) and c the
+      largest integer >= 1 with f c^2 <= I_mean: if one partial tile costs
+      about f MAC iterations (store, wait, load and add; f = max(4,
+      BM*BN/8192), measured), a tile of I iterations split into c pieces
+      takes about I/c + f(c - 1) iteration times, least near c = sqrt(I/f);
+      with c = 1 tiles are not split at all.  m = 1 keeps g.  Steps (3)-(5)
+      use g'.
   (3) Split point S over the T = sum T_p tiles: tiles [0,S) are Stream-K
       tiles, [S,T) data-parallel tiles.  SK mode: S = T.  DP mode: S = 0 with
       one workgroup per tile.  Hybrid ("two-tile SK + DP"): S = 0 when
-      T mod g == 0, else min(T, T mod g + g).  An explicit dp_tiles >= 0 sets
-      S = T - min(dp_tiles, T).
+      T mod g == 0, else min(T, T mod g + g).  Auto mode (not in the report):
+      the hybrid rule, and S = 0 also when Stream-K cannot beat the
+      data-parallel waves under the cost model of step (2b) with an eighth
+      added for the L2 reuse that workgroups at different k-phases lose:
+      with b = ceil(W_all / g), when b + ceil(b / 8) + f >=
+      ceil(T / g) * ceil(W_all / T).  An explicit
+      dp_tiles >= 0 sets S = T - min(dp_tiles, T).
   (4) Iteration space of the SK tiles: J_0 = 0, J_{t+1} = J_t + I_t, W = J_S.
   (5) Even split over g persistent workgroups: q = W // g, rho = W % g;
       workgroup x owns [s_x, e_x) with s_x = x*q + min(x, rho) and
@@ -48,11 +62,12 @@ applied):
 """
 from bisect import bisect_right
 from collections import defaultdict
+from math import gcd
 from dataclasses import dataclass
 
 FULL, FINISH, PARTIAL, DP = 0, 1, 2, 3
 ROLE_NAMES = {FULL: "FULL", FINISH: "FINISH", PARTIAL: "PARTIAL", DP: "DP"}
-MODE_HYBRID, MODE_SK, MODE_DP = 0, 1, 2
+MODE_HYBRID, MODE_SK, MODE_DP, MODE_AUTO = 0, 1, 2, 3
 
 
 @dataclass(frozen=True)
@@ -99,17 +114,23 @@ class Plan:
     rho: int
     J: list              # prefix sums over the SK tiles, len S+1
     dp_grid: bool        # DP mode: one workgroup per tile
+    group_m: int = 0     # tile order used
 
 
-def isqrt_ceil(n):
-    """Smallest m >= 0 with m*m >= n (n >= 0), by plain search."""
-    m = 0
-    while m * m < n:
-        m += 1
-    return m
+def fixup_cost(block_m, block_n):
+    """Step (2b): MAC iterations one partial tile costs (measured)."""
+    return max(4, block_m * block_n // 8192)
 
 
-def grid_floor(g, iters, min_iters):
+def auto_split(I_mean, f=4):
+    """Largest c >= 1 with f c^2 <= I_mean, by plain search."""
+    c = 1
+    while f * (c + 1) * (c + 1) <= I_mean:
+        c += 1
+    return c
+
+
+def grid_floor(g, iters, min_iters, f=4):
     """Step (2b): workgroups actually launched for Stream-K/hybrid."""
     T = len(iters)
     W_all = sum(iters)
@@ -117,7 +138,8 @@ def grid_floor(g, iters, min_iters):
         return g
     m = min_iters
     if m == 0:
-        m = isqrt_ceil(2 * cdiv(W_all, T))
+        I_mean = cdiv(W_all, T)
+        m = cdiv(I_mean, auto_split(I_mean, f))
     if m <= 1:
         return g
     return min(g, max(1, W_all // m))
@@ -126,18 +148,20 @@ def grid_floor(g, iters, min_iters):
 def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
               dp_tiles=-1, group_m=0, min_iters=1):
     """Steps (1)-(5) for a list of (M, N, K) problems."""
-    tiles, iters = [], []
+    local, iters, first = [], [], None
     for p, (M, N, K) in enumerate(problems):
         tm = cdiv(M, block_m) if M > 0 else 0
         tn = cdiv(N, block_n) if N > 0 else 0
         I = max(1, cdiv(K, block_k))
+        if tm * tn > 0 and first is None:
+            first = (I, tm)
         for u in range(tm * tn):
-            r, c = tile_coords(u, tm, tn, group_m)
-            tiles.append((p, r, c))
+            local.append((p, u, tm, tn))
             iters.append(I)
-    T = len(tiles)
+    T = len(local)
+    f = fixup_cost(block_m, block_n)
     if mode != MODE_DP:
-        g = grid_floor(g, iters, min_iters)
+        g = grid_floor(g, iters, min_iters, f)
     if mode == MODE_DP:
         S = 0
         g = T
@@ -145,6 +169,10 @@ def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
         S = T
     else:
         S = 0 if (g == 0 or T % g == 0) else min(T, T % g + g)
+        W_all = sum(iters)
+        b = cdiv(W_all, g) if g > 0 else 0
+        if mode == MODE_AUTO and S > 0 and b + cdiv(b, 8) + f >= cdiv(T, g) * cdiv(W_all, T):
+            S = 0
     if mode != MODE_DP and dp_tiles >= 0:
         S = T - min(dp_tiles, T)
     J = [0]
@@ -152,7 +180,17 @@ def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
         J.append(J[-1] + iters[t])
     W = J[-1]
     q, rho = (W // g, W % g) if g > 0 else (0, 0)
-    return Plan(tiles, iters, T, S, W, g, q, rho, J, mode == MODE_DP)
+    if group_m < 0:
+        if S > 0 and q > 0:
+            D = q // gcd(q, first[0])
+            group_m = max(G for G in range(1, min(D, first[1]) + 1) if D % G == 0)
+        else:
+            group_m = 8
+    tiles = []
+    for p, u, tm, tn in local:
+        r, c = tile_coords(u, tm, tn, group_m)
+        tiles.append((p, r, c))
+    return Plan(tiles, iters, T, S, W, g, q, rho, J, mode == MODE_DP, group_m)
 
 
 def wg_range(plan, x):
@@ -393,7 +431,7 @@ def check(problems, block_m, block_n, block_k, g, mode, segs, dp_tiles=-1,
         if k != I:
             _fail(f"I4: tile {t}: contributions stop at {k} of {I}")
         partial_wgs.extend(s.wg for s in peers)
-        if (mode == MODE_HYBRID and dp_tiles < 0 and len(problems) == 1
+        if (mode in (MODE_HYBRID, MODE_AUTO) and dp_tiles < 0 and len(problems) == 1
                 and S >= g and f.npeers != 1):
             _fail(f"I8: hybrid split tile {t} has {f.npeers + 1} contributors")
 

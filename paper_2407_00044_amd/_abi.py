@@ -28,10 +28,10 @@ SK_ERR_DEVICE_TIMEOUT = -7
 # dtypes / layouts / modes / roles
 SK_F32, SK_F16, SK_BF16, SK_F8E4M3 = 0, 1, 2, 3
 SK_ROW_MAJOR, SK_COL_MAJOR = 0, 1
-SK_MODE_HYBRID, SK_MODE_SK, SK_MODE_DP = 0, 1, 2
+SK_MODE_HYBRID, SK_MODE_SK, SK_MODE_DP, SK_MODE_AUTO = 0, 1, 2, 3
 SK_ROLE_FULL, SK_ROLE_FINISH, SK_ROLE_PARTIAL, SK_ROLE_DP = 0, 1, 2, 3
 
-MODES = {"hybrid": SK_MODE_HYBRID, "sk": SK_MODE_SK, "dp": SK_MODE_DP}
+MODES = {"hybrid": SK_MODE_HYBRID, "sk": SK_MODE_SK, "dp": SK_MODE_DP, "auto": SK_MODE_AUTO}
 
 
 class SkProblem(ctypes.Structure):
@@ -60,7 +60,7 @@ class SkSegment(ctypes.Structure):
 class SkPlanInfo(ctypes.Structure):
     _fields_ = [("T", c_i64), ("S", c_i64), ("W", c_i64), ("g", c_i64),
                 ("q", c_i64), ("rho", c_i64), ("workspace_bytes", c_i64),
-                ("max_iters", c_i64)]
+                ("max_iters", c_i64), ("group_m", c_i64)]
 
 
 class SkDebug(ctypes.Structure):

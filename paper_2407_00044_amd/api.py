@@ -29,17 +29,20 @@ class Config:
     """Launch configuration (mirrors sk_config).
 
     tile: (block_m, block_n); block_k follows from the input type.
-    mode: 'hybrid' (data-parallel + Stream-K), 'sk' or 'dp' (baseline grid).
+    mode: 'auto' (hybrid that splits tiles only where the cost model says
+    Stream-K beats data-parallel waves), 'hybrid' (data-parallel + Stream-K,
+    two-tile rule), 'sk' or 'dp' (baseline grid).
     num_cu: compute units (0 = all); wg_per_cu: persistent workgroups per CU.
     dp_tiles: -1 = two-tile hybrid rule, else number of data-parallel tiles.
+    group_m: tile order (0 row-major, > 0 bands of group_m rows, -1 automatic).
     min_iters: Stream-K grid floor (0 = automatic, 1 = always g workgroups).
     """
     tile: tuple = (256, 128)
-    mode: str = "hybrid"
+    mode: str = "auto"
     num_cu: int = 0
     wg_per_cu: int = 1
     dp_tiles: int = -1
-    group_m: int = 0
+    group_m: int = -1
     xcd_remap: int = 1
     spin_limit: int = 0
     min_iters: int = 0
@@ -50,16 +53,25 @@ class Config:
                         self.xcd_remap, self.spin_limit, self.min_iters)
 
 
-def default_tile(M, N, K, dtype):
-    """Tile for a problem when none is given: the largest tile whose grid still
-    gives every compute unit work, smaller tiles for small or skinny shapes."""
+def default_tile(M, N, K, dtype, kmajor=True, cus=256):
+    """Tile for a problem when none is given.
+
+    Larger tiles need fewer operand bytes per flop but leave more compute
+    units idle or split more; measured on the BF16 shape sweep, 256x256 pays
+    once it yields at least ~0.55 tiles per CU (only with both operands
+    K-contiguous, whose 8-wave kernel keeps its accumulators in registers),
+    256x128 once it yields one tile per CU, and 128x128 is best below."""
     code = DTYPE_CODES[dtype]
     if code == _abi.SK_F32:
         return (128, 128)
-    if M >= 256 and N >= 128:
-        return (256, 128)
     if code == _abi.SK_F8E4M3 and M <= 64:
         return (64, 128)
+    t256 = -(-M // 256) * -(-N // 256)
+    if kmajor and code in (_abi.SK_F16, _abi.SK_BF16) and M >= 256 and N >= 256 and \
+            t256 * 100 >= cus * 55:
+        return (256, 256)
+    if M >= 256 and -(-M // 256) * -(-N // 128) >= cus:
+        return (256, 128)
     return (128, 128)
 
 
@@ -152,8 +164,10 @@ def gemm(A, B, C=None, *, alpha=1.0, beta=0.0, out=None, out_dtype=torch.float32
             (M, N), dtype=out_dtype, device=A.device)
     if beta != 0.0 and C is None:
         raise ValueError("beta != 0 needs C")
-    cfg = config or Config(tile=default_tile(M, N, A.shape[1], A.dtype))
     p = _problem(A, B, out, alpha, beta, scale_a, scale_b)
+    cfg = config or Config(tile=default_tile(
+        M, N, A.shape[1], A.dtype,
+        kmajor=(p.layout_a == SK_ROW_MAJOR and p.layout_b == SK_COL_MAJOR)))
     if C is not None and beta != 0.0:
         if tuple(C.shape) != (M, N) or C.dtype != out.dtype or C.stride() != out.stride():
             raise ValueError("C must match out in shape, dtype and strides")
@@ -327,7 +341,9 @@ class GroupedGemm:
             ptrs["Cout"][i] = out.data_ptr()
         dev = problems[0][0].device
         M0, N0, K0 = probs[0].M, probs[0].N, probs[0].K
-        self.config = config or Config(tile=default_tile(M0, N0, K0, problems[0][0].dtype))
+        self.config = config or Config(tile=default_tile(
+            M0, N0, K0, problems[0][0].dtype,
+            kmajor=(probs[0].layout_a == SK_ROW_MAJOR and probs[0].layout_b == SK_COL_MAJOR)))
         c = self.config.c_struct(probs[0].dtype_ab)
         dbytes = ctypes.c_size_t()
         check("sk_grouped_desc_size", lib.sk_grouped_desc_size(n, ctypes.byref(dbytes)))

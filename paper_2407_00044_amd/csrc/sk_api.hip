@@ -48,6 +48,7 @@ constexpr int64_t kMaxIndex = (int64_t(1) << 31) - 1;
 struct Plan {
   int64_t T = 0, S = 0, W = 0, g = 0, q = 0, rho = 0, max_iters = 0;
   int64_t ws_bytes = 0;
+  int32_t group_m = 0;           // resolved tile order
   std::vector<ProbDesc> descs;   // pointers left null by plan_problems
 };
 
@@ -118,10 +119,10 @@ static sk_status check_problem(const sk_problem& p) {
 // Resolves g and checks the config against the tile menu.
 static sk_status resolve_config(const sk_config* cfg, int32_t dtype_ab, int64_t* g_out) {
   if (cfg == nullptr) return SK_ERR_INVALID_ARG;
-  if (cfg->mode < 0 || cfg->mode > 2) return SK_ERR_INVALID_ARG;
+  if (cfg->mode < 0 || cfg->mode > 3) return SK_ERR_INVALID_ARG;
   if (cfg->block_k != k_per_iter(dtype_ab)) return SK_ERR_UNSUPPORTED;
   if (!tile_built(dtype_ab, cfg->block_m, cfg->block_n)) return SK_ERR_UNSUPPORTED;
-  if (cfg->group_m < 0 || cfg->wg_per_cu < 0 || cfg->num_cu < 0) return SK_ERR_INVALID_ARG;
+  if (cfg->group_m < -1 || cfg->wg_per_cu < 0 || cfg->num_cu < 0) return SK_ERR_INVALID_ARG;
   if (cfg->dp_tiles < -1) return SK_ERR_INVALID_ARG;
   if (cfg->spin_limit < 0 || cfg->min_iters < 0) return SK_ERR_INVALID_ARG;
   int32_t cus = cfg->num_cu;
@@ -150,21 +151,56 @@ static bool offsets_fit(const sk_problem& p, int64_t bm, int64_t bn) {
   return span_a <= kMaxIndex && span_b <= kMaxIndex && span_c <= kMaxIndex;
 }
 
-// Grid floor: with m = min_iters > 1 (0: m = ceil(sqrt(2 ceil(W_all/T))),
-// the point where the finisher's extra work for more contributors, about
-// two MAC iterations per partial tile, balances the shorter pieces), a
-// Stream-K launch of a small problem uses max(1, W_all / m) < g workgroups.
-static int64_t grid_floor(int64_t g, int64_t T, int64_t W_all, int32_t min_iters) {
+// Grid floor: with m = min_iters > 1 a Stream-K launch of a small problem
+// uses max(1, W_all / m) < g workgroups.  Automatic m (min_iters = 0): one
+// partial tile costs about f = fixup_iters(BM, BN) MAC iterations of the
+// finisher's time, so a tile of I iterations split into c pieces takes
+// about I/c + f(c-1) iteration times; c is the largest integer >= 1 with
+// f c^2 <= I_mean and m = ceil(I_mean/c).
+static int64_t grid_floor(int64_t g, int64_t T, int64_t W_all, int32_t min_iters, int64_t f) {
   if (T == 0 || W_all == 0) return g;
   int64_t m = min_iters;
   if (m == 0) {
-    const int64_t target = 2 * cdiv(W_all, T);
-    m = (int64_t)std::sqrt((double)target);
-    while (m * m < target) ++m;
-    while (m > 1 && (m - 1) * (m - 1) >= target) --m;
+    const int64_t i_mean = cdiv(W_all, T);
+    int64_t c = 1;
+    while (f * (c + 1) * (c + 1) <= i_mean) ++c;
+    m = cdiv(i_mean, c);
   }
   if (m <= 1) return g;
   return std::min<int64_t>(g, std::max<int64_t>(1, W_all / m));
+}
+
+// Automatic tile order (group_m = -1).  Under the balanced split workgroup x
+// starts at iteration x*q, i.e. at k-phase x*q mod I of its first tile, and
+// workgroups x and x + I/gcd(q, I) start at the same phase, so they walk K
+// in step; their first tiles lie D = q/gcd(q, I) apart.  In bands of G
+// tile rows walked down the band first, tiles t and t + D sit side by side
+// in one tile row whenever G divides D, so such workgroups read the same A
+// panel slices at the same time and share them in L2, as the workgroups of
+// a data-parallel wave do.  G is the largest divisor of D not above the
+// tile-row count tm.  Without Stream-K tiles: bands of 8 rows (the
+// data-parallel wave's tiles on one XCD then form a compact block).
+static int64_t gcd64(int64_t a, int64_t b) {
+  while (b != 0) {
+    const int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+static int32_t resolve_group_m(int32_t group_m, const Plan& P) {
+  if (group_m >= 0) return group_m;
+  if (P.S > 0 && P.q > 0) {
+    for (const ProbDesc& d : P.descs) {
+      if ((int64_t)d.tm * d.tn == 0) continue;
+      const int64_t D = P.q / gcd64(P.q, d.I);
+      int64_t G = std::min<int64_t>(D, d.tm);
+      while (D % G != 0) --G;
+      return (int32_t)G;
+    }
+  }
+  return 8;
 }
 
 // Tile counts, split point, iteration space and per-problem offsets.
@@ -211,8 +247,9 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
   } else {
     int64_t W_all = 0;
     for (int32_t i = 0; i < n; ++i) W_all += (int64_t)P.descs[i].tm * P.descs[i].tn * P.descs[i].I;
-    P.g = grid_floor(g, T, W_all, cfg->min_iters);
-    P.S = split_point(T, P.g, cfg->mode, cfg->dp_tiles);
+    const int64_t fix = fixup_iters(bm, bn);
+    P.g = grid_floor(g, T, W_all, cfg->min_iters, fix);
+    P.S = split_point(T, W_all, P.g, cfg->mode, cfg->dp_tiles, fix);
   }
   // Stream-K iteration offsets (problem-major, so J is monotone in p).
   int64_t J = 0;
@@ -231,6 +268,7 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
   }
   P.ws_bytes = cfg->mode == SK_MODE_DP ? 0
                                        : ws_bytes(P.S, P.S > 0 ? P.g : 0, bm, bn);
+  P.group_m = resolve_group_m(cfg->group_m, P);
   *out = std::move(P);
   return SK_OK;
 }
@@ -255,7 +293,7 @@ static void host_segments(const Plan& P, const sk_config* cfg, std::vector<sk_se
     s.wg = (int32_t)x;
     s.problem = p;
     s.tile = (int32_t)t;
-    tile_coords(u, d.tm, d.tn, cfg->group_m, &s.tile_m, &s.tile_n);
+    tile_coords(u, d.tm, d.tn, P.group_m, &s.tile_m, &s.tile_n);
     s.k_begin = kb;
     s.k_end = ke;
     s.role = role;
@@ -331,7 +369,7 @@ static sk_status launch(const Plan& P, const sk_config* cfg, int32_t dt, int32_t
   kp.nprobs = nprobs;
   kp.dtype_c = dtype_c;
   kp.T = P.T; kp.S = P.S; kp.W = P.W; kp.g = P.g; kp.q = P.q; kp.rho = P.rho;
-  kp.group_m = cfg->group_m;
+  kp.group_m = P.group_m;
   kp.xcd_remap = cfg->xcd_remap;
   kp.dp_grid = cfg->mode == SK_MODE_DP ? 1 : 0;
   kp.spin_limit = cfg->spin_limit > 0 ? cfg->spin_limit : kDefaultSpinLimit;
@@ -448,6 +486,7 @@ sk_status sk_plan(const sk_problem* probs, int32_t nprobs, const sk_config* cfg,
   info->q = P.q; info->rho = P.rho;
   info->workspace_bytes = P.ws_bytes;
   info->max_iters = P.max_iters;
+  info->group_m = P.group_m;
   return SK_OK;
 }
 
@@ -564,7 +603,7 @@ sk_status sk_grouped_prepare(const sk_problem* probs, const void* const* A,
   plan->q = P.q; plan->rho = P.rho;
   plan->workspace_bytes = P.ws_bytes;
   plan->xcd_remap = cfg->xcd_remap;
-  plan->group_m = cfg->group_m;
+  plan->group_m = P.group_m;
   plan->spin_limit = cfg->spin_limit;
   plan->all_aligned = all_aligned;
   return SK_OK;
@@ -577,6 +616,7 @@ sk_status sk_gemm_grouped(const sk_grouped_plan* plan, const void* dev_desc, voi
   P.T = plan->T; P.S = plan->S; P.W = plan->W; P.g = plan->g;
   P.q = plan->q; P.rho = plan->rho;
   P.ws_bytes = plan->workspace_bytes;
+  P.group_m = plan->group_m;
   sk_config cfg;
   memset(&cfg, 0, sizeof(cfg));
   cfg.block_m = plan->block_m;
@@ -585,7 +625,7 @@ sk_status sk_gemm_grouped(const sk_grouped_plan* plan, const void* dev_desc, voi
   cfg.xcd_remap = plan->xcd_remap;
   cfg.group_m = plan->group_m;
   cfg.spin_limit = plan->spin_limit;
-  if (plan->mode < 0 || plan->mode > 2) return SK_ERR_INVALID_ARG;
+  if (plan->mode < 0 || plan->mode > 3) return SK_ERR_INVALID_ARG;
   cfg.mode = plan->mode;
   return launch(P, &cfg, plan->dtype_ab, plan->layout_a, plan->layout_b, plan->dtype_c, nullptr,
                 (const ProbDesc*)dev_desc, plan->nprobs, workspace, ws_bytes_, nullptr,

@@ -6,7 +6,9 @@ rounded up to 16 bytes, N(0,1) entries, FP32 C_in uniform in [-1, 1],
 alpha = 1, beta = 0.5.  Times are GPU times: `reps` launches are captured in
 one HIP graph and replayed, so host-side call overhead (which exceeds the
 kernel time of the smallest shapes) is not counted.  For each shape both
-schedules use the same tile;
+schedules use the same tile: the library's Stream-K policy ('auto': the
+two-tile hybrid rule, splitting tiles only where its cost model predicts a
+gain), the plain two-tile hybrid rule, and the data-parallel grid;
 the report lists TFLOP/s = 2*M*N*K / t per shape, the min and geometric mean
 of each schedule, the predicted quantization loss of one-tile-per-workgroup
 tiling 1 - T / (ceil(T/g) * g) and the measured ratio t_DP / t_SK.
@@ -27,8 +29,7 @@ import torch
 from . import api, synth, tune
 
 
-def _time(fn, reps, replays=3):
-    """Milliseconds per call of fn, from replays of a graph of `reps` calls."""
+def _graph(fn, reps):
     fn()
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
@@ -37,14 +38,25 @@ def _time(fn, reps, replays=3):
             fn()
     g.replay()
     torch.cuda.synchronize()
+    return g
+
+
+def _time_all(fns, reps, rounds=5):
+    """Milliseconds per call of each fn: each fn's `reps` calls are captured
+    in one graph; the graphs are replayed in turn for `rounds` rounds (so
+    clock or thermal drift hits every fn alike) and the median is kept."""
+    graphs = [_graph(fn, reps) for fn in fns]
+    times = [[] for _ in fns]
     s = torch.cuda.Event(enable_timing=True)
     e = torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(replays):
-        g.replay()
-    e.record()
-    torch.cuda.synchronize()
-    return s.elapsed_time(e) / (reps * replays)
+    for _ in range(rounds):
+        for i, g in enumerate(graphs):
+            s.record()
+            g.replay()
+            e.record()
+            torch.cuda.synchronize()
+            times[i].append(s.elapsed_time(e) / reps)
+    return [sorted(t)[len(t) // 2] for t in times]
 
 
 def gmean(xs):
@@ -70,30 +82,31 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False)
         C = (torch.rand((M, N), generator=gen, device=dev) * 2 - 1)
         outC = torch.empty_like(C)
         tile = api.default_tile(M, N, K, torch.bfloat16)
-        cfg_sk = api.Config(tile=tile, mode="hybrid")
+        cfg_sk = api.Config(tile=tile, mode="auto")
+        cfg_hy = api.Config(tile=tile, mode="hybrid")
         cfg_dp = api.Config(tile=tile, mode="dp")
 
         def go(cfg):
             return lambda: api.gemm(A, B, C, beta=0.5, out=outC, config=cfg, workspace=ws)
-        t_sk = _time(go(cfg_sk), reps)
-        t_dp = _time(go(cfg_dp), reps)
+        t_sk, t_hy, t_dp = _time_all([go(cfg_sk), go(cfg_hy), go(cfg_dp)], reps)
         p = api.plan([(M, N, K)], torch.bfloat16, cfg_sk)
         T = p["T"]
         q_eff = T / (math.ceil(T / cus) * cus)
         flops = 2.0 * M * N * K
         row = {"M": M, "N": N, "K": K, "tile": list(tile), "T": T, "S": p["S"],
-               "sk_tflops": flops / t_sk / 1e9, "dp_tflops": flops / t_dp / 1e9,
+               "sk_tflops": flops / t_sk / 1e9, "hybrid_tflops": flops / t_hy / 1e9,
+               "dp_tflops": flops / t_dp / 1e9,
                "dp_quant_eff": q_eff, "t_dp_over_t_sk": t_dp / t_sk}
         if all_tiles:
             row["tiles"] = {}
             for t in ALL_TILES:
                 key = f"{t[0]}x{t[1]}"
-                row["tiles"][key] = {
-                    "sk": flops / _time(go(api.Config(tile=t, mode="hybrid")), reps) / 1e9,
-                    "dp": flops / _time(go(api.Config(tile=t, mode="dp")), reps) / 1e9}
+                ts, td = _time_all([go(api.Config(tile=t, mode="auto")),
+                                    go(api.Config(tile=t, mode="dp"))], reps)
+                row["tiles"][key] = {"sk": flops / ts / 1e9, "dp": flops / td / 1e9}
         if use_tuner:
             best = tune.tune_gemm(A, B, torch.float32, reps=max(3, reps // 2))
-            t_best = _time(go(best), reps)
+            t_best = _time_all([go(best)], reps)[0]
             row["tuned"] = {"config": [list(best.tile), best.mode, best.dp_tiles],
                             "tflops": flops / t_best / 1e9}
         rows.append(row)
@@ -102,9 +115,11 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False)
               file=sys.stderr, flush=True)
         del A, B, C, outC
     sk = [r["sk_tflops"] for r in rows]
+    hy = [r["hybrid_tflops"] for r in rows]
     dp = [r["dp_tflops"] for r in rows]
     summary = {"shapes": len(rows), "sk_min": min(sk), "sk_geomean": gmean(sk),
                "dp_min": min(dp), "dp_geomean": gmean(dp),
+               "hybrid_min": min(hy), "hybrid_geomean": gmean(hy),
                "sk_beats_dp_geomean": gmean(sk) > gmean(dp), "sk_beats_dp_min": min(sk) > min(dp),
                "mean_predicted_quant_loss": sum(1 - r["dp_quant_eff"] for r in rows) / len(rows),
                "geomean_t_dp_over_t_sk": gmean([r["t_dp_over_t_sk"] for r in rows])}

@@ -1,9 +1,10 @@
 """Autotuner: picks the tile shape and the data-parallel / Stream-K split.
 
 Candidates are every built tile for the input type crossed with a small set
-of schedules: the two-tile hybrid rule, all tiles Stream-K, a one-tile
-Stream-K remainder (dp_tiles = T - T mod g), and the plain data-parallel
-grid.  Each candidate is timed with HIP events over a few back-to-back
+of schedules: the cost-model (auto) rule, the two-tile hybrid rule, all
+tiles Stream-K, a one-tile Stream-K remainder (dp_tiles = T - T mod g), and
+the plain data-parallel grid, each with the automatic tile order; the
+hybrid rule is also tried in plain row-major tile order.  Each candidate is timed with HIP events over a few back-to-back
 launches on the caller's buffers; the fastest is cached in a JSON file keyed
 by device, CU count, input/output types, layouts and shape, so a shape is
 measured once per machine.
@@ -56,11 +57,13 @@ def candidates(shapes, dtype, num_cu=0, tiles=None):
         T, g = p["T"], p["g"]
         if T == 0:
             continue
-        out.append(base)                                       # two-tile hybrid rule
+        out.append(base)                                       # cost-model rule
+        out.append(api.Config(tile=t, mode="hybrid", num_cu=num_cu))   # two-tile rule
+        out.append(api.Config(tile=t, mode="hybrid", num_cu=num_cu, group_m=0))
         out.append(api.Config(tile=t, mode="sk", num_cu=num_cu))
         one = T - T % g if T % g else T                        # one-tile SK remainder
         if one not in (0, T):
-            out.append(api.Config(tile=t, num_cu=num_cu, dp_tiles=one))
+            out.append(api.Config(tile=t, mode="hybrid", num_cu=num_cu, dp_tiles=one))
         out.append(api.Config(tile=t, mode="dp", num_cu=num_cu))
     return out
 

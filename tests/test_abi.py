@@ -46,7 +46,7 @@ def _status(fn):
 
 
 def test_plan_closed_forms():
-    p = _plan(3840, 4096, 4096, dtype=torch.float16, tile=(256, 128), num_cu=256)
+    p = _plan(3840, 4096, 4096, dtype=torch.float16, tile=(256, 128), num_cu=256, mode="hybrid")
     assert (p["T"], p["S"], p["W"], p["q"], p["rho"]) == (480, 480, 30720, 120, 0)
     p = _plan(512, 512, 512, dtype=torch.float32, tile=(128, 128), mode="sk", num_cu=256,
               min_iters=1)
@@ -56,9 +56,10 @@ def test_plan_closed_forms():
     assert (p["T"], p["S"], p["g"], p["workspace_bytes"]) == (9, 0, 9, 0)
     p = _plan(8192, 4096, 11008, tile=(256, 128), num_cu=256)   # T mod g == 0: pure DP
     assert (p["T"], p["S"]) == (1024, 0)
-    # automatic grid floor: 6 tiles x 50 iterations -> m = 10, 30 workgroups
+    # automatic grid floor: 6 tiles x 50 iterations -> 3 pieces per tile,
+    # m = 17, 17 workgroups
     p = _plan(607, 187, 3155, tile=(256, 128), num_cu=256)
-    assert (p["T"], p["g"], p["q"], p["rho"]) == (6, 30, 10, 0)
+    assert (p["T"], p["g"], p["q"], p["rho"]) == (6, 17, 17, 11)
     p = _plan(607, 187, 3155, tile=(256, 128), num_cu=256, min_iters=1)
     assert (p["g"], p["q"], p["rho"]) == (256, 1, 44)
 
@@ -145,6 +146,7 @@ def test_tuner_candidates():
     c = tune.candidates([(3840, 4096, 4096)], torch.bfloat16, num_cu=256)
     modes = {(x.tile, x.mode, x.dp_tiles) for x in c}
     assert ((256, 128), "hybrid", -1) in modes and ((256, 256), "dp", -1) in modes
+    assert ((256, 256), "auto", -1) in modes
     assert ((128, 128), "sk", -1) in modes
     # T = 480 tiles of 256x128 on 256 workgroups: one-tile remainder keeps 256 DP tiles
     assert ((256, 128), "hybrid", 256) in modes

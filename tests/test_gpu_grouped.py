@@ -63,7 +63,8 @@ def test_grouped_schedule_matches_simulator():
     for tile in [(64, 128), (128, 128), (256, 128)]:
         for mode, m in [("hybrid", sch.MODE_HYBRID), ("sk", sch.MODE_SK)]:
             cfg = sk.Config(tile=tile, mode=mode, num_cu=256)
-            _, sim = sch.simulate(shapes, tile[0], tile[1], 128, 256, m, min_iters=0)
+            _, sim = sch.simulate(shapes, tile[0], tile[1], 128, 256, m, group_m=-1,
+                                  min_iters=0)
             assert sk.schedule(shapes, torch.float8_e4m3fn, cfg) == [s.as_tuple() for s in sim]
 
 

@@ -16,7 +16,7 @@ from oracle import schedule as sch
 
 pytestmark = gpu
 
-MODES = {"sk": sch.MODE_SK, "hybrid": sch.MODE_HYBRID, "dp": sch.MODE_DP}
+MODES = {"sk": sch.MODE_SK, "hybrid": sch.MODE_HYBRID, "dp": sch.MODE_DP, "auto": sch.MODE_AUTO}
 BK = {"f32": 32, "f16": 64, "bf16": 64, "e4m3": 128}
 
 # (M, N, K, dtype, tile, mode, g, min_iters): min_iters = 1 keeps all g
@@ -33,6 +33,8 @@ CASES = [
     (607, 187, 3155, "bf16", (256, 128), "hybrid", 256, 0),
     (235, 2337, 528, "bf16", (128, 128), "sk", 256, 0),
     (1000, 700, 900, "f16", (128, 128), "hybrid", 256, 7),
+    (1713, 1597, 14203, "bf16", (128, 128), "auto", 256, 0),
+    (1000, 700, 900, "bf16", (128, 128), "auto", 256, 0),
 ]
 
 
@@ -44,7 +46,7 @@ def test_device_trace_matches_simulator(M, N, K, dtype, tile, mode, g, mi):
     out, segs, cover = sk.gemm_debug(A.view, B.view, config=cfg, scale_a=A.scale,
                                      scale_b=B.scale)
     _, sim = sch.simulate([(M, N, K)], tile[0], tile[1], BK[dtype], g, MODES[mode],
-                          min_iters=mi)
+                          group_m=cfg.group_m, min_iters=mi)
     assert segs == [s.as_tuple() for s in sim]
     plan = sk.plan([(M, N, K)], out.dtype if dtype == "f32" else A.view.dtype, cfg)
     T, I = plan["T"], plan["max_iters"]

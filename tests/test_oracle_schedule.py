@@ -80,15 +80,16 @@ def test_hybrid_split_rule():
 
 def test_grid_floor_hand_values():
     # 607x187x3155 on 256x128x64 tiles: 3x2 = 6 tiles of ceil(3155/64) = 50
-    # iterations, W_all = 300; automatic m = ceil(sqrt(2*50)) = 10, so the
-    # grid shrinks from 256 to 300 // 10 = 30 workgroups of 10 iterations.
+    # iterations, W_all = 300; automatic split c = 3 (4*9 <= 50 < 4*16),
+    # m = ceil(50/3) = 17, so the grid shrinks from 256 to 300 // 17 = 17
+    # workgroups: 300 = 17*17 + 11.
     plan = sch.make_plan([(607, 187, 3155)], 256, 128, 64, 256, sch.MODE_HYBRID, min_iters=0)
-    assert (plan.T, plan.g, plan.S, plan.W, plan.q, plan.rho) == (6, 30, 6, 300, 10, 0)
+    assert (plan.T, plan.g, plan.S, plan.W, plan.q, plan.rho) == (6, 17, 6, 300, 17, 11)
     # m = 1 keeps the grid: 300 iterations over 256 workgroups
     plan = sch.make_plan([(607, 187, 3155)], 256, 128, 64, 256, sch.MODE_HYBRID, min_iters=1)
     assert (plan.g, plan.q, plan.rho) == (256, 1, 44)
-    # the headline shape on 256x256 tiles is large enough: m = ceil(sqrt(128))
-    # = 12, 15360 // 12 = 1280 > 256
+    # the headline shape on 256x256 tiles (fixup cost 8) is large enough:
+    # c = 2 (8*4 <= 64 < 8*9), m = 32, 15360 // 32 = 480 > 256
     plan = sch.make_plan([(3840, 4096, 4096)], 256, 256, 64, 256, sch.MODE_SK, min_iters=0)
     assert (plan.T, plan.g, plan.W, plan.q) == (240, 256, 15360, 60)
     # explicit m; a floor above W_all leaves one workgroup; DP mode ignores it
@@ -98,11 +99,52 @@ def test_grid_floor_hand_values():
     assert (plan.g, plan.q) == (1, 4)
     plan = sch.make_plan([(512, 512, 512)], 128, 128, 32, 256, sch.MODE_DP, min_iters=40)
     assert plan.g == 16
-    # the floor feeds the hybrid rule: 20 tiles x 8 iterations, m = 4 ->
-    # g' = 40; 20 mod 40 = 20 -> S = min(20, 60) = 20
+    # the floor feeds the hybrid rule: 20 tiles x 8 iterations are too short
+    # to split (c = 1, m = 8) -> g' = 20 = T -> S = 0, pure data-parallel
     plan = sch.make_plan([(20, 1, 8)], 1, 1, 1, 256, sch.MODE_HYBRID, min_iters=0)
-    assert (plan.g, plan.S, plan.q) == (40, 20, 4)
-    assert [sch.isqrt_ceil(n) for n in (0, 1, 2, 4, 5, 100, 101, 128)] == [0, 1, 2, 2, 3, 10, 11, 12]
+    assert (plan.g, plan.S, plan.W) == (20, 0, 0)
+    # 20 tiles x 64 iterations: c = 4, m = 16 -> g' = 80; 20 mod 80 = 20 ->
+    # S = min(20, 100) = 20, q = 16
+    plan = sch.make_plan([(20, 1, 64)], 1, 1, 1, 256, sch.MODE_HYBRID, min_iters=0)
+    assert (plan.g, plan.S, plan.q, plan.rho) == (80, 20, 16, 0)
+    assert [sch.auto_split(n) for n in (0, 1, 15, 16, 35, 36, 64, 99, 100)] == [
+        1, 1, 1, 2, 2, 3, 4, 4, 5]
+
+
+def test_auto_tile_order_hand_values():
+    # 3840x4096x4096, 256x128x64 tiles on 256 workgroups: q = 120, I = 64,
+    # gcd 8 -> bands of 15 rows = the whole 15-row grid, i.e. column-major;
+    # workgroups x and x+8 start at the same k-phase on tiles 15 apart,
+    # which are neighbours in one tile row.
+    plan = sch.make_plan([(3840, 4096, 4096)], 256, 128, 64, 256, sch.MODE_HYBRID,
+                         group_m=-1, min_iters=0)
+    assert plan.group_m == 15
+    assert plan.tiles[:3] == [(0, 0, 0), (0, 1, 0), (0, 2, 0)]
+    assert plan.tiles[14:17] == [(0, 14, 0), (0, 0, 1), (0, 1, 1)]
+    for x in range(0, 248, 8):
+        s0 = sch.wg_range(plan, x)[0]
+        s1 = sch.wg_range(plan, x + 8)[0]
+        assert s0 % 64 == s1 % 64                        # same k-phase
+        (_, r0, c0), (_, r1, c1) = plan.tiles[s0 // 64], plan.tiles[s1 // 64]
+        assert r0 == r1 and c1 == c0 + 1                 # same tile row
+    # 256x256 tiles: q = 60, gcd(60, 64) = 4 -> 15
+    assert sch.make_plan([(3840, 4096, 4096)], 256, 256, 64, 256, sch.MODE_SK,
+                         group_m=-1).group_m == 15
+    # no Stream-K tiles: bands of 8 rows
+    plan = sch.make_plan([(3840, 4096, 4096)], 256, 256, 64, 256, sch.MODE_DP, group_m=-1)
+    assert plan.group_m == 8 and plan.tiles[8] == (0, 0, 1)
+    assert plan.tiles[120] == (0, 0, 15) and plan.tiles[128] == (0, 8, 0)   # band 0: 8x16 tiles
+    # q = 17, I = 50 (coprime): D = 17, largest divisor <= tm = 3 is 1
+    # (row-major bands of one row)
+    plan = sch.make_plan([(607, 187, 3155)], 256, 128, 64, 256, sch.MODE_HYBRID,
+                         group_m=-1, min_iters=0)
+    assert plan.group_m == 1 and plan.tiles[1] == (0, 0, 1)
+    # 4826x1341x13813 on 128x128x64: tm = 38, I = 216, q = 352 (rho = 176):
+    # D = 352 / gcd(352, 216) = 44; largest divisor of 44 <= 38 is 22
+    plan = sch.make_plan([(4826, 1341, 13813)], 128, 128, 64, 256, sch.MODE_HYBRID,
+                         group_m=-1, min_iters=0)
+    assert (plan.q, plan.group_m) == (352, 22)
+    assert plan.tiles[0][1:] == (0, 0) and plan.tiles[44][1:] == (0, 2)
 
 
 def test_grid_floor_invariants():
@@ -114,8 +156,34 @@ def test_grid_floor_invariants():
                 sch.check([shape], bm, bn, bk, plan.g, mode, segs)
                 if plan.T and plan.W:
                     # no workgroup below the floor unless the grid is one WG
-                    mm = m or sch.isqrt_ceil(2 * -(-sum(plan.iters) // plan.T))
+                    im = -(-sum(plan.iters) // plan.T)
+                    mm = m or -(-im // sch.auto_split(im, sch.fixup_cost(bm, bn)))
                     assert plan.g == g or plan.g == 1 or sum(plan.iters) // plan.g >= mm
+
+
+def test_auto_mode_cost_rule():
+    # The worked example (9 tiles of 4 iterations, 4 workgroups): Stream-K
+    # would need b + ceil(b/8) + 4 = 9 + 2 + 4 = 15 iteration times against
+    # 3 waves x 4 = 12 for data-parallel, so auto mode splits nothing;
+    # hybrid keeps its two-tile rule (S = 5).
+    assert sch.make_plan([(384, 384, 128)], 128, 128, 32, 4, sch.MODE_AUTO).S == 0
+    assert sch.make_plan([(384, 384, 128)], 128, 128, 32, 4, sch.MODE_HYBRID).S == 5
+    # 3840x4096x4096, 256x128 tiles: 480 tiles x 64 iterations on 256:
+    # 120 + 15 + 4 = 139 >= 2 x 64 = 128 -> data-parallel
+    p = sch.make_plan([(3840, 4096, 4096)], 256, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
+    assert (p.S, p.W) == (0, 0)
+    # 2190x3876x1024 on 128x128: 558 tiles x 16 iterations on 256: b = 35,
+    # 35 + 5 + 4 = 44 < 3 x 16 = 48 -> two-tile rule, S = 558 mod 256 + 256
+    p = sch.make_plan([(2190, 3876, 1024)], 128, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
+    assert (p.T, p.S) == (558, 302)
+    # ... but on 256x256 (fixup 8): 144 tiles, b = 9, 9 + 2 + 8 >= 16 -> DP
+    p = sch.make_plan([(2190, 3876, 1024)], 256, 256, 64, 256, sch.MODE_AUTO, min_iters=0)
+    assert p.S == 0
+    # long K, few tiles: 6 tiles x 50 on g' = 17: 18 + 3 + 4 = 25 < 50 -> split
+    p = sch.make_plan([(607, 187, 3155)], 256, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
+    assert (p.g, p.S) == (17, 6)
+    assert [sch.fixup_cost(*t) for t in [(64, 128), (128, 128), (256, 128), (256, 256)]] == [
+        4, 4, 4, 8]
 
 
 def test_group_m_tile_order_is_a_bijection():
@@ -139,11 +207,13 @@ def _cases(seed, n):
         yield shape, rng.choice(TILES), rng.choice(GS)
 
 
-@pytest.mark.parametrize("mode", [sch.MODE_SK, sch.MODE_HYBRID, sch.MODE_DP])
+@pytest.mark.parametrize("mode", [sch.MODE_SK, sch.MODE_HYBRID, sch.MODE_DP, sch.MODE_AUTO])
 def test_brute_force_invariants(mode):
     for shape, (bm, bn, bk), g in _cases(10 + mode, 400):
         for gm in (0, 3):
             for dp in ((-1,) if mode == sch.MODE_DP else (-1, 0, 2)):
+                plan, segs = sch.simulate([shape], bm, bn, bk, g, mode, dp, -1)
+                sch.check([shape], bm, bn, bk, g, mode, segs, dp, plan.group_m)
                 plan, segs = sch.simulate([shape], bm, bn, bk, g, mode, dp, gm)
                 sch.check([shape], bm, bn, bk, g, mode, segs, dp, gm)
 

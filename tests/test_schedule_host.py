@@ -9,7 +9,7 @@ import paper_2407_00044_amd as sk
 from oracle import schedule as sch
 from paper_2407_00044_amd import synth
 
-MODES = {"sk": sch.MODE_SK, "hybrid": sch.MODE_HYBRID, "dp": sch.MODE_DP}
+MODES = {"sk": sch.MODE_SK, "hybrid": sch.MODE_HYBRID, "dp": sch.MODE_DP, "auto": sch.MODE_AUTO}
 BK = {torch.float32: 32, torch.float16: 64, torch.bfloat16: 64, torch.float8_e4m3fn: 128}
 
 
@@ -20,10 +20,11 @@ def compare(shapes, dtype, tile, g, mode, dp_tiles=-1, group_m=0, min_iters=0):
     plan, sim = sch.simulate(shapes, tile[0], tile[1], BK[dtype], g, MODES[mode], dp_tiles,
                              group_m, min_iters)
     assert lib_segs == [s.as_tuple() for s in sim]
-    assert sk.plan(shapes, dtype, cfg)["g"] == plan.g
+    info = sk.plan(shapes, dtype, cfg)
+    assert (info["g"], info["group_m"]) == (plan.g, plan.group_m)
 
 
-@pytest.mark.parametrize("mode", ["sk", "hybrid", "dp"])
+@pytest.mark.parametrize("mode", ["sk", "hybrid", "dp", "auto"])
 def test_random_small_shapes(mode):
     r = random.Random(7)
     sizes = [1, 5, 31, 32, 33, 64, 127, 128, 129, 200, 255, 256, 257, 300]
@@ -34,7 +35,7 @@ def test_random_small_shapes(mode):
         shape = (r.choice(sizes), r.choice(sizes), r.choice(sizes + [0, 1000]))
         g = r.choice([1, 2, 3, 7, 8, 16, 64, 120, 255, 256])
         dp = r.choice([-1, -1, 0, 3]) if mode != "dp" else -1
-        gm = r.choice([0, 0, 2, 5])
+        gm = r.choice([0, -1, -1, 2, 5])
         compare([shape], dt, r.choice(tiles[dt]), g, mode, dp, gm, r.choice([0, 0, 1, 3, 40]))
 
 
@@ -52,6 +53,8 @@ def test_paper_configurations():
 def test_sweep_shapes():
     for M, N, K in synth.sweep_shapes()[:24]:
         compare([(M, N, K)], torch.bfloat16, (256, 128), 256, "hybrid")
+        compare([(M, N, K)], torch.bfloat16, (128, 128), 256, "hybrid", group_m=-1)
+        compare([(M, N, K)], torch.bfloat16, (128, 128), 256, "auto", group_m=-1)
 
 
 def test_grouped_sets():
