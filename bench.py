@@ -133,14 +133,18 @@ def traffic_from_profile(kernel_key):
 
 
 def copy_leg():
-    """A plain device copy of known size (calibrates FETCH_SIZE/WRITE_SIZE)."""
+    """Kernels of known traffic (calibrate FETCH_SIZE/WRITE_SIZE): a device
+    copy of 512 MiB, then an elementwise add that reads 512 MiB and writes
+    512 MiB."""
     import torch
     n = 512 * 1024 * 1024
     src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": n}))
+    torch.add(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "add_read_bytes": n, "add_write_bytes": n}))
 
 
 def main():

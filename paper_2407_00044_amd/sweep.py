@@ -41,11 +41,12 @@ def _graph(fn, reps):
     return g
 
 
-def _time_all(fns, reps, rounds=5):
+def _time_all(fns, reps, rounds=None):
     """Milliseconds per call of each fn: each fn's `reps` calls are captured
     in one graph; the graphs are replayed in turn for `rounds` rounds (so
     clock or thermal drift hits every fn alike) and the median is kept."""
     graphs = [_graph(fn, reps) for fn in fns]
+    rounds = rounds or 2 * len(fns) + 1
     times = [[] for _ in fns]
     s = torch.cuda.Event(enable_timing=True)
     e = torch.cuda.Event(enable_timing=True)
