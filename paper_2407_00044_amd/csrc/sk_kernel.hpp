@@ -142,7 +142,11 @@ struct KMajorStage {
     const char* base = o.X + o.row0 * o.ld_b;
     const int64_t rows_left = o.rows - o.row0;
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, (rows_left - 1) * o.ld_b + o.K * EB);
-    const int wave = uniform32(tid >> 6), lane = tid & 63;
+    const int wave = uniform32(tid >> 6);
+    int lane = tid & 63;
+    // per-lane offsets are formed at each issue (a few adds), not hoisted
+    // into registers that would live across the MAC loop
+    asm volatile("" : "+v"(lane));
     const uint32_t ld32 = (uint32_t)o.ld_b;
     const uint32_t kb32 = (uint32_t)(k0 * EB);
     const int32_t rl = (int32_t)imin(rows_left, R);
