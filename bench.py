@@ -7,7 +7,9 @@ B column-major, entries uniform in [-1, 1] (seeded), alpha=1, beta=0,
 one persistent workgroup per CU (480 tiles on 256 CUs: every tile is a
 Stream-K tile), in the automatic tile order.  Also timed: the equal-tile
 data-parallel grid, the library's auto policy (which may fall back to
-data-parallel), and BF16 with 256x256 and 256x128 tiles.  Before any timed
+data-parallel), BF16 with 256x256 and 256x128 tiles, and (report.py) FP32
+512^3, the BF16 linear layer's three products and the FP8 grouped GEMM,
+each beside its data-parallel comparator.  Before any timed
 region the legs are run untimed for about a second (clocks, TLBs and caches
 settle; the first leg of a fresh process otherwise reads up to 15% slow).  The same shape is also timed with the equal-tile
 data-parallel grid, and in BF16 with 256x256 and 256x128 tiles.
@@ -33,6 +35,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the FP32 512^3, linear-layer and grouped FP8 timings")
     ap.add_argument("--only", default="",
                     help="run only this leg: sk | dp | bf16 | copy (plain device copy of "
                          "512 MiB, used to calibrate byte counters)")
@@ -239,6 +243,9 @@ def main():
                                                          cfg_auto)["S"]}
     if bf:
         line["bf16_same_shape"] = bf
+    if not args.no_configs:
+        from paper_2407_00044_amd import report
+        line["other_configs"] = report.run_all(dev)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(host, M, N, K)
     print(json.dumps(line), flush=True)

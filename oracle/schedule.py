@@ -46,7 +46,9 @@ applied):
       added for the L2 reuse that workgroups at different k-phases lose:
       with b = ceil(W_all / g), when b + ceil(b / 8) + f >=
       ceil(T / g) * ceil(W_all / T).  An explicit
-      dp_tiles >= 0 sets S = T - min(dp_tiles, T).
+      dp_tiles >= 0 sets S = T - min(dp_tiles, T).  Auto mode with S = 0 on a
+      single problem launches the DP grid (one workgroup per tile) instead of
+      handing whole tiles round-robin to the persistent workgroups.
   (4) Iteration space of the SK tiles: J_0 = 0, J_{t+1} = J_t + I_t, W = J_S.
   (5) Even split over g persistent workgroups: q = W // g, rho = W % g;
       workgroup x owns [s_x, e_x) with s_x = x*q + min(x, rho) and
@@ -175,6 +177,9 @@ def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
             S = 0
     if mode != MODE_DP and dp_tiles >= 0:
         S = T - min(dp_tiles, T)
+    dp_grid = mode == MODE_DP or (mode == MODE_AUTO and S == 0 and len(problems) == 1)
+    if dp_grid:
+        g = T
     J = [0]
     for t in range(S):
         J.append(J[-1] + iters[t])
@@ -190,7 +195,7 @@ def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
     for p, u, tm, tn in local:
         r, c = tile_coords(u, tm, tn, group_m)
         tiles.append((p, r, c))
-    return Plan(tiles, iters, T, S, W, g, q, rho, J, mode == MODE_DP, group_m)
+    return Plan(tiles, iters, T, S, W, g, q, rho, J, dp_grid, group_m)
 
 
 def wg_range(plan, x):

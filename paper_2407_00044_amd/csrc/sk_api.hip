@@ -49,6 +49,7 @@ struct Plan {
   int64_t T = 0, S = 0, W = 0, g = 0, q = 0, rho = 0, max_iters = 0;
   int64_t ws_bytes = 0;
   int32_t group_m = 0;           // resolved tile order
+  bool dp_grid = false;          // one workgroup per tile, no fixup
   std::vector<ProbDesc> descs;   // pointers left null by plan_problems
 };
 
@@ -244,12 +245,20 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
   if (cfg->mode == SK_MODE_DP) {
     P.S = 0;
     P.g = T;
+    P.dp_grid = true;
   } else {
     int64_t W_all = 0;
     for (int32_t i = 0; i < n; ++i) W_all += (int64_t)P.descs[i].tm * P.descs[i].tn * P.descs[i].I;
     const int64_t fix = fixup_iters(bm, bn);
     P.g = grid_floor(g, T, W_all, cfg->min_iters, fix);
     P.S = split_point(T, W_all, P.g, cfg->mode, cfg->dp_tiles, fix);
+    // auto mode with nothing to split on one problem: the data-parallel
+    // grid itself (the hardware hands out tiles as workgroups finish, which
+    // beats a fixed round-robin of whole tiles over persistent workgroups)
+    if (cfg->mode == SK_MODE_AUTO && P.S == 0 && n == 1) {
+      P.g = T;
+      P.dp_grid = true;
+    }
   }
   // Stream-K iteration offsets (problem-major, so J is monotone in p).
   int64_t J = 0;
@@ -262,12 +271,11 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
   }
   if (J > kMaxIndex) return SK_ERR_UNSUPPORTED;
   P.W = J;
-  if (cfg->mode != SK_MODE_DP && P.g > 0) {
+  if (!P.dp_grid && P.g > 0) {
     P.q = P.W / P.g;
     P.rho = P.W % P.g;
   }
-  P.ws_bytes = cfg->mode == SK_MODE_DP ? 0
-                                       : ws_bytes(P.S, P.S > 0 ? P.g : 0, bm, bn);
+  P.ws_bytes = P.dp_grid ? 0 : ws_bytes(P.S, P.S > 0 ? P.g : 0, bm, bn);
   P.group_m = resolve_group_m(cfg->group_m, P);
   *out = std::move(P);
   return SK_OK;
@@ -300,7 +308,7 @@ static void host_segments(const Plan& P, const sk_config* cfg, std::vector<sk_se
     s.npeers = npeers;
     out->push_back(s);
   };
-  if (cfg->mode == SK_MODE_DP) {
+  if (P.dp_grid) {
     for (int64_t t = 0; t < P.T; ++t) {
       int32_t p = host_find_problem(P, t, false);
       emit(t, p, t, t - P.descs[p].tile_start, 0, P.descs[p].I, SK_ROLE_DP, 0);
@@ -350,7 +358,7 @@ static sk_status launch(const Plan& P, const sk_config* cfg, int32_t dt, int32_t
   const KernelEntry* ke = find_kernel(dt, la, lb, cfg->block_m, cfg->block_n);
   if (ke == nullptr) return SK_ERR_UNSUPPORTED;
   if (P.T == 0) return SK_OK;
-  if (cfg->mode != SK_MODE_DP) {
+  if (!P.dp_grid) {
     if (ws == nullptr || (int64_t)ws_len < P.ws_bytes) return SK_ERR_WORKSPACE;
     int32_t cus = 0;
     sk_status st = device_cus(&cus);
@@ -371,7 +379,7 @@ static sk_status launch(const Plan& P, const sk_config* cfg, int32_t dt, int32_t
   kp.T = P.T; kp.S = P.S; kp.W = P.W; kp.g = P.g; kp.q = P.q; kp.rho = P.rho;
   kp.group_m = P.group_m;
   kp.xcd_remap = cfg->xcd_remap;
-  kp.dp_grid = cfg->mode == SK_MODE_DP ? 1 : 0;
+  kp.dp_grid = P.dp_grid ? 1 : 0;
   kp.spin_limit = cfg->spin_limit > 0 ? cfg->spin_limit : kDefaultSpinLimit;
   if (ws) {
     char* w = (char*)ws;
@@ -391,7 +399,7 @@ static sk_status launch(const Plan& P, const sk_config* cfg, int32_t dt, int32_t
     if (kp.cover && kp.cover_stride < P.max_iters) return SK_ERR_INVALID_ARG;
   }
   void* args[] = {&kp};
-  const int64_t grid = cfg->mode == SK_MODE_DP ? P.T : P.g;
+  const int64_t grid = P.dp_grid ? P.T : P.g;
   if (hipLaunchKernel(ke->fn, dim3((unsigned)grid), dim3((unsigned)ke->nt), args, 0, stream) != hipSuccess)
     return SK_ERR_HIP;
   return SK_OK;
@@ -617,6 +625,8 @@ sk_status sk_gemm_grouped(const sk_grouped_plan* plan, const void* dev_desc, voi
   P.q = plan->q; P.rho = plan->rho;
   P.ws_bytes = plan->workspace_bytes;
   P.group_m = plan->group_m;
+  P.dp_grid = plan->mode == SK_MODE_DP ||
+              (plan->mode == SK_MODE_AUTO && plan->S == 0 && plan->nprobs == 1);
   sk_config cfg;
   memset(&cfg, 0, sizeof(cfg));
   cfg.block_m = plan->block_m;

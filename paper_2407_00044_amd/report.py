@@ -1,0 +1,131 @@
+"""Timings of the other workloads of record, beside the FP16 3840x4096x4096
+headline of bench.py: FP32 512^3 split over 256 workgroups, the BF16 linear
+layer's forward, dX and dW products, and the 48-problem FP8 grouped GEMM.
+Each Stream-K launch is timed against its data-parallel comparator with
+graph replays (warm-up, rotated order, median; see sweep._time_all).
+
+Inputs are drawn on the GPU with torch's seeded generator in the recipes'
+distributions (timing only; the parity tests use synth.py's FP64 draws).
+
+    python -m paper_2407_00044_amd.report
+"""
+import json
+import sys
+
+import torch
+
+from . import api, synth
+from .sweep import _time_all
+
+
+def _normal(shape, seed, dev):
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    return torch.randn(shape, generator=g, device=dev)
+
+
+def _uniform(shape, seed, dev):
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    return torch.rand(shape, generator=g, device=dev) * 2 - 1
+
+
+def _tf(flops, ms):
+    return round(flops / ms / 1e9, 2)
+
+
+def c1(dev, reps=20):
+    """FP32 512^3, A and B row-major, 128x128x32 tiles, all Stream-K over 256
+    workgroups (16 tiles, 16 contributors each) vs the 16-workgroup grid."""
+    A = _uniform((512, 512), 1, dev)
+    B = _uniform((512, 512), 2, dev)
+    out = torch.empty((512, 512), device=dev)
+    ws = api.Workspace(dev)
+    ws.get(64 << 20, torch.cuda.current_stream().cuda_stream)
+    cfgs = {"sk_g256": api.Config(tile=(128, 128), mode="sk", num_cu=256, min_iters=1),
+            "auto": api.Config(tile=(128, 128), mode="auto"),
+            "dp": api.Config(tile=(128, 128), mode="dp")}
+    fns = [(lambda c: (lambda: api.gemm(A, B, out=out, config=c, workspace=ws)))(c)
+           for c in cfgs.values()]
+    ts = _time_all(fns, reps)
+    fl = 2.0 * 512 ** 3
+    return {"workload": "fp32 512x512x512, A and B row-major, 128x128x32 tiles",
+            **{k: {"us": round(t * 1e3, 2), "tflops": _tf(fl, t)} for k, t in zip(cfgs, ts)}}
+
+
+def c4(dev, reps=5):
+    """BF16 linear layer Y = X W^T, X [8192, 4096], W [11008, 4096], dY
+    [8192, 11008]: forward (A row, B col), dX = dY W (A row, B row) and
+    dW = dY^T X (A col, B row), each Stream-K (auto) vs data-parallel at the
+    default tile."""
+    X = _normal((8192, 4096), 4, dev).to(torch.bfloat16)
+    W = _normal((11008, 4096), 5, dev).to(torch.bfloat16)
+    dY = _normal((8192, 11008), 40, dev).to(torch.bfloat16)
+    ws = api.Workspace(dev)
+    ws.get(96 << 20, torch.cuda.current_stream().cuda_stream)
+    res = {"workload": "bf16 linear layer X[8192,4096] W[11008,4096], FP32 products"}
+    for name, A, B in [("forward", X, W.t()), ("dX", dY, W), ("dW", dY.t(), X)]:
+        M, K = A.shape
+        N = B.shape[1]
+        la, _ = api.operand_layout(A)
+        lb, _ = api.operand_layout(B)
+        tile = api.default_tile(M, N, K, torch.bfloat16,
+                                kmajor=(la == api.SK_ROW_MAJOR and lb == api.SK_COL_MAJOR))
+        out = torch.empty((M, N), device=dev)
+        cfgs = [api.Config(tile=tile, mode="auto"), api.Config(tile=tile, mode="dp")]
+        t_sk, t_dp = _time_all([(lambda c: (lambda: api.gemm(A, B, out=out, config=c,
+                                                                workspace=ws)))(c)
+                                for c in cfgs], reps)
+        fl = 2.0 * M * N * K
+        p = api.plan([(M, N, K)], torch.bfloat16, cfgs[0])
+        res[name] = {"M": M, "N": N, "K": K, "tile": list(tile), "stream_k_tiles": p["S"],
+                     "tiles": p["T"], "sk_tflops": _tf(fl, t_sk), "dp_tflops": _tf(fl, t_dp)}
+        del out
+    return res
+
+
+def c5(dev, reps=5, tile=(128, 128)):
+    """48 FP8-e4m3 problems (synth.grouped_shapes), per-tensor amax scales,
+    FP32 outputs: one grouped Stream-K launch (auto) vs one grouped
+    data-parallel launch vs 48 separate data-parallel launches, equal tiles."""
+    shapes = synth.grouped_shapes()
+    probs, scales = [], []
+    for i, (M, N, K) in enumerate(shapes):
+        a = _normal((M, K), 500 + i, dev)
+        b = _normal((N, K), 1500 + i, dev)
+        sa = float(a.abs().max()) / 448.0
+        sb = float(b.abs().max()) / 448.0
+        A = (a / sa).to(torch.float8_e4m3fn)
+        B = (b / sb).to(torch.float8_e4m3fn).t()          # K x N, column-major
+        probs.append((A, B, torch.empty((M, N), device=dev)))
+        scales.append((sa, sb))
+    g_sk = api.GroupedGemm(probs, config=api.Config(tile=tile, mode="auto"), scales=scales)
+    g_dp = api.GroupedGemm(probs, config=api.Config(tile=tile, mode="dp"), scales=scales)
+    ws = api.Workspace(dev)
+    ws.get(64 << 20, torch.cuda.current_stream().cuda_stream)
+    cfg_dp = api.Config(tile=tile, mode="dp")
+
+    def separate():
+        for (A, B, out), (sa, sb) in zip(probs, scales):
+            api.gemm(A, B, out=out, scale_a=sa, scale_b=sb, config=cfg_dp, workspace=ws)
+    t_sk, t_gdp, t_sep = _time_all([g_sk.run, g_dp.run, separate], reps)
+    fl = sum(2.0 * M * N * K for M, N, K in shapes)
+    info = g_sk.info()
+    return {"workload": "48 fp8-e4m3 problems, M log-uniform [16,4096], N in {1024,2048,4096}, "
+                        "K in {2048,4096,8192}", "tile": list(tile), "gflop": round(fl / 1e9, 1),
+            "tiles": info["T"], "stream_k_tiles": info["S"],
+            "grouped_sk_tflops": _tf(fl, t_sk), "grouped_dp_tflops": _tf(fl, t_gdp),
+            "separate_dp_tflops": _tf(fl, t_sep)}
+
+
+def run_all(dev):
+    out = {}
+    for name, fn in [("c1", c1), ("c4", c4), ("c5", c5)]:
+        out[name] = fn(dev)
+        print(f"# {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    return out
+
+
+if __name__ == "__main__":
+    print(json.dumps(run_all(torch.device("cuda", 0))))

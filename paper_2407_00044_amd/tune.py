@@ -53,7 +53,7 @@ def candidates(shapes, dtype, num_cu=0, tiles=None):
     out = []
     for t in tiles:
         base = api.Config(tile=t, num_cu=num_cu)
-        p = api.plan(shapes, dtype, base)
+        p = api.plan(shapes, dtype, api.Config(tile=t, mode="hybrid", num_cu=num_cu))
         T, g = p["T"], p["g"]
         if T == 0:
             continue

@@ -169,9 +169,13 @@ def test_auto_mode_cost_rule():
     assert sch.make_plan([(384, 384, 128)], 128, 128, 32, 4, sch.MODE_AUTO).S == 0
     assert sch.make_plan([(384, 384, 128)], 128, 128, 32, 4, sch.MODE_HYBRID).S == 5
     # 3840x4096x4096, 256x128 tiles: 480 tiles x 64 iterations on 256:
-    # 120 + 15 + 4 = 139 >= 2 x 64 = 128 -> data-parallel
+    # 120 + 15 + 4 = 139 >= 2 x 64 = 128 -> data-parallel, and with nothing
+    # split on a single problem the launch is the DP grid (480 workgroups)
     p = sch.make_plan([(3840, 4096, 4096)], 256, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
-    assert (p.S, p.W) == (0, 0)
+    assert (p.S, p.W, p.g, p.dp_grid) == (0, 0, 480, True)
+    # ... but a grouped launch stays on the persistent grid
+    p = sch.make_plan([(3840, 4096, 4096)] * 2, 256, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
+    assert (p.S, p.g, p.dp_grid) == (0, 256, False)
     # 2190x3876x1024 on 128x128: 558 tiles x 16 iterations on 256: b = 35,
     # 35 + 5 + 4 = 44 < 3 x 16 = 48 -> two-tile rule, S = 558 mod 256 + 256
     p = sch.make_plan([(2190, 3876, 1024)], 128, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
@@ -213,9 +217,9 @@ def test_brute_force_invariants(mode):
         for gm in (0, 3):
             for dp in ((-1,) if mode == sch.MODE_DP else (-1, 0, 2)):
                 plan, segs = sch.simulate([shape], bm, bn, bk, g, mode, dp, -1)
-                sch.check([shape], bm, bn, bk, g, mode, segs, dp, plan.group_m)
+                sch.check([shape], bm, bn, bk, plan.g, mode, segs, dp, plan.group_m)
                 plan, segs = sch.simulate([shape], bm, bn, bk, g, mode, dp, gm)
-                sch.check([shape], bm, bn, bk, g, mode, segs, dp, gm)
+                sch.check([shape], bm, bn, bk, plan.g, mode, segs, dp, gm)
 
 
 def test_brute_force_grouped():
