@@ -180,20 +180,50 @@ struct KMajorStage {
 
   __device__ __forceinline__ void commit(char*, int) const {}
 
-  // Element-wise path (any alignment, any K): every element of the thread's
-  // chunks is loaded on its own with an out-of-range offset where it lies
-  // outside the matrix; all loads are issued before the chunks are packed
-  // and written to LDS.
+  // Edge iterations.  Rows 16-byte aligned (K ends inside a chunk): every
+  // chunk is one 16-byte load, and the elements at k >= K are zeroed in
+  // registers.  The buffer then extends to the end of the 4-byte word that
+  // holds the matrix's last element (a word with valid data lies in a mapped
+  // page), so no load reaches past it; the bytes it does read past K are
+  // row padding or that word's tail, both masked.
+  // Otherwise (any alignment) every element of the thread's chunks is loaded
+  // on its own with an out-of-range offset where it lies outside the
+  // matrix; all loads are issued before the chunks are packed and written.
   __device__ static void copy_slow(char* L, const OpTile& o, int64_t k0, int tid) {
     constexpr int NCH = R * 8 / NT;
     const char* base = o.X + o.row0 * o.ld_b;
     const int64_t rows_left = o.rows - o.row0;
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, (rows_left - 1) * o.ld_b + o.K * EB);
     const int32_t rl = (int32_t)imin(rows_left, R);
     const int32_t kleft = (int32_t)imin(o.K - k0, KE);
     const uint32_t ld32 = (uint32_t)o.ld_b;
     const uint32_t kb32 = (uint32_t)(k0 * EB);
     const int c = tid & 7;
+    if (o.aligned) {
+      const __amdgpu_buffer_rsrc_t rw =
+          make_rsrc(base, (rows_left - 1) * o.ld_b + ((o.K * EB + 3) & ~(int64_t)3));
+      const int nb = (kleft - c * EPC) * EB;   // valid bytes of this lane's chunk
+      u32x4 v[NCH];
+#pragma unroll
+      for (int j = 0; j < NCH; ++j) {
+        const int r = (tid >> 3) + j * (NT / 8);
+        const bool ok = r < rl && nb > 0;
+        v[j] = __builtin_amdgcn_raw_buffer_load_b128(
+            rw, (int)(ok ? (uint32_t)r * ld32 + kb32 + (uint32_t)(c * 16) : kOOB), 0, 0);
+      }
+      u32x4 keep;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int kb = nb - 4 * w;             // valid bytes of word w
+        keep[w] = kb >= 4 ? 0xffffffffu : kb <= 0 ? 0u : (1u << (8 * kb)) - 1u;
+      }
+#pragma unroll
+      for (int j = 0; j < NCH; ++j) {
+        const int r = (tid >> 3) + j * (NT / 8);
+        *(u32x4*)(L + lds_off(r, c)) = v[j] & keep;
+      }
+      return;
+    }
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, (rows_left - 1) * o.ld_b + o.K * EB);
     uint32_t e[NCH][EPC];
 #pragma unroll
     for (int j = 0; j < NCH; ++j) {

@@ -26,7 +26,8 @@ def x64_to_e4m3(x64):
 class Operand:
     """A seeded operand: rounded CPU tensor, its GPU placement and codes."""
 
-    def __init__(self, x64, dtype, col_major, ld=None, pad_align=True, scaled=True):
+    def __init__(self, x64, dtype, col_major, ld=None, pad_align=True, scaled=True,
+                 pad_nan=False):
         self.dtype = dtype
         self.col_major = col_major
         if dtype == "e4m3" and scaled:
@@ -42,6 +43,12 @@ class Operand:
             ld = synth.ld_aligned(inner, ELEM[dtype])
         self.view, store, self.ld = synth.place(self.t, col_major, ld, device=dev())
         self.codes = synth.codes(store.cpu())
+        if pad_nan and self.ld > inner:
+            # row padding (never part of the product) holds NaN on the GPU
+            if dtype == "e4m3":
+                store.view(torch.uint8)[:, inner:] = 0x7F
+            else:
+                store[:, inner:] = float("nan")
         self.x64 = x64
 
     def decoded(self):
@@ -50,7 +57,7 @@ class Operand:
 
 
 def make_inputs(M, N, K, dtype, a_col=False, b_col=True, seed=1, dist="uniform", lda=None,
-                ldb=None):
+                ldb=None, pad_nan=False):
     if dist == "uniform":
         a64 = synth.uniform((M, K), seed)
         b64 = synth.uniform((K, N), seed + 1000)
@@ -63,8 +70,8 @@ def make_inputs(M, N, K, dtype, a_col=False, b_col=True, seed=1, dist="uniform",
     else:
         raise ValueError(dist)
     scaled = dist != "int"
-    return (Operand(a64, dtype, a_col, lda, scaled=scaled),
-            Operand(b64, dtype, b_col, ldb, scaled=scaled))
+    return (Operand(a64, dtype, a_col, lda, scaled=scaled, pad_nan=pad_nan),
+            Operand(b64, dtype, b_col, ldb, scaled=scaled, pad_nan=pad_nan))
 
 
 def oracle(A, B, M, N, K, alpha=1.0, beta=0.0, cin=None, rows=None):

@@ -178,3 +178,17 @@ def test_bf16_sweep_shapes_beta_sampled():
         for mode in ["hybrid", "dp"]:
             C = run(A, B, sk.Config(tile=tile, mode=mode), beta=0.5, C=Cin.clone())
             assert rel_err(as64(C)[rows], ref) <= 1e-4, (i, mode)
+
+
+@pytest.mark.parametrize("dtype,K,ld", [("bf16", 77, 80), ("f16", 130, 136), ("f32", 30, 32),
+                                        ("e4m3", 100, 112), ("bf16", 1001, 1008)])
+def test_aligned_rows_with_k_inside_a_chunk(dtype, K, ld):
+    # 16-byte aligned rows whose K ends inside a 16-byte chunk (the masked
+    # edge iteration), checked on every element including the last row of
+    # A and the last column of B; the row padding holds NaN, so any element
+    # past K that reached the matrix cores would poison the result
+    M, N = 300, 200
+    for tile in TILES[dtype][:2]:
+        for mode in ("sk", "dp"):
+            check(M, N, K, dtype, False, True, sk.Config(tile=tile, mode=mode, num_cu=64),
+                  lda=ld, ldb=ld, seed=31, pad_nan=True)
