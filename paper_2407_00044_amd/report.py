@@ -7,7 +7,10 @@ graph replays (warm-up, rotated order, median; see sweep._time_all).
 Inputs are drawn on the GPU with torch's seeded generator in the recipes'
 distributions (timing only; the parity tests use synth.py's FP64 draws).
 
-    python -m paper_2407_00044_amd.report
+    python -m paper_2407_00044_amd.report [--extra]
+
+--extra adds the report's two experiments on MI355X: the padding ablation of
+Table 1 and Stream-K throughput against the "Compute Units" count.
 """
 import json
 import sys
@@ -118,9 +121,69 @@ def c5(dev, reps=5, tile=(128, 128)):
             "separate_dp_tflops": _tf(fl, t_sep)}
 
 
-def run_all(dev):
+def padding(dev, reps=10, tile=(256, 128)):
+    """The report's padding experiment (Methodology, Results, Table 1) on
+    FP16: each shape run unpadded (edges through out-of-range loads and
+    dropped stores) and on copies zero-padded to tile multiples in M, N and
+    K (every tile full); TFLOP/s counts the unpadded 2MNK in both."""
+    out = {"tile": list(tile), "schedule": "hybrid"}
+    ws = api.Workspace(dev)
+    ws.get(96 << 20, torch.cuda.current_stream().cuda_stream)
+    bk = 64
+    for M, N, K in [(3840, 4096, 4096), (1920, 2000, 2000), (480, 512, 512)]:
+        Mp = -(-M // tile[0]) * tile[0]
+        Np = -(-N // tile[1]) * tile[1]
+        Kp = -(-K // bk) * bk
+        A = _uniform((M, K), 2, dev).half()
+        Bt = _uniform((N, K), 3, dev).half()
+        Ap = torch.zeros((Mp, Kp), device=dev, dtype=torch.half)
+        Ap[:M, :K] = A
+        Bp = torch.zeros((Np, Kp), device=dev, dtype=torch.half)
+        Bp[:N, :K] = Bt
+        o = torch.empty((M, N), device=dev)
+        op = torch.empty((Mp, Np), device=dev)
+        cfg = api.Config(tile=tile, mode="hybrid")
+        t_u, t_p = _time_all([lambda: api.gemm(A, Bt.t(), out=o, config=cfg, workspace=ws),
+                              lambda: api.gemm(Ap, Bp.t(), out=op, config=cfg, workspace=ws)],
+                             reps)
+        fl = 2.0 * M * N * K
+        out[f"{M}x{N}x{K}"] = {"padded_to": [Mp, Np, Kp], "unpadded_us": round(t_u * 1e3, 2),
+                              "padded_us": round(t_p * 1e3, 2), "unpadded_tflops": _tf(fl, t_u),
+                              "padded_tflops": _tf(fl, t_p),
+                              "no_padding_gain_pct": round(100 * (t_p / t_u - 1), 2)}
+    return out
+
+
+def compute_units(dev, reps=10):
+    """The report's "Compute Units" argument: Stream-K (all tiles split, no
+    grid floor) on FP16 3840x4096x4096 and 1920x2000x2000, 256x128 tiles,
+    with g = 8 .. 256 workgroups (one per CU); the data-parallel grid beside
+    it uses every CU."""
+    ws = api.Workspace(dev)
+    ws.get(96 << 20, torch.cuda.current_stream().cuda_stream)
     out = {}
-    for name, fn in [("c1", c1), ("c4", c4), ("c5", c5)]:
+    for M, N, K in [(3840, 4096, 4096), (1920, 2000, 2000)]:
+        A = _uniform((M, K), 2, dev).half()
+        Bt = _uniform((N, K), 3, dev).half()
+        o = torch.empty((M, N), device=dev)
+        gs = [8, 16, 32, 64, 120, 128, 192, 240, 256]
+        cfgs = [api.Config(tile=(256, 128), mode="sk", num_cu=g, min_iters=1) for g in gs]
+        cfgs.append(api.Config(tile=(256, 128), mode="dp"))
+        ts = _time_all([(lambda c: (lambda: api.gemm(A, Bt.t(), out=o, config=c,
+                                                       workspace=ws)))(c) for c in cfgs], reps)
+        fl = 2.0 * M * N * K
+        out[f"{M}x{N}x{K}"] = {"stream_k_tflops_by_cus": {str(g): _tf(fl, t) for g, t in
+                                                          zip(gs, ts[:-1])},
+                              "dp_tflops": _tf(fl, ts[-1])}
+    return out
+
+
+def run_all(dev, extra=False):
+    out = {}
+    todo = [("c1", c1), ("c4", c4), ("c5", c5)]
+    if extra:
+        todo += [("padding", padding), ("compute_units", compute_units)]
+    for name, fn in todo:
         out[name] = fn(dev)
         print(f"# {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
@@ -128,4 +191,4 @@ def run_all(dev):
 
 
 if __name__ == "__main__":
-    print(json.dumps(run_all(torch.device("cuda", 0))))
+    print(json.dumps(run_all(torch.device("cuda", 0), extra="--extra" in sys.argv)))
