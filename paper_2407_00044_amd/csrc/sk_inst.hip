@@ -20,11 +20,20 @@
 SK_INST(128, 128, 2, 4)
 #else
 // f16 / bf16 / e4m3: large tiles for compute-bound shapes, smaller ones for
-// small or skinny problems.  256x256 runs 8 waves (two per SIMD, 128x64
-// each); the others 4 waves.
+// small or skinny problems.  256x256 runs 8 waves (two per SIMD, 128x64 wave
+// tiles).  With both operands K-contiguous (LDS-direct copies), 256x128 and
+// 128x128 also run 8 waves (64x64 and 32x64 wave tiles): two waves per SIMD
+// hide LDS and load latency that one wave per SIMD leaves exposed.  With an
+// M- or N-major operand the copies are staged through registers, and there
+// 4 waves (128x64 and 64x64 wave tiles) were faster or spilled less.
 SK_INST(256, 256, 2, 8)
+#if SK_LA == 0 && SK_LB == 1
+SK_INST(256, 128, 4, 8)
+SK_INST(128, 128, 4, 8)
+#else
 SK_INST(256, 128, 2, 4)
 SK_INST(128, 128, 2, 4)
+#endif
 #if SK_DT == 3
 SK_INST(64, 128, 2, 4)
 #endif

@@ -2,7 +2,7 @@
 headline of bench.py: FP32 512^3 split over 256 workgroups, the BF16 linear
 layer's forward, dX and dW products, and the 48-problem FP8 grouped GEMM.
 Each Stream-K launch is timed against its data-parallel comparator with
-graph replays (warm-up, rotated order, median; see sweep._time_all).
+graph replays (warm-up, rotated order, median; see timing.time_all).
 
 Inputs are drawn on the GPU with torch's seeded generator in the recipes'
 distributions (timing only; the parity tests use synth.py's FP64 draws).
@@ -18,7 +18,7 @@ import sys
 import torch
 
 from . import api, synth
-from .sweep import _time_all
+from .timing import time_all as _time_all
 
 
 def _normal(shape, seed, dev):

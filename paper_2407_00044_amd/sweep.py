@@ -27,37 +27,7 @@ import time
 import torch
 
 from . import api, synth, tune
-
-
-def _graph(fn, reps):
-    fn()
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        for _ in range(reps):
-            fn()
-    g.replay()
-    torch.cuda.synchronize()
-    return g
-
-
-def _time_all(fns, reps, rounds=None):
-    """Milliseconds per call of each fn: each fn's `reps` calls are captured
-    in one graph; the graphs are replayed in turn for `rounds` rounds (so
-    clock or thermal drift hits every fn alike) and the median is kept."""
-    graphs = [_graph(fn, reps) for fn in fns]
-    rounds = rounds or 2 * len(fns) + 1
-    times = [[] for _ in fns]
-    s = torch.cuda.Event(enable_timing=True)
-    e = torch.cuda.Event(enable_timing=True)
-    for _ in range(rounds):
-        for i, g in enumerate(graphs):
-            s.record()
-            g.replay()
-            e.record()
-            torch.cuda.synchronize()
-            times[i].append(s.elapsed_time(e) / reps)
-    return [sorted(t)[len(t) // 2] for t in times]
+from .timing import time_all as _time_all
 
 
 def gmean(xs):

@@ -4,9 +4,12 @@ Candidates are every built tile for the input type crossed with a small set
 of schedules: the cost-model (auto) rule, the two-tile hybrid rule, all
 tiles Stream-K, a one-tile Stream-K remainder (dp_tiles = T - T mod g), and
 the plain data-parallel grid, each with the automatic tile order; the
-hybrid rule is also tried in plain row-major tile order.  Each candidate is timed with HIP events over a few back-to-back
-launches on the caller's buffers; the fastest is cached in a JSON file keyed
-by device, CU count, input/output types, layouts and shape, so a shape is
+hybrid rule is also tried in plain row-major tile order.  The candidates run
+on the caller's buffers and are timed together by graph replay (each
+candidate's launches captured in one HIP graph, the graphs replayed in turn,
+median kept; see timing.time_all), so host call overhead does not decide
+between them on small shapes.  The fastest is cached in a JSON file keyed by
+device, CU count, input/output types, layouts and shape, so a shape is
 measured once per machine.
 """
 import json
@@ -16,6 +19,7 @@ import threading
 import torch
 
 from . import api
+from .timing import time_all
 
 _lock = threading.Lock()
 
@@ -68,19 +72,6 @@ def candidates(shapes, dtype, num_cu=0, tiles=None):
     return out
 
 
-def _time(fn, reps):
-    fn()
-    torch.cuda.synchronize()
-    s = torch.cuda.Event(enable_timing=True)
-    e = torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(reps):
-        fn()
-    e.record()
-    torch.cuda.synchronize()
-    return s.elapsed_time(e) / reps
-
-
 def _key(kind, shapes, A, B, out_dtype, num_cu):
     la, _ = api.operand_layout(A)
     lb, _ = api.operand_layout(B)
@@ -88,13 +79,15 @@ def _key(kind, shapes, A, B, out_dtype, num_cu):
     return f"{_device_key()}|{kind}|{A.dtype}|{out_dtype}|{la}{lb}|g{num_cu}|{shp}"
 
 
+_FIELDS = ("mode", "num_cu", "dp_tiles", "group_m", "min_iters")
+
+
 def _cfg_to_dict(c):
-    return {"tile": list(c.tile), "mode": c.mode, "num_cu": c.num_cu, "dp_tiles": c.dp_tiles}
+    return {"tile": list(c.tile), **{f: getattr(c, f) for f in _FIELDS}}
 
 
 def _cfg_from_dict(d):
-    return api.Config(tile=tuple(d["tile"]), mode=d["mode"], num_cu=d["num_cu"],
-                      dp_tiles=d["dp_tiles"])
+    return api.Config(tile=tuple(d["tile"]), **{f: d[f] for f in _FIELDS if f in d})
 
 
 def tune_gemm(A, B, out_dtype=torch.float32, num_cu=0, reps=10, use_cache=True,
@@ -108,11 +101,13 @@ def tune_gemm(A, B, out_dtype=torch.float32, num_cu=0, reps=10, use_cache=True,
         if hit:
             return _cfg_from_dict(hit["config"])
     out = torch.empty((M, N), dtype=out_dtype, device=A.device)
-    results = []
-    for c in candidates([(M, N, K)], A.dtype, num_cu):
-        ms = _time(lambda: api.gemm(A, B, out=out, config=c), reps)
-        results.append((ms, c))
-    results.sort(key=lambda r: r[0])
+    cands = candidates([(M, N, K)], A.dtype, num_cu)
+    ws = api.Workspace(A.device)
+    need = max(api.plan([(M, N, K)], A.dtype, c)["workspace_bytes"] for c in cands)
+    ws.get(need, torch.cuda.current_stream().cuda_stream)     # before any capture
+    fns = [(lambda c: (lambda: api.gemm(A, B, out=out, config=c, workspace=ws)))(c)
+           for c in cands]
+    results = sorted(zip(time_all(fns, reps, rounds=3), cands), key=lambda r: r[0])
     best_ms, best = results[0]
     if report is not None:
         report.extend(results)
@@ -133,12 +128,11 @@ def tune_grouped(problems, scales=None, num_cu=0, reps=10, use_cache=True, repor
         hit = _load_cache().get(key)
         if hit:
             return _cfg_from_dict(hit["config"])
-    results = []
-    for c in candidates(shapes, A0.dtype, num_cu):
-        gg = api.GroupedGemm(problems, config=c, scales=scales)
-        ms = _time(gg.run, reps)
-        results.append((ms, c))
-    results.sort(key=lambda r: r[0])
+    cands = candidates(shapes, A0.dtype, num_cu)
+    groups = [api.GroupedGemm(problems, config=c, scales=scales) for c in cands]
+    results = sorted(zip(time_all([gg.run for gg in groups], reps, rounds=3), cands),
+                     key=lambda r: r[0])
+    del groups
     best_ms, best = results[0]
     if report is not None:
         report.extend(results)

@@ -2,6 +2,7 @@
 function include/streamk.h declares, and its host-only entry points validate
 arguments and report capacity as documented."""
 import ctypes
+import json
 import os
 import re
 
@@ -150,3 +151,11 @@ def test_tuner_candidates():
     assert ((128, 128), "sk", -1) in modes
     # T = 480 tiles of 256x128 on 256 workgroups: one-tile remainder keeps 256 DP tiles
     assert ((256, 128), "hybrid", 256) in modes
+
+
+def test_tuner_cache_round_trip_keeps_every_schedule_field():
+    from paper_2407_00044_amd import tune
+    c = sk.Config(tile=(256, 128), mode="hybrid", num_cu=200, dp_tiles=128, group_m=0,
+                  min_iters=1)
+    d = json.loads(json.dumps(tune._cfg_to_dict(c)))
+    assert tune._cfg_from_dict(d) == c
