@@ -53,22 +53,21 @@ class Config:
                         self.xcd_remap, self.spin_limit, self.min_iters)
 
 
-def default_tile(M, N, K, dtype, kmajor=True, cus=256):
+def default_tile(M, N, K, dtype, cus=256):
     """Tile for a problem when none is given.
 
     Larger tiles need fewer operand bytes per flop but leave more compute
     units idle or split more; measured on the BF16 shape sweep, 256x256 pays
-    once it yields at least ~0.55 tiles per CU (only with both operands
-    K-contiguous, whose 8-wave kernel keeps its accumulators in registers),
-    256x128 once it yields one tile per CU, and 128x128 is best below."""
+    once it yields at least ~0.55 tiles per CU (f16/bf16, any layout: both
+    operands are copied LDS-direct), 256x128 once it yields one tile per CU,
+    and 128x128 is best below."""
     code = DTYPE_CODES[dtype]
     if code == _abi.SK_F32:
         return (128, 128)
     if code == _abi.SK_F8E4M3 and M <= 64:
         return (64, 128)
     t256 = -(-M // 256) * -(-N // 256)
-    if kmajor and code in (_abi.SK_F16, _abi.SK_BF16) and M >= 256 and N >= 256 and \
-            t256 * 100 >= cus * 55:
+    if code in (_abi.SK_F16, _abi.SK_BF16) and M >= 256 and N >= 256 and t256 * 100 >= cus * 55:
         return (256, 256)
     if M >= 256 and -(-M // 256) * -(-N // 128) >= cus:
         return (256, 128)
@@ -165,9 +164,7 @@ def gemm(A, B, C=None, *, alpha=1.0, beta=0.0, out=None, out_dtype=torch.float32
     if beta != 0.0 and C is None:
         raise ValueError("beta != 0 needs C")
     p = _problem(A, B, out, alpha, beta, scale_a, scale_b)
-    cfg = config or Config(tile=default_tile(
-        M, N, A.shape[1], A.dtype,
-        kmajor=(p.layout_a == SK_ROW_MAJOR and p.layout_b == SK_COL_MAJOR)))
+    cfg = config or Config(tile=default_tile(M, N, A.shape[1], A.dtype))
     if C is not None and beta != 0.0:
         if tuple(C.shape) != (M, N) or C.dtype != out.dtype or C.stride() != out.stride():
             raise ValueError("C must match out in shape, dtype and strides")
@@ -341,9 +338,7 @@ class GroupedGemm:
             ptrs["Cout"][i] = out.data_ptr()
         dev = problems[0][0].device
         M0, N0, K0 = probs[0].M, probs[0].N, probs[0].K
-        self.config = config or Config(tile=default_tile(
-            M0, N0, K0, problems[0][0].dtype,
-            kmajor=(probs[0].layout_a == SK_ROW_MAJOR and probs[0].layout_b == SK_COL_MAJOR)))
+        self.config = config or Config(tile=default_tile(M0, N0, K0, problems[0][0].dtype))
         c = self.config.c_struct(probs[0].dtype_ab)
         dbytes = ctypes.c_size_t()
         check("sk_grouped_desc_size", lib.sk_grouped_desc_size(n, ctypes.byref(dbytes)))

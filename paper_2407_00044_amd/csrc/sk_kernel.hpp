@@ -9,16 +9,19 @@
 //  * baseline data-parallel grid: one workgroup per tile.
 //
 // Tile datapath (per MAC iteration = 128 bytes of K):
-//  * global -> registers with 16-byte loads, rows of 128 contiguous bytes of
-//    K; operands stored with M (or N) contiguous are transposed in registers
-//    so that LDS always holds K-contiguous rows;
-//  * LDS, double-buffered; the 16-byte chunk c of row r is stored at
+//  * K-contiguous operands: global -> LDS with LDS-direct 16-byte copies,
+//    tile rows of 128 bytes of K; the 16-byte chunk c of row r is stored at
 //    position c ^ ((r & 7) ^ ((r >> 3) & 3)), which keeps 8, 16 or 32
 //    consecutive rows reading the same chunk on distinct banks and repeats
 //    every 32 rows (so per-lane LDS addresses are shared by all 32-row
-//    blocks of a wave);
-//  * LDS -> MFMA operands with 16-byte reads; 32x32 MFMA blocks accumulate in
-//    FP32 (v_mfma_f32_32x32x2_f32, _32x32x16_f16/_bf16, and the block-scaled
+//    blocks of a wave); LDS -> MFMA operands with 16-byte reads;
+//  * M/N-contiguous f16/bf16 operands: LDS-direct copies of k-rows as they
+//    lie in memory (chunk c of k-row k at position c ^ 4(k mod 4)), read into
+//    MFMA operands with gfx950's transposing LDS reads (ds_read_b64_tr_b16);
+//  * M/N-contiguous f32/e4m3 operands: 16-byte loads into registers,
+//    transposed there and written to LDS as K-contiguous rows;
+//  * LDS multi-buffered; 32x32 MFMA blocks accumulate in FP32
+//    (v_mfma_f32_32x32x2_f32, _32x32x16_f16/_bf16, and the block-scaled
 //    32x32x64 f8f6f4 form with unit scales for e4m3).
 //  A and B fragments are read with the same (lane, slot) -> k assignment, so
 //  the product is independent of how the matrix core orders k inside one
@@ -39,6 +42,8 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef short v4s __attribute__((ext_vector_type(4)));
 
 enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3 };
 enum { L_ROW = 0, L_COL = 1 };
@@ -418,10 +423,101 @@ struct MNMajorStage {
   }
 };
 
-template <bool KMAJOR, int R, int EB, int NT>
-struct StageSel;
+// M/N-contiguous f16/bf16 operand copied into LDS as it lies in memory: the
+// stage holds KE k-rows of R elements (PITCH bytes each).  16-byte chunk c of
+// k-row k sits at position c ^ 4(k mod 4): the four k-rows that one
+// transposing read spans then fall on four different 64-byte bank groups
+// (see TrReader).  One wave copy fills 1 KiB = 64 / CPR k-rows, lane i
+// fetching the chunk that the swizzle puts at its position.  k-rows past K
+// and chunks wholly past M (N) are out-of-range offsets (zeros); a chunk that
+// straddles M (N) reads row padding or the next k-row into tile rows that no
+// output uses, and the buffer ends at the 4-byte word holding the last
+// element, so no copy reads past it.
 template <int R, int EB, int NT>
-struct StageSel<true, R, EB, NT> {
+struct MNMajorDMAStage {
+  static constexpr int EPC = 16 / EB;
+  static constexpr int KE = 128 / EB;        // k-rows per stage
+  static constexpr int PITCH = R * EB;       // bytes per k-row
+  static constexpr int CPR = PITCH / 16;     // chunks per k-row
+  static constexpr int RPC = 1024 / PITCH;   // k-rows per 1 KiB copy
+  static constexpr int NI = R / (NT / 8);    // 1 KiB copies per wave
+  static_assert(EB == 2 && CPR >= 16 && CPR <= 64 && R % (NT / 8) == 0, "tile rows");
+
+  __device__ __forceinline__ static bool slow(const OpTile& o, int64_t) { return !o.aligned; }
+
+  __device__ __forceinline__ static __amdgpu_buffer_rsrc_t rsrc(const OpTile& o) {
+    const int64_t rows_left = o.rows - o.row0;
+    return make_rsrc(o.X + o.row0 * EB, ((o.K - 1) * o.ld_b + rows_left * EB + 3) & ~(int64_t)3);
+  }
+
+  __device__ __forceinline__ void issue(char* L, const OpTile& o, int64_t k0, int tid) {
+    const __amdgpu_buffer_rsrc_t rs = rsrc(o);
+    const int wave = uniform32(tid >> 6);
+    int lane = tid & 63;
+    asm volatile("" : "+v"(lane));
+    const uint32_t ld32 = (uint32_t)o.ld_b;
+    const uint32_t kb32 = (uint32_t)k0 * ld32;
+    const int32_t rl = (int32_t)imin(o.rows - o.row0, R);
+    const int32_t kleft = (int32_t)imin(o.K - k0, KE);
+    const int lk = lane / CPR;                 // k-row inside the copy
+    const int pc = lane % CPR;                 // chunk position inside the k-row
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int jj = wave * NI + j;
+      const int kr = jj * RPC + lk;
+      const int c = pc ^ (4 * (kr & 3));
+      const bool ok = kr < kleft && c * EPC < rl;
+      const uint32_t off = ok ? kb32 + (uint32_t)kr * ld32 + (uint32_t)(c * 16) : kOOB;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rs, (__attribute__((address_space(3))) void*)(L + jj * 1024), 16, (int)off, 0, 0, 0);
+    }
+  }
+
+  __device__ __forceinline__ void commit(char*, int) const {}
+
+  // Any alignment: every element loaded on its own (out-of-range offsets
+  // read as zero), packed into chunks written at their swizzled positions.
+  __device__ static void copy_slow(char* L, const OpTile& o, int64_t k0, int tid) {
+    constexpr int NCH = KE * CPR / NT;
+    static_assert((KE * CPR) % NT == 0, "chunks per thread");
+    const char* base = o.X + o.row0 * EB;
+    const int64_t rows_left = o.rows - o.row0;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, (o.K - 1) * o.ld_b + rows_left * EB);
+    const uint32_t ld32 = (uint32_t)o.ld_b;
+    const uint32_t kb32 = (uint32_t)k0 * ld32;
+    const int32_t rl = (int32_t)imin(rows_left, R);
+    const int32_t kleft = (int32_t)imin(o.K - k0, KE);
+    uint32_t e[NCH][EPC];
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+      const int idx = tid + t * NT;
+      const int kr = idx / CPR, c = idx % CPR;
+#pragma unroll
+      for (int i = 0; i < EPC; ++i) {
+        const int m = c * EPC + i;
+        const bool ok = kr < kleft && m < rl;
+        e[t][i] = buf_elem<EB>(rs, ok ? kb32 + (uint32_t)kr * ld32 + (uint32_t)(m * EB) : kOOB);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+      const int idx = tid + t * NT;
+      const int kr = idx / CPR, c = idx % CPR;
+      *(u32x4*)(L + kr * PITCH + ((c ^ (4 * (kr & 3))) << 4)) = pack_chunk<EB>(e[t]);
+    }
+  }
+};
+
+#ifndef SK_MN_TR
+#define SK_MN_TR 1
+#endif
+
+// Stage of an operand: K-contiguous, M/N-contiguous through transposing LDS
+// reads (TR), or M/N-contiguous transposed in registers.
+template <bool KMAJOR, bool TR, int R, int EB, int NT>
+struct StageSel;
+template <bool TR, int R, int EB, int NT>
+struct StageSel<true, TR, R, EB, NT> {
 #if SK_KMAJOR_DMA
   using type = KMajorStage<R, EB, NT>;
 #else
@@ -429,7 +525,9 @@ struct StageSel<true, R, EB, NT> {
 #endif
 };
 template <int R, int EB, int NT>
-struct StageSel<false, R, EB, NT> { using type = MNMajorStage<R, EB, NT>; };
+struct StageSel<false, true, R, EB, NT> { using type = MNMajorDMAStage<R, EB, NT>; };
+template <int R, int EB, int NT>
+struct StageSel<false, false, R, EB, NT> { using type = MNMajorStage<R, EB, NT>; };
 
 // ---------------------------------------------------------------------------
 // Matrix-core step: one 32-byte (f32/f16/bf16) or 64-byte (e4m3) slice of K
@@ -493,17 +591,24 @@ struct Cfg {
   static constexpr int STEPS = DT == DT_F8 ? 2 : 4;  // matrix-core steps per iteration
   static constexpr int BOFF = BM * 128;              // B tile offset in a stage
   static constexpr int STAGE = (BM + BN) * 128;      // LDS bytes per stage
-  // Both operands K-contiguous: LDS-direct copies, as many stages as fit in
-  // 160 KiB (at most 4); otherwise double-buffered register staging.
-  static constexpr bool DMA = (LA == L_ROW) && (LB == L_COL) && SK_KMAJOR_DMA;
+  // M/N-contiguous 16-bit operands are read with transposing LDS reads
+  static constexpr bool TR16 = (DT == DT_F16 || DT == DT_BF16) && SK_MN_TR && SK_KMAJOR_DMA;
+  static constexpr bool TRA = LA == L_COL && TR16;
+  static constexpr bool TRB = LB == L_ROW && TR16;
+  // Both operands copied LDS-direct: as many stages as fit in 160 KiB (at
+  // most 4); otherwise double-buffered register staging.
+  static constexpr bool DMA = (LA == L_ROW || TRA) && (LB == L_COL || TRB) && SK_KMAJOR_DMA;
   static constexpr int NS_FIT = (160 * 1024) / STAGE;
   static constexpr int NSTAGE = DMA ? (NS_FIT > 4 ? 4 : NS_FIT) : 2;
   // LDS-direct copies issued per wave for one iteration
   static constexpr int NLOADS = (BM + BN) / (NT / 8);
+  // LDS read instructions per matrix-core step
+  static constexpr int RD_K = DT == DT_F8 ? 2 : 1;   // K-contiguous fragment
+  static constexpr int NRD = FM * (TRA ? 2 : RD_K) + FN * (TRB ? 2 : RD_K);
   static_assert(WGM * WGN == NW && FM >= 1 && FN >= 1, "wave grid");
   static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile");
-  using StageA = typename StageSel<LA == L_ROW, BM, EB, NT>::type;
-  using StageB = typename StageSel<LB == L_COL, BN, EB, NT>::type;
+  using StageA = typename StageSel<LA == L_ROW, TRA, BM, EB, NT>::type;
+  using StageB = typename StageSel<LB == L_COL, TRB, BN, EB, NT>::type;
 };
 
 template <typename C>
@@ -525,22 +630,81 @@ __device__ __forceinline__ void zero_acc(Acc<C>& acc) {
 // Software-pipelined: the fragments of step s+1 are read from LDS before the
 // matrix-core instructions of step s are issued, so LDS latency overlaps
 // with the previous step's MFMAs.
+// Fragments of one operand out of an LDS stage, for the wave's 32-row
+// blocks i = 0 .. NB-1 starting at tile row `rowbase`.
+//  * K-contiguous stage: lane l reads the 16-byte (e4m3: 32-byte) piece
+//    2s + l/32 (4s + 2(l/32), +1) of row rowbase + 32i + l%32.
+//  * Transposed stage (TR): a ds_read_b64_tr_b16 gives lane i of each
+//    16-lane group the (i mod 4)-th 16-bit element of the 8 bytes addressed
+//    by lane 4j + i/4 of its group, j = 0..3.  Lane p of group g addresses
+//    k-row k0 + 8(g/2) + p/4 at rows 16(g mod 2) + 4(p mod 4) .. +3 of the
+//    block, so lane l receives rows l%32, k-rows k0 + 8(l/32) + 0..3: the
+//    first half of its MFMA operand; a second read at k0 + 4 gives the
+//    other half.  With the stage's chunk swizzle, each group's four k-rows
+//    lie in distinct 64-byte bank groups and the two groups reading one
+//    block take the two halves of each, so a 32-lane half-wave reads all 64
+//    banks once.
+template <typename C, bool TR, int NB, int R>
+struct FragReader {
+  static constexpr int PITCH = R * C::EB;    // bytes per k-row (TR stage)
+  int off[NB];
+  int l32, half;
+
+  __device__ __forceinline__ void init(int rowbase, int lane) {
+    l32 = lane & 31;
+    half = lane >> 5;
+    if constexpr (TR) {
+      static_assert(C::EB == 2 && C::STEPS == 4, "transposing reads: 16-bit types");
+      const int p = lane & 15, g = lane >> 4, j = p >> 2, q = p & 3;
+      const int part = (8 * (g >> 1) + j) * PITCH + 16 * (2 * (g & 1) + (q >> 1)) + 8 * (q & 1);
+#pragma unroll
+      for (int i = 0; i < NB; ++i) off[i] = part + 64 * ((rowbase / 32 + i) ^ j);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) off[i] = (rowbase + 32 * i) * 128;
+    }
+  }
+
+  // Fragment of block i for matrix-core step s (16 k-values for 16-bit types).
+  __device__ __forceinline__ Frag<C::DT> read(const char* op, int i, int s) const {
+    Frag<C::DT> f;
+    if constexpr (TR) {
+      const char* p = op + off[i] + 16 * s * PITCH;
+      const u32x2 lo = __builtin_bit_cast(
+          u32x2, __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                     (__attribute__((address_space(3))) v4s*)(p)));
+      const u32x2 hi = __builtin_bit_cast(
+          u32x2, __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                     (__attribute__((address_space(3))) v4s*)(p + 4 * PITCH)));
+      f.c[0] = u32x4{lo[0], lo[1], hi[0], hi[1]};
+    } else {
+      int lo[2];
+      if constexpr (C::DT == DT_F8) {
+        lo[0] = frag_lane_off(l32, 4 * s + 2 * half);
+        lo[1] = frag_lane_off(l32, 4 * s + 2 * half + 1);
+      } else {
+        lo[0] = frag_lane_off(l32, 2 * s + half);
+        lo[1] = 0;
+      }
+      f = read_frag<C::DT>(op + off[i], lo);
+    }
+    return f;
+  }
+};
+
+template <typename C>
+using ReaderA = FragReader<C, C::TRA, C::FM, C::BM>;
+template <typename C>
+using ReaderB = FragReader<C, C::TRB, C::FN, C::BN>;
+
 template <typename C>
 __device__ __forceinline__ void read_step(Frag<C::DT> (&fa)[C::FM], Frag<C::DT> (&fb)[C::FN],
-                                          const char* LA_, const char* LB_, int l32, int half,
-                                          int s) {
-  int lo[2];
-  if constexpr (C::DT == DT_F8) {
-    lo[0] = frag_lane_off(l32, 4 * s + 2 * half);
-    lo[1] = frag_lane_off(l32, 4 * s + 2 * half + 1);
-  } else {
-    lo[0] = frag_lane_off(l32, 2 * s + half);
-    lo[1] = 0;
-  }
+                                          const ReaderA<C>& ra, const ReaderB<C>& rb,
+                                          const char* opA, const char* opB, int s) {
 #pragma unroll
-  for (int i = 0; i < C::FM; ++i) fa[i] = read_frag<C::DT>(LA_ + i * 32 * 128, lo);
+  for (int i = 0; i < C::FM; ++i) fa[i] = ra.read(opA, i, s);
 #pragma unroll
-  for (int j = 0; j < C::FN; ++j) fb[j] = read_frag<C::DT>(LB_ + j * 32 * 128, lo);
+  for (int j = 0; j < C::FN; ++j) fb[j] = rb.read(opB, j, s);
 }
 
 // Fragment registers are triple-buffered: the reads for step s+2 go to the
@@ -549,31 +713,32 @@ __device__ __forceinline__ void read_step(Frag<C::DT> (&fa)[C::FM], Frag<C::DT> 
 // MFMAs of step s (one LDS read, then a couple of MFMAs).
 template <typename C>
 __device__ __forceinline__ void compute_stage(Acc<C>& acc, const char* stage, int tid) {
-  constexpr int NR = C::FM + C::FN;              // LDS reads per step (per piece)
   constexpr int NM = C::FM * C::FN;              // MFMAs per step
   const int wave = uniform32(tid >> 6);
   const int lane = tid & 63;
-  const int half = lane >> 5;
-  const int l32 = lane & 31;
-  const char* LA_ = stage + ((wave / C::WGN) * C::WM) * 128;
-  const char* LB_ = stage + C::BOFF + ((wave % C::WGN) * C::WN) * 128;
+  ReaderA<C> ra;
+  ReaderB<C> rb;
+  ra.init((wave / C::WGN) * C::WM, lane);
+  rb.init((wave % C::WGN) * C::WN, lane);
+  const char* opA = stage;
+  const char* opB = stage + C::BOFF;
   Frag<C::DT> fa[3][C::FM], fb[3][C::FN];
-  read_step<C>(fa[0], fb[0], LA_, LB_, l32, half, 0);
-  if (C::STEPS > 1) read_step<C>(fa[1], fb[1], LA_, LB_, l32, half, 1);
+  read_step<C>(fa[0], fb[0], ra, rb, opA, opB, 0);
+  if (C::STEPS > 1) read_step<C>(fa[1], fb[1], ra, rb, opA, opB, 1);
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int s = 0; s < C::STEPS; ++s) {
     const int cur = s % 3;
-    if (s + 2 < C::STEPS) read_step<C>(fa[(s + 2) % 3], fb[(s + 2) % 3], LA_, LB_, l32, half, s + 2);
+    if (s + 2 < C::STEPS) read_step<C>(fa[(s + 2) % 3], fb[(s + 2) % 3], ra, rb, opA, opB, s + 2);
 #pragma unroll
     for (int i = 0; i < C::FM; ++i)
 #pragma unroll
       for (int j = 0; j < C::FN; ++j) mma<C::DT>(acc.a[i][j], fa[cur][i], fb[cur][j]);
     if (s + 2 < C::STEPS) {
       // interleave: each LDS read followed by its share of the MFMAs
-      constexpr int PER = NM / NR > 0 ? NM / NR : 1;
+      constexpr int PER = NM / C::NRD > 0 ? NM / C::NRD : 1;
 #pragma unroll
-      for (int r = 0; r < NR * (C::DT == DT_F8 ? 2 : 1); ++r) {
+      for (int r = 0; r < C::NRD; ++r) {
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one DS read
         __builtin_amdgcn_sched_group_barrier(0x008, PER, 0); // MFMAs
       }
@@ -624,7 +789,7 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
-// Multi-stage MAC loop for LDS-direct copies (both operands K-contiguous).
+// Multi-stage MAC loop for LDS-direct copies of both operands.
 //
 // Iteration k works on LDS stage k mod NSTAGE in two halves of its
 // matrix-core steps.  During the first half the fragments of the second
@@ -644,32 +809,19 @@ template <typename C>
 __device__ __forceinline__ void step_with_reads(Acc<C>& acc, const Frag<C::DT> (&fa)[C::FM],
                                                 const Frag<C::DT> (&fb)[C::FN],
                                                 Frag<C::DT> (&ra)[C::FM], Frag<C::DT> (&rb)[C::FN],
-                                                const char* LA_, const char* LB_, int l32,
-                                                int half, int rs) {
-  constexpr int NR = C::FM + C::FN;
+                                                const ReaderA<C>& rda, const ReaderB<C>& rdb,
+                                                const char* opA, const char* opB, int rs) {
   constexpr int NM = C::FM * C::FN;
-  constexpr int NT_ = NR > NM ? NR : NM;
-  int lo[2];
-  if constexpr (C::DT == DT_F8) {
-    lo[0] = frag_lane_off(l32, 4 * rs + 2 * half);
-    lo[1] = frag_lane_off(l32, 4 * rs + 2 * half + 1);
-  } else {
-    lo[0] = frag_lane_off(l32, 2 * rs + half);
-    lo[1] = 0;
-  }
-#pragma unroll
-  for (int i = 0; i < C::FM; ++i) ra[i] = read_frag<C::DT>(LA_ + i * 32 * 128, lo);
-#pragma unroll
-  for (int j = 0; j < C::FN; ++j) rb[j] = read_frag<C::DT>(LB_ + j * 32 * 128, lo);
+  constexpr int NT_ = C::NRD > NM ? C::NRD : NM;
+  read_step<C>(ra, rb, rda, rdb, opA, opB, rs);
 #pragma unroll
   for (int i = 0; i < C::FM; ++i)
 #pragma unroll
     for (int j = 0; j < C::FN; ++j) mma<C::DT>(acc.a[i][j], fa[i], fb[j]);
   // pattern for the scheduler: (one DS read, one MFMA) pairs, then the rest
-  constexpr int NRD = NR * (C::DT == DT_F8 ? 2 : 1);
 #pragma unroll
   for (int t = 0; t < NT_; ++t) {
-    if (t < NRD) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    if (t < C::NRD) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     if (t < NM) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -696,10 +848,10 @@ __device__ __forceinline__ void mac_loop_dma(Acc<C>& acc, const OpTile& oa, cons
   typename C::StageB sb;
   const int wave = uniform32(tid >> 6);
   const int lane = tid & 63;
-  const int half = lane >> 5;
-  const int l32 = lane & 31;
-  const int aoff = ((wave / C::WGN) * C::WM) * 128;
-  const int boff = C::BOFF + ((wave % C::WGN) * C::WN) * 128;
+  ReaderA<C> rda;
+  ReaderB<C> rdb;
+  rda.init((wave / C::WGN) * C::WM, lane);
+  rdb.init((wave % C::WGN) * C::WN, lane);
 
 #pragma unroll
   for (int j = 0; j < NS - 1; ++j) {
@@ -715,7 +867,7 @@ __device__ __forceinline__ void mac_loop_dma(Acc<C>& acc, const OpTile& oa, cons
   Frag<C::DT> fa[ST][C::FM], fb[ST][C::FN];
 #pragma unroll
   for (int s = 0; s < HALF; ++s)
-    read_step<C>(fa[s], fb[s], lds + aoff, lds + boff, l32, half, s);
+    read_step<C>(fa[s], fb[s], rda, rdb, lds, lds + C::BOFF, s);
 
   int slot = 0;
   for (int k = kb; k < ke; ++k) {
@@ -727,8 +879,8 @@ __device__ __forceinline__ void mac_loop_dma(Acc<C>& acc, const OpTile& oa, cons
     // first half: MFMAs of steps [0, HALF), reads of steps [HALF, ST)
 #pragma unroll
     for (int s = 0; s < HALF; ++s)
-      step_with_reads<C>(acc, fa[s], fb[s], fa[s + HALF], fb[s + HALF], cur + aoff, cur + boff,
-                         l32, half, s + HALF);
+      step_with_reads<C>(acc, fa[s], fb[s], fa[s + HALF], fb[s + HALF], rda, rdb, cur,
+                         cur + C::BOFF, s + HALF);
     // copies of k+1 landed in every wave; the stage of k-1 is free
     wait_vmcnt_le<C::NLOADS>((int)imin(NS - 3, imax(ke - 2 - k, 0)));
     __builtin_amdgcn_s_barrier();
@@ -743,8 +895,8 @@ __device__ __forceinline__ void mac_loop_dma(Acc<C>& acc, const OpTile& oa, cons
     // steps [0, HALF)
 #pragma unroll
     for (int s = HALF; s < ST; ++s)
-      step_with_reads<C>(acc, fa[s], fb[s], fa[s - HALF], fb[s - HALF], nxt + aoff, nxt + boff,
-                         l32, half, s - HALF);
+      step_with_reads<C>(acc, fa[s], fb[s], fa[s - HALF], fb[s - HALF], rda, rdb, nxt,
+                         nxt + C::BOFF, s - HALF);
     slot = nslot;
   }
   __syncthreads();   // the stages are reused by the next segment

@@ -70,10 +70,7 @@ def c4(dev, reps=5):
     for name, A, B in [("forward", X, W.t()), ("dX", dY, W), ("dW", dY.t(), X)]:
         M, K = A.shape
         N = B.shape[1]
-        la, _ = api.operand_layout(A)
-        lb, _ = api.operand_layout(B)
-        tile = api.default_tile(M, N, K, torch.bfloat16,
-                                kmajor=(la == api.SK_ROW_MAJOR and lb == api.SK_COL_MAJOR))
+        tile = api.default_tile(M, N, K, torch.bfloat16)
         out = torch.empty((M, N), device=dev)
         cfgs = [api.Config(tile=tile, mode="auto"), api.Config(tile=tile, mode="dp")]
         t_sk, t_dp = _time_all([(lambda c: (lambda: api.gemm(A, B, out=out, config=c,

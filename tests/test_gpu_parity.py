@@ -192,3 +192,18 @@ def test_aligned_rows_with_k_inside_a_chunk(dtype, K, ld):
         for mode in ("sk", "dp"):
             check(M, N, K, dtype, False, True, sk.Config(tile=tile, mode=mode, num_cu=64),
                   lda=ld, ldb=ld, seed=31, pad_nan=True)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+@pytest.mark.parametrize("a_col,b_col", [(True, False), (False, False), (True, True)])
+def test_mn_major_odd_edges_nan_padding(dtype, a_col, b_col):
+    # M/N-contiguous operands copied LDS-direct: M and N odd (the last chunk
+    # of every k-row straddles the matrix edge, and the last element of the
+    # last k-row shares its 4-byte word with nothing valid), ragged K, and
+    # NaN in the row padding, which the straddling chunks read into tile
+    # rows that no output uses
+    for tile in TILES[dtype][:3]:
+        M, N, K = tile[0] * 2 + 37, tile[1] + 19, 392 + 7
+        for mode, g in [("sk", 9), ("dp", 0)]:
+            check(M, N, K, dtype, a_col, b_col, sk.Config(tile=tile, mode=mode, num_cu=g),
+                  seed=41, pad_nan=True)
