@@ -57,19 +57,22 @@ def default_tile(M, N, K, dtype, cus=256):
     """Tile for a problem when none is given.
 
     Larger tiles need fewer operand bytes per flop but leave more compute
-    units idle or split more; measured on the BF16 shape sweep, 256x256 pays
-    once it yields at least ~0.55 tiles per CU (f16/bf16, any layout: both
-    operands are copied LDS-direct), 256x128 once it yields one tile per CU,
-    and 128x128 is best below."""
+    units idle or split more.  Measured on the BF16 shape sweep (auto mode):
+    256x256 (f16/bf16, any layout) pays once it yields ~0.55 tiles per CU, or
+    once its MAC iterations reach 32 per CU, where Stream-K spreads a few
+    long-K tiles over every CU; 256x128 pays from ~0.9 tiles per CU; 128x128
+    is best below."""
     code = DTYPE_CODES[dtype]
     if code == _abi.SK_F32:
         return (128, 128)
     if code == _abi.SK_F8E4M3 and M <= 64:
         return (64, 128)
+    iters = max(1, -(-K // K_PER_ITER[code]))
     t256 = -(-M // 256) * -(-N // 256)
-    if code in (_abi.SK_F16, _abi.SK_BF16) and M >= 256 and N >= 256 and t256 * 100 >= cus * 55:
+    if code in (_abi.SK_F16, _abi.SK_BF16) and M >= 256 and N >= 256 and \
+            (t256 * 100 >= cus * 55 or t256 * iters >= 32 * cus):
         return (256, 256)
-    if M >= 256 and -(-M // 256) * -(-N // 128) >= cus:
+    if M >= 256 and -(-M // 256) * -(-N // 128) * 10 >= cus * 9:
         return (256, 128)
     return (128, 128)
 

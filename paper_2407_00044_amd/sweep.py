@@ -16,7 +16,10 @@ tiling 1 - T / (ceil(T/g) * g) and the measured ratio t_DP / t_SK.
     python -m paper_2407_00044_amd.sweep [--n 64] [--reps 10] [--tune] [--all-tiles]
 
 --all-tiles also times every f16/bf16 tile of the menu under both schedules
-(per-shape "tiles" entries), the data behind the default-tile rule.
+and auto mode in row-major tile order (per-shape "tiles" entries), the data
+behind the default-tile and tile-order rules.
+--tune also runs the autotuner on each shape and reports the tuned best, and
+how often the default (auto mode on the default tile) is within 3% of it.
 """
 import argparse
 import json
@@ -72,14 +75,17 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False)
             row["tiles"] = {}
             for t in ALL_TILES:
                 key = f"{t[0]}x{t[1]}"
-                ts, td = _time_all([go(api.Config(tile=t, mode="auto")),
-                                    go(api.Config(tile=t, mode="dp"))], reps)
-                row["tiles"][key] = {"sk": flops / ts / 1e9, "dp": flops / td / 1e9}
+                ts, tr, td = _time_all([go(api.Config(tile=t, mode="auto")),
+                                        go(api.Config(tile=t, mode="auto", group_m=0)),
+                                        go(api.Config(tile=t, mode="dp"))], reps)
+                pt = api.plan([(M, N, K)], torch.bfloat16, api.Config(tile=t, mode="auto"))
+                row["tiles"][key] = {"sk": flops / ts / 1e9, "sk_rowmajor": flops / tr / 1e9,
+                                     "dp": flops / td / 1e9, "T": pt["T"], "S": pt["S"],
+                                     "g": pt["g"], "group_m": pt["group_m"]}
         if use_tuner:
             best = tune.tune_gemm(A, B, torch.float32, reps=max(3, reps // 2))
             t_best = _time_all([go(best)], reps)[0]
-            row["tuned"] = {"config": [list(best.tile), best.mode, best.dp_tiles],
-                            "tflops": flops / t_best / 1e9}
+            row["tuned"] = {"config": tune.config_to_dict(best), "tflops": flops / t_best / 1e9}
         rows.append(row)
         print(f"# {idx:2d} {M}x{N}x{K} tile {tile} T={T}: SK {row['sk_tflops']:.1f} "
               f"DP {row['dp_tflops']:.1f} TFLOP/s  (DP quant eff {q_eff:.3f})",
@@ -96,7 +102,11 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False)
                "geomean_t_dp_over_t_sk": gmean([r["t_dp_over_t_sk"] for r in rows])}
     if use_tuner:
         tb = [r["tuned"]["tflops"] for r in rows]
-        summary.update({"tuned_min": min(tb), "tuned_geomean": gmean(tb)})
+        # the default policy (auto mode, default tile) against the tuned best
+        ratio = [r["sk_tflops"] / r["tuned"]["tflops"] for r in rows]
+        summary.update({"tuned_min": min(tb), "tuned_geomean": gmean(tb),
+                        "default_within_3pct_of_tuned": sum(x >= 0.97 for x in ratio),
+                        "geomean_default_over_tuned": gmean(ratio)})
     json.dump({"summary": summary, "rows": rows}, out)
     out.write("\n")
     return summary

@@ -82,11 +82,11 @@ def _key(kind, shapes, A, B, out_dtype, num_cu):
 _FIELDS = ("mode", "num_cu", "dp_tiles", "group_m", "min_iters")
 
 
-def _cfg_to_dict(c):
+def config_to_dict(c):
     return {"tile": list(c.tile), **{f: getattr(c, f) for f in _FIELDS}}
 
 
-def _cfg_from_dict(d):
+def config_from_dict(d):
     return api.Config(tile=tuple(d["tile"]), **{f: d[f] for f in _FIELDS if f in d})
 
 
@@ -99,7 +99,7 @@ def tune_gemm(A, B, out_dtype=torch.float32, num_cu=0, reps=10, use_cache=True,
     if use_cache:
         hit = _load_cache().get(key)
         if hit:
-            return _cfg_from_dict(hit["config"])
+            return config_from_dict(hit["config"])
     out = torch.empty((M, N), dtype=out_dtype, device=A.device)
     cands = candidates([(M, N, K)], A.dtype, num_cu)
     ws = api.Workspace(A.device)
@@ -114,7 +114,7 @@ def tune_gemm(A, B, out_dtype=torch.float32, num_cu=0, reps=10, use_cache=True,
     if use_cache:
         with _lock:
             c = _load_cache()
-            c[key] = {"config": _cfg_to_dict(best), "ms": best_ms}
+            c[key] = {"config": config_to_dict(best), "ms": best_ms}
             _store_cache(c)
     return best
 
@@ -127,7 +127,7 @@ def tune_grouped(problems, scales=None, num_cu=0, reps=10, use_cache=True, repor
     if use_cache:
         hit = _load_cache().get(key)
         if hit:
-            return _cfg_from_dict(hit["config"])
+            return config_from_dict(hit["config"])
     cands = candidates(shapes, A0.dtype, num_cu)
     groups = [api.GroupedGemm(problems, config=c, scales=scales) for c in cands]
     results = sorted(zip(time_all([gg.run for gg in groups], reps, rounds=3), cands),
@@ -139,6 +139,6 @@ def tune_grouped(problems, scales=None, num_cu=0, reps=10, use_cache=True, repor
     if use_cache:
         with _lock:
             c = _load_cache()
-            c[key] = {"config": _cfg_to_dict(best), "ms": best_ms}
+            c[key] = {"config": config_to_dict(best), "ms": best_ms}
             _store_cache(c)
     return best

@@ -157,5 +157,15 @@ def test_tuner_cache_round_trip_keeps_every_schedule_field():
     from paper_2407_00044_amd import tune
     c = sk.Config(tile=(256, 128), mode="hybrid", num_cu=200, dp_tiles=128, group_m=0,
                   min_iters=1)
-    d = json.loads(json.dumps(tune._cfg_to_dict(c)))
-    assert tune._cfg_from_dict(d) == c
+    d = json.loads(json.dumps(tune.config_to_dict(c)))
+    assert tune.config_from_dict(d) == c
+
+
+def test_default_tile_rule():
+    bf = torch.bfloat16
+    assert sk.default_tile(3840, 4096, 4096, bf) == (256, 256)       # 240 tiles >= 0.55/CU
+    assert sk.default_tile(4826, 1341, 13813, bf) == (256, 256)     # 114 tiles x 216 iterations
+    assert sk.default_tile(5222, 1459, 1260, bf) == (256, 128)      # 252 tiles >= 0.9/CU
+    assert sk.default_tile(2048, 2048, 4096, bf) == (128, 128)
+    assert sk.default_tile(512, 512, 512, torch.float32) == (128, 128)
+    assert sk.default_tile(48, 1024, 2048, torch.float8_e4m3fn) == (64, 128)

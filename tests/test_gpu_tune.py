@@ -11,7 +11,7 @@ pytestmark = gpu
 
 
 def _as_key(c):
-    return tune._cfg_to_dict(c)
+    return tune.config_to_dict(c)
 
 
 def test_tune_gemm_picks_a_candidate_and_caches_it(tmp_path, monkeypatch):
