@@ -121,19 +121,19 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_key):
-    """HBM bytes per launch of `kernel_key` from the committed counter
-    summary, or None when absent or taken on different kernel sources."""
+def profile_entry(kernel_key):
+    """Counter figures of `kernel_key` from the committed profile summary
+    (HBM bytes per launch, shader clock during the kernel), or {} when absent
+    or taken on different kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
     if d.get("source_hash") != kernel_source_hash():
-        return None
-    e = d.get("kernels", {}).get(kernel_key)
-    return None if e is None else e.get("hbm_bytes_per_launch")
+        return {}
+    return d.get("kernels", {}).get(kernel_key) or {}
 
 
 def copy_leg():
@@ -204,6 +204,7 @@ def main():
 
     ms = result["sk"]
     tflops = flops / ms / 1e9
+    prof = profile_entry("sk_f16_rc_256x128_hybrid")
     line = {
         "metric": "TFLOP/s & % MFMA peak: Stream-K vs data-parallel tiling, same GPU, per dtype",
         "value": round(tflops, 2),
@@ -229,8 +230,15 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(tflops, 2),
                      "peak": PEAK_TFLOPS["f16"], "unit": "TFLOP/s",
                      "frac": round(tflops / PEAK_TFLOPS["f16"], 4),
-                     "traffic": traffic_from_profile("sk_f16_rc_256x128_hybrid")},
+                     "traffic": prof.get("hbm_bytes_per_launch")},
     }
+    sclk = prof.get("sclk_mhz")
+    if sclk:
+        # the published peak assumes 2.4 GHz; the clock under this load is
+        # lower (SQ_CYCLES per shader engine over the kernel's duration)
+        peak_sclk = PEAK_TFLOPS["f16"] * sclk / 2400.0
+        line["sclk_mhz_measured"] = sclk
+        line["pct_mfma_peak_at_measured_sclk"] = round(100 * tflops / peak_sclk, 2)
     if "dp" in result:
         dtf = flops / result["dp"] / 1e9
         line["dp_baseline"] = {"ms": round(result["dp"], 5), "tflops": round(dtf, 2),

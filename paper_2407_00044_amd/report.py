@@ -110,12 +110,17 @@ def c5(dev, reps=5, tile=(128, 128)):
             api.gemm(A, B, out=out, scale_a=sa, scale_b=sb, config=cfg_dp, workspace=ws)
     t_sk, t_gdp, t_sep = _time_all([g_sk.run, g_dp.run, separate], reps)
     fl = sum(2.0 * M * N * K for M, N, K in shapes)
+    # roofline time: each problem at the FP8 MFMA peak or at HBM bandwidth
+    # for its operands and FP32 output, whichever is slower
+    t_roof = sum(max(2.0 * M * N * K / 5033.2e12, (M * K + K * N + 4 * M * N) / 8.0e12)
+                 for M, N, K in shapes) * 1e3
     info = g_sk.info()
     return {"workload": "48 fp8-e4m3 problems, M log-uniform [16,4096], N in {1024,2048,4096}, "
                         "K in {2048,4096,8192}", "tile": list(tile), "gflop": round(fl / 1e9, 1),
             "tiles": info["T"], "stream_k_tiles": info["S"],
             "grouped_sk_tflops": _tf(fl, t_sk), "grouped_dp_tflops": _tf(fl, t_gdp),
-            "separate_dp_tflops": _tf(fl, t_sep)}
+            "separate_dp_tflops": _tf(fl, t_sep), "roofline_us": round(t_roof * 1e3, 1),
+            "grouped_sk_frac_of_roofline": round(t_roof / t_sk, 4)}
 
 
 def padding(dev, reps=10, tile=(256, 128)):

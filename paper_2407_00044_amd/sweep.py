@@ -67,7 +67,11 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False)
         T = p["T"]
         q_eff = T / (math.ceil(T / cus) * cus)
         flops = 2.0 * M * N * K
+        # per-shape roofline: BF16 MFMA peak or HBM bandwidth for A, B, C_in
+        # and C_out (FP32), whichever bounds it
+        roof = min(2516.6, flops / (2 * M * K + 2 * K * N + 8 * M * N) * 8.0)
         row = {"M": M, "N": N, "K": K, "tile": list(tile), "T": T, "S": p["S"],
+               "roofline_tflops": roof,
                "sk_tflops": flops / t_sk / 1e9, "hybrid_tflops": flops / t_hy / 1e9,
                "dp_tflops": flops / t_dp / 1e9,
                "dp_quant_eff": q_eff, "t_dp_over_t_sk": t_dp / t_sk}
@@ -99,6 +103,10 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False)
                "hybrid_min": min(hy), "hybrid_geomean": gmean(hy),
                "sk_beats_dp_geomean": gmean(sk) > gmean(dp), "sk_beats_dp_min": min(sk) > min(dp),
                "mean_predicted_quant_loss": sum(1 - r["dp_quant_eff"] for r in rows) / len(rows),
+               "sk_geomean_frac_of_roofline": gmean([r["sk_tflops"] / r["roofline_tflops"]
+                                                     for r in rows]),
+               "dp_geomean_frac_of_roofline": gmean([r["dp_tflops"] / r["roofline_tflops"]
+                                                     for r in rows]),
                "geomean_t_dp_over_t_sk": gmean([r["t_dp_over_t_sk"] for r in rows])}
     if use_tuner:
         tb = [r["tuned"]["tflops"] for r in rows]
