@@ -20,22 +20,14 @@
 SK_INST(128, 128, 2, 4)
 #else
 // f16 / bf16 / e4m3: large tiles for compute-bound shapes, smaller ones for
-// small or skinny problems.  256x256 runs 8 waves (two per SIMD, 128x64 wave
-// tiles).  Where both operands are copied LDS-direct (every f16/bf16 layout,
-// e4m3 with K-contiguous A and B), 256x128 and 128x128 also run 8 waves
-// (64x64 and 32x64 wave tiles): two waves per SIMD hide LDS and load
-// latency that one wave per SIMD leaves exposed.  e4m3 with an M- or
-// N-major operand transposes bytes in registers while staging and runs out
-// of registers at two waves per SIMD, so there 256x128 and 128x128 keep
-// 4 waves (128x64 and 64x64 wave tiles).
+// small or skinny problems.  Both operands are copied LDS-direct in every
+// layout (M/N-major ones read back with transposing LDS reads), and the
+// three large tiles run 8 waves, two per SIMD, which hide LDS and load
+// latency that one wave per SIMD leaves exposed: 128x64 wave tiles on
+// 256x256, 64x64 on 256x128, 32x64 on 128x128.
 SK_INST(256, 256, 2, 8)
-#if SK_DT != 3 || (SK_LA == 0 && SK_LB == 1)
 SK_INST(256, 128, 4, 8)
 SK_INST(128, 128, 4, 8)
-#else
-SK_INST(256, 128, 2, 4)
-SK_INST(128, 128, 2, 4)
-#endif
 #if SK_DT == 3
 SK_INST(64, 128, 2, 4)
 #endif

@@ -15,11 +15,13 @@
 //    consecutive rows reading the same chunk on distinct banks and repeats
 //    every 32 rows (so per-lane LDS addresses are shared by all 32-row
 //    blocks of a wave); LDS -> MFMA operands with 16-byte reads;
-//  * M/N-contiguous f16/bf16 operands: LDS-direct copies of k-rows as they
-//    lie in memory (chunk c of k-row k at position c ^ 4(k mod 4)), read into
-//    MFMA operands with gfx950's transposing LDS reads (ds_read_b64_tr_b16);
-//  * M/N-contiguous f32/e4m3 operands: 16-byte loads into registers,
-//    transposed there and written to LDS as K-contiguous rows;
+//  * M/N-contiguous f16/bf16/e4m3 operands: LDS-direct copies of k-rows as
+//    they lie in memory (16-byte chunks swizzled per k-row), read into MFMA
+//    operands with gfx950's transposing LDS reads (ds_read_b64_tr_b16 /
+//    _tr_b8);
+//  * M/N-contiguous f32 operands (and e4m3 tiles of 64 rows): 16-byte loads
+//    into registers, transposed there and written to LDS as K-contiguous
+//    rows;
 //  * LDS multi-buffered; 32x32 MFMA blocks accumulate in FP32
 //    (v_mfma_f32_32x32x2_f32, _32x32x16_f16/_bf16, and the block-scaled
 //    32x32x64 f8f6f4 form with unit scales for e4m3).
@@ -44,6 +46,7 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
 
 enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3 };
 enum { L_ROW = 0, L_COL = 1 };
@@ -423,16 +426,27 @@ struct MNMajorStage {
   }
 };
 
-// M/N-contiguous f16/bf16 operand copied into LDS as it lies in memory: the
-// stage holds KE k-rows of R elements (PITCH bytes each).  16-byte chunk c of
-// k-row k sits at position c ^ 4(k mod 4): the four k-rows that one
-// transposing read spans then fall on four different 64-byte bank groups
-// (see TrReader).  One wave copy fills 1 KiB = 64 / CPR k-rows, lane i
+// M/N-contiguous f16/bf16/e4m3 operand copied into LDS as it lies in memory:
+// the stage holds KE k-rows of R elements (PITCH bytes each).  16-byte chunk
+// c of k-row k sits at position c ^ tr_swizzle(k), which spreads the k-rows
+// that one transposing read spans over distinct bank groups (see
+// FragReader).  One wave copy fills 1 KiB = 64 / CPR k-rows, lane i
 // fetching the chunk that the swizzle puts at its position.  k-rows past K
 // and chunks wholly past M (N) are out-of-range offsets (zeros); a chunk that
 // straddles M (N) reads row padding or the next k-row into tile rows that no
 // output uses, and the buffer ends at the 4-byte word holding the last
 // element, so no copy reads past it.
+// Chunk swizzle of a transposed stage: 16-bit elements, 4 k-rows per read,
+// XOR on chunk bits 2-3; 8-bit, 8 k-rows per read, XOR on bits 1-3 (k-rows
+// of 16 or more chunks) or on bits 1-2 by k/2 (8 chunks: two k-rows share a
+// 256-byte bank period).
+template <int EB, int CPR>
+__device__ __forceinline__ int tr_swizzle(int kr) {
+  if constexpr (EB == 2) return 4 * (kr & 3);
+  else if constexpr (CPR >= 16) return 2 * (kr & 7);
+  else return 2 * ((kr >> 1) & 3);
+}
+
 template <int R, int EB, int NT>
 struct MNMajorDMAStage {
   static constexpr int EPC = 16 / EB;
@@ -441,7 +455,8 @@ struct MNMajorDMAStage {
   static constexpr int CPR = PITCH / 16;     // chunks per k-row
   static constexpr int RPC = 1024 / PITCH;   // k-rows per 1 KiB copy
   static constexpr int NI = R / (NT / 8);    // 1 KiB copies per wave
-  static_assert(EB == 2 && CPR >= 16 && CPR <= 64 && R % (NT / 8) == 0, "tile rows");
+  static_assert(((EB == 2 && CPR >= 16) || (EB == 1 && CPR >= 8)) && CPR <= 64 &&
+                    R % (NT / 8) == 0, "tile rows");
 
   __device__ __forceinline__ static bool slow(const OpTile& o, int64_t) { return !o.aligned; }
 
@@ -465,7 +480,7 @@ struct MNMajorDMAStage {
     for (int j = 0; j < NI; ++j) {
       const int jj = wave * NI + j;
       const int kr = jj * RPC + lk;
-      const int c = pc ^ (4 * (kr & 3));
+      const int c = pc ^ tr_swizzle<EB, CPR>(kr);
       const bool ok = kr < kleft && c * EPC < rl;
       const uint32_t off = ok ? kb32 + (uint32_t)kr * ld32 + (uint32_t)(c * 16) : kOOB;
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
@@ -503,7 +518,7 @@ struct MNMajorDMAStage {
     for (int t = 0; t < NCH; ++t) {
       const int idx = tid + t * NT;
       const int kr = idx / CPR, c = idx % CPR;
-      *(u32x4*)(L + kr * PITCH + ((c ^ (4 * (kr & 3))) << 4)) = pack_chunk<EB>(e[t]);
+      *(u32x4*)(L + kr * PITCH + ((c ^ tr_swizzle<EB, CPR>(kr)) << 4)) = pack_chunk<EB>(e[t]);
     }
   }
 };
@@ -592,9 +607,11 @@ struct Cfg {
   static constexpr int BOFF = BM * 128;              // B tile offset in a stage
   static constexpr int STAGE = (BM + BN) * 128;      // LDS bytes per stage
   // M/N-contiguous 16-bit operands are read with transposing LDS reads
+  // (e4m3: tiles of at least 128 rows)
   static constexpr bool TR16 = (DT == DT_F16 || DT == DT_BF16) && SK_MN_TR && SK_KMAJOR_DMA;
-  static constexpr bool TRA = LA == L_COL && TR16;
-  static constexpr bool TRB = LB == L_ROW && TR16;
+  static constexpr bool TR8 = DT == DT_F8 && SK_MN_TR && SK_KMAJOR_DMA;
+  static constexpr bool TRA = LA == L_COL && (TR16 || (TR8 && BM >= 128));
+  static constexpr bool TRB = LB == L_ROW && (TR16 || (TR8 && BN >= 128));
   // Both operands copied LDS-direct: as many stages as fit in 160 KiB (at
   // most 4); otherwise double-buffered register staging.
   static constexpr bool DMA = (LA == L_ROW || TRA) && (LB == L_COL || TRB) && SK_KMAJOR_DMA;
@@ -604,7 +621,8 @@ struct Cfg {
   static constexpr int NLOADS = (BM + BN) / (NT / 8);
   // LDS read instructions per matrix-core step
   static constexpr int RD_K = DT == DT_F8 ? 2 : 1;   // K-contiguous fragment
-  static constexpr int NRD = FM * (TRA ? 2 : RD_K) + FN * (TRB ? 2 : RD_K);
+  static constexpr int RD_T = DT == DT_F8 ? 4 : 2;   // transposed fragment
+  static constexpr int NRD = FM * (TRA ? RD_T : RD_K) + FN * (TRB ? RD_T : RD_K);
   static_assert(WGM * WGN == NW && FM >= 1 && FN >= 1, "wave grid");
   static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile");
   using StageA = typename StageSel<LA == L_ROW, TRA, BM, EB, NT>::type;
@@ -634,16 +652,22 @@ __device__ __forceinline__ void zero_acc(Acc<C>& acc) {
 // blocks i = 0 .. NB-1 starting at tile row `rowbase`.
 //  * K-contiguous stage: lane l reads the 16-byte (e4m3: 32-byte) piece
 //    2s + l/32 (4s + 2(l/32), +1) of row rowbase + 32i + l%32.
-//  * Transposed stage (TR): a ds_read_b64_tr_b16 gives lane i of each
-//    16-lane group the (i mod 4)-th 16-bit element of the 8 bytes addressed
-//    by lane 4j + i/4 of its group, j = 0..3.  Lane p of group g addresses
-//    k-row k0 + 8(g/2) + p/4 at rows 16(g mod 2) + 4(p mod 4) .. +3 of the
-//    block, so lane l receives rows l%32, k-rows k0 + 8(l/32) + 0..3: the
-//    first half of its MFMA operand; a second read at k0 + 4 gives the
-//    other half.  With the stage's chunk swizzle, each group's four k-rows
-//    lie in distinct 64-byte bank groups and the two groups reading one
-//    block take the two halves of each, so a 32-lane half-wave reads all 64
-//    banks once.
+//  * Transposed 16-bit stage (TR): a ds_read_b64_tr_b16 gives lane i of
+//    each 16-lane group the (i mod 4)-th 16-bit element of the 8 bytes
+//    addressed by lane 4j + i/4 of its group, j = 0..3.  Lane p of group g
+//    addresses k-row k0 + 8(g/2) + p/4 at rows 16(g mod 2) + 4(p mod 4) ..
+//    +3 of the block, so lane l receives row l%32, k-rows k0 + 8(l/32) +
+//    0..3: the first half of its MFMA operand; a second read at k0 + 4 gives
+//    the other half.  With the stage's chunk swizzle, each group's four
+//    k-rows lie in distinct 64-byte bank groups and the two groups reading
+//    one block take the two halves of each, so a 32-lane half-wave reads all
+//    64 banks once.
+//  * Transposed e4m3 stage: ds_read_b64_tr_b8 gives lane i the (i mod 8)-th
+//    byte of the 8 bytes addressed by lane 2j + i/8, j = 0..7.  Lane p of
+//    group g addresses k-row k0 + 32(g/2) + p/2 at rows 16(g mod 2) +
+//    8(p mod 2) .. +7, so lane l receives row l%32, k-rows k0 + 32(l/32) +
+//    0..7; four reads (k0 + 8r) give its 32 k-values.  The swizzle puts a
+//    group pair's eight k-rows on eight distinct 32-byte bank groups.
 template <typename C, bool TR, int NB, int R>
 struct FragReader {
   static constexpr int PITCH = R * C::EB;    // bytes per k-row (TR stage)
@@ -653,12 +677,19 @@ struct FragReader {
   __device__ __forceinline__ void init(int rowbase, int lane) {
     l32 = lane & 31;
     half = lane >> 5;
-    if constexpr (TR) {
-      static_assert(C::EB == 2 && C::STEPS == 4, "transposing reads: 16-bit types");
+    if constexpr (TR && C::EB == 2) {
+      static_assert(C::STEPS == 4, "16 k-values per step");
       const int p = lane & 15, g = lane >> 4, j = p >> 2, q = p & 3;
       const int part = (8 * (g >> 1) + j) * PITCH + 16 * (2 * (g & 1) + (q >> 1)) + 8 * (q & 1);
 #pragma unroll
       for (int i = 0; i < NB; ++i) off[i] = part + 64 * ((rowbase / 32 + i) ^ j);
+    } else if constexpr (TR) {
+      static_assert(C::EB == 1 && C::STEPS == 2 && PITCH >= 128, "64 k-values per step");
+      const int p = lane & 15, g = lane >> 4, j = p >> 1, q = p & 1;
+      const int sw = PITCH >= 256 ? j : (j >> 1);   // chunk-pair XOR of the swizzle
+      const int part = (32 * (g >> 1) + j) * PITCH + 16 * (g & 1) + 8 * q;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) off[i] = part + 32 * ((rowbase / 32 + i) ^ sw);
     } else {
 #pragma unroll
       for (int i = 0; i < NB; ++i) off[i] = (rowbase + 32 * i) * 128;
@@ -668,7 +699,16 @@ struct FragReader {
   // Fragment of block i for matrix-core step s (16 k-values for 16-bit types).
   __device__ __forceinline__ Frag<C::DT> read(const char* op, int i, int s) const {
     Frag<C::DT> f;
-    if constexpr (TR) {
+    if constexpr (TR && C::EB == 1) {
+      const char* p = op + off[i] + 64 * s * PITCH;
+      v2i r[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        r[t] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
+            (__attribute__((address_space(3))) v2i*)(p + 8 * t * PITCH));
+      f.c[0] = u32x4{(uint32_t)r[0][0], (uint32_t)r[0][1], (uint32_t)r[1][0], (uint32_t)r[1][1]};
+      f.c[1] = u32x4{(uint32_t)r[2][0], (uint32_t)r[2][1], (uint32_t)r[3][0], (uint32_t)r[3][1]};
+    } else if constexpr (TR) {
       const char* p = op + off[i] + 16 * s * PITCH;
       const u32x2 lo = __builtin_bit_cast(
           u32x2, __builtin_amdgcn_ds_read_tr16_b64_v4i16(
