@@ -1,6 +1,7 @@
 """Timings of the other workloads of record, beside the FP16 3840x4096x4096
 headline of bench.py: FP32 512^3 split over 256 workgroups, the BF16 linear
-layer's forward, dX and dW products, and the 48-problem FP8 grouped GEMM.
+layer's forward, dX and dW products, and the 48-problem FP8 grouped GEMM
+(tile and schedule from the autotuner).
 Each Stream-K launch is timed against its data-parallel comparator with
 graph replays (warm-up, rotated order, median; see timing.time_all).
 
@@ -17,7 +18,7 @@ import sys
 
 import torch
 
-from . import api, synth
+from . import api, synth, tune
 from .timing import time_all as _time_all
 
 
@@ -84,10 +85,12 @@ def c4(dev, reps=5):
     return res
 
 
-def c5(dev, reps=5, tile=(128, 128)):
+def c5(dev, reps=5, tile=None):
     """48 FP8-e4m3 problems (synth.grouped_shapes), per-tensor amax scales,
-    FP32 outputs: one grouped Stream-K launch (auto) vs one grouped
-    data-parallel launch vs 48 separate data-parallel launches, equal tiles."""
+    FP32 outputs: one grouped Stream-K launch vs one grouped data-parallel
+    launch vs 48 separate data-parallel launches, equal tiles.  The grouped
+    launch's tile and schedule come from the autotuner (tune.tune_grouped)
+    unless `tile` is given (then auto mode on that tile)."""
     shapes = synth.grouped_shapes()
     probs, scales = [], []
     for i, (M, N, K) in enumerate(shapes):
@@ -99,11 +102,16 @@ def c5(dev, reps=5, tile=(128, 128)):
         B = (b / sb).to(torch.float8_e4m3fn).t()          # K x N, column-major
         probs.append((A, B, torch.empty((M, N), device=dev)))
         scales.append((sa, sb))
-    g_sk = api.GroupedGemm(probs, config=api.Config(tile=tile, mode="auto"), scales=scales)
-    g_dp = api.GroupedGemm(probs, config=api.Config(tile=tile, mode="dp"), scales=scales)
+    if tile is None:
+        cfg = tune.tune_grouped(probs, scales=scales, reps=3)
+        tuned = tune.config_to_dict(cfg)
+    else:
+        cfg, tuned = api.Config(tile=tile, mode="auto"), None
+    cfg_dp = api.Config(tile=cfg.tile, mode="dp")
+    g_sk = api.GroupedGemm(probs, config=cfg, scales=scales)
+    g_dp = api.GroupedGemm(probs, config=cfg_dp, scales=scales)
     ws = api.Workspace(dev)
     ws.get(64 << 20, torch.cuda.current_stream().cuda_stream)
-    cfg_dp = api.Config(tile=tile, mode="dp")
 
     def separate():
         for (A, B, out), (sa, sb) in zip(probs, scales):
@@ -116,8 +124,8 @@ def c5(dev, reps=5, tile=(128, 128)):
                  for M, N, K in shapes) * 1e3
     info = g_sk.info()
     return {"workload": "48 fp8-e4m3 problems, M log-uniform [16,4096], N in {1024,2048,4096}, "
-                        "K in {2048,4096,8192}", "tile": list(tile), "gflop": round(fl / 1e9, 1),
-            "tiles": info["T"], "stream_k_tiles": info["S"],
+                        "K in {2048,4096,8192}", "tile": list(cfg.tile), "config": tuned,
+            "gflop": round(fl / 1e9, 1), "tiles": info["T"], "stream_k_tiles": info["S"],
             "grouped_sk_tflops": _tf(fl, t_sk), "grouped_dp_tflops": _tf(fl, t_gdp),
             "separate_dp_tflops": _tf(fl, t_sep), "roofline_us": round(t_roof * 1e3, 1),
             "grouped_sk_frac_of_roofline": round(t_roof / t_sk, 4)}
