@@ -16,10 +16,10 @@ from paper_2407_00044_amd import synth
 pytestmark = gpu
 
 
-def build(shapes, dtype, seed0, dist="normal"):
+def build(shapes, dtype, seed0, dist="normal", a_col=False, b_col=True):
     ops = []
     for i, (M, N, K) in enumerate(shapes):
-        A, B = make_inputs(M, N, K, dtype, False, True, seed0 + i, dist)
+        A, B = make_inputs(M, N, K, dtype, a_col, b_col, seed0 + i, dist)
         out = torch.full((M, N), float("nan"), device=dev())
         ops.append((A, B, out))
     return ops
@@ -91,3 +91,15 @@ def test_c5_fp8_grouped_48_problems_graph():
                      rows_per_problem=6, replays=10)
     info = gg.info()
     assert info["nprobs"] == 48 and info["T"] > 0
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "e4m3"])
+@pytest.mark.parametrize("a_col,b_col", [(True, False), (False, False), (True, True)])
+def test_grouped_m_n_major_layouts(dtype, a_col, b_col):
+    # one grouped launch whose operands are M- or N-contiguous (copied into
+    # LDS as k-rows and read back transposed), ragged in every dimension
+    shapes = [(300, 200, 520), (129, 257, 1000), (513, 130, 96), (64, 384, 777)]
+    for tile in [(128, 128), (256, 128)]:
+        for mode in ["sk", "hybrid"]:
+            ops = build(shapes, dtype, 700, a_col=a_col, b_col=b_col)
+            check_group(ops, sk.Config(tile=tile, mode=mode, num_cu=29))
