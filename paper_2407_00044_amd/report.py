@@ -11,7 +11,9 @@ distributions (timing only; the parity tests use synth.py's FP64 draws).
     python -m paper_2407_00044_amd.report [--extra]
 
 --extra adds the report's two experiments on MI355X: the padding ablation of
-Table 1 and Stream-K throughput against the "Compute Units" count.
+Table 1 and Stream-K throughput against the "Compute Units" count, and the
+data-parallel + Stream-K split variants (two-tile rule, one-tile remainder,
+all Stream-K, auto, data-parallel).
 """
 import json
 import sys
@@ -188,11 +190,43 @@ def compute_units(dev, reps=10):
     return out
 
 
+def hybrid_variants(dev, reps=10, tile=(256, 128)):
+    """Data-parallel + Stream-K splits on FP16 (256 CUs): the two-tile rule
+    (S = T mod g + g), the one-tile remainder (S = T mod g: Stream-K only for
+    the last, partial wave), all tiles Stream-K, the auto policy and the
+    data-parallel grid."""
+    ws = api.Workspace(dev)
+    ws.get(96 << 20, torch.cuda.current_stream().cuda_stream)
+    cus, _ = api.device_query(api.Config(tile=tile), torch.float16)
+    out = {"tile": list(tile)}
+    for M, N, K in [(3840, 4096, 4096), (1920, 2000, 2000), (480, 512, 512)]:
+        A = _uniform((M, K), 2, dev).half()
+        Bt = _uniform((N, K), 3, dev).half()
+        o = torch.empty((M, N), device=dev)
+        T = -(-M // tile[0]) * -(-N // tile[1])
+        cfgs = {"two_tile": api.Config(tile=tile, mode="hybrid"),
+                "one_tile": api.Config(tile=tile, mode="hybrid", dp_tiles=T - T % cus),
+                "all_stream_k": api.Config(tile=tile, mode="sk"),
+                "auto": api.Config(tile=tile, mode="auto"),
+                "dp": api.Config(tile=tile, mode="dp")}
+        ts = _time_all([(lambda c: (lambda: api.gemm(A, Bt.t(), out=o, config=c,
+                                                       workspace=ws)))(c) for c in cfgs.values()],
+                       reps)
+        fl = 2.0 * M * N * K
+        row = {"tiles": T}
+        for (name, c), t in zip(cfgs.items(), ts):
+            row[name] = {"stream_k_tiles": api.plan([(M, N, K)], torch.float16, c)["S"],
+                         "tflops": _tf(fl, t)}
+        out[f"{M}x{N}x{K}"] = row
+    return out
+
+
 def run_all(dev, extra=False):
     out = {}
     todo = [("c1", c1), ("c4", c4), ("c5", c5)]
     if extra:
-        todo += [("padding", padding), ("compute_units", compute_units)]
+        todo += [("padding", padding), ("compute_units", compute_units),
+                 ("hybrid_variants", hybrid_variants)]
     for name, fn in todo:
         out[name] = fn(dev)
         print(f"# {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
