@@ -38,12 +38,16 @@ def _load_cache():
 
 
 def _store_cache(c):
+    """Writes the cache; an unwritable location only costs re-tuning."""
     p = cache_path()
-    os.makedirs(os.path.dirname(p), exist_ok=True)
     tmp = p + f".tmp{os.getpid()}"
-    with open(tmp, "w") as f:
-        json.dump(c, f, indent=1, sort_keys=True)
-    os.replace(tmp, p)
+    try:
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        with open(tmp, "w") as f:
+            json.dump(c, f, indent=1, sort_keys=True)
+        os.replace(tmp, p)
+    except OSError:
+        pass
 
 
 def _device_key():

@@ -169,3 +169,12 @@ def test_default_tile_rule():
     assert sk.default_tile(2048, 2048, 4096, bf) == (128, 128)
     assert sk.default_tile(512, 512, 512, torch.float32) == (128, 128)
     assert sk.default_tile(48, 1024, 2048, torch.float8_e4m3fn) == (64, 128)
+
+
+def test_tuner_cache_unwritable_location_is_harmless(monkeypatch, tmp_path):
+    from paper_2407_00044_amd import tune
+    blocker = tmp_path / "file"
+    blocker.write_text("x")
+    monkeypatch.setenv("SK_TUNE_CACHE", str(blocker / "sub" / "tune.json"))
+    tune._store_cache({"k": 1})                 # parent is a file: cannot be created
+    assert tune._load_cache() == {}
