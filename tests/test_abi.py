@@ -178,3 +178,24 @@ def test_tuner_cache_unwritable_location_is_harmless(monkeypatch, tmp_path):
     monkeypatch.setenv("SK_TUNE_CACHE", str(blocker / "sub" / "tune.json"))
     tune._store_cache({"k": 1})                 # parent is a file: cannot be created
     assert tune._load_cache() == {}
+
+
+def test_tile_span_limit_and_large_problems():
+    # buffer offsets are 32-bit relative to a tile's first element: a tile
+    # whose furthest element lies 2^31 bytes or more away is rejected
+    lib = sk.load()
+    cfg = sk.Config(tile=(128, 128), num_cu=256).c_struct(_abi.SK_BF16)
+    info = _abi.SkPlanInfo()
+    K = 64
+    near = (2 ** 31 // 2 - K) // 127                 # 127 * lda + K elements just fit
+    p = _abi.SkProblem(4096, 4096, K, 0, 1, near, K, 4096, _abi.SK_BF16, 0, 1, 0, 1, 1)
+    assert lib.sk_plan(ctypes.byref(p), 1, ctypes.byref(cfg), ctypes.byref(info)) == _abi.SK_OK
+    p.lda = near + 1
+    assert lib.sk_plan(ctypes.byref(p), 1, ctypes.byref(cfg), ctypes.byref(info)) == \
+        _abi.SK_ERR_UNSUPPORTED
+    # a large problem: 65536^3 on 128x128 tiles, 256 workgroups
+    big = _abi.SkProblem(65536, 65536, 65536, 0, 1, 65536, 65536, 65536, _abi.SK_BF16, 0,
+                         1, 0, 1, 1)
+    hyb = sk.Config(tile=(128, 128), num_cu=256, mode="hybrid").c_struct(_abi.SK_BF16)
+    assert lib.sk_plan(ctypes.byref(big), 1, ctypes.byref(hyb), ctypes.byref(info)) == _abi.SK_OK
+    assert info.T == 512 * 512 and info.S == 0        # T mod g == 0: pure data-parallel
