@@ -32,8 +32,10 @@ applied):
       tiles, so that no workgroup gets much less than m iterations.  m = 0
       selects m = ceil(I_mean / c) with I_mean = ceil(W_all / T) and c the
       largest integer >= 1 with f c^2 <= I_mean: if one partial tile costs
-      about f MAC iterations (store, wait, load and add; f = max(4,
-      BM*BN/8192), measured), a tile of I iterations split into c pieces
+      about f MAC iterations (store, wait, load and add; measured:
+      f = max(4, BM*BN/8192) for 16-bit and e4m3 iterations, f = max(1,
+      BM*BN/32768) for FP32 iterations of 32 K-values, which take ~4.5x as
+      long), a tile of I iterations split into c pieces
       takes about I/c + f(c - 1) iteration times, least near c = sqrt(I/f);
       with c = 1 tiles are not split at all.  m = 1 keeps g.  Steps (3)-(5)
       use g'.
@@ -119,8 +121,11 @@ class Plan:
     group_m: int = 0     # tile order used
 
 
-def fixup_cost(block_m, block_n):
-    """Step (2b): MAC iterations one partial tile costs (measured)."""
+def fixup_cost(block_m, block_n, block_k):
+    """Step (2b): MAC iterations one partial tile costs (measured): FP32
+    iterations (32 K-values) are ~4.5x longer than 16-bit / e4m3 ones."""
+    if block_k == 32:
+        return max(1, block_m * block_n // 32768)
     return max(4, block_m * block_n // 8192)
 
 
@@ -161,7 +166,7 @@ def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
             local.append((p, u, tm, tn))
             iters.append(I)
     T = len(local)
-    f = fixup_cost(block_m, block_n)
+    f = fixup_cost(block_m, block_n, block_k)
     if mode != MODE_DP:
         g = grid_floor(g, iters, min_iters, f)
     if mode == MODE_DP:

@@ -154,7 +154,7 @@ static bool offsets_fit(const sk_problem& p, int64_t bm, int64_t bn) {
 
 // Grid floor: with m = min_iters > 1 a Stream-K launch of a small problem
 // uses max(1, W_all / m) < g workgroups.  Automatic m (min_iters = 0): one
-// partial tile costs about f = fixup_iters(BM, BN) MAC iterations of the
+// partial tile costs about f = fixup_iters(BM, BN, BK) MAC iterations of the
 // finisher's time, so a tile of I iterations split into c pieces takes
 // about I/c + f(c-1) iteration times; c is the largest integer >= 1 with
 // f c^2 <= I_mean and m = ceil(I_mean/c).
@@ -249,7 +249,7 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
   } else {
     int64_t W_all = 0;
     for (int32_t i = 0; i < n; ++i) W_all += (int64_t)P.descs[i].tm * P.descs[i].tn * P.descs[i].I;
-    const int64_t fix = fixup_iters(bm, bn);
+    const int64_t fix = fixup_iters(bm, bn, bk);
     P.g = grid_floor(g, T, W_all, cfg->min_iters, fix);
     P.S = split_point(T, W_all, P.g, cfg->mode, cfg->dp_tiles, fix);
     // auto mode with nothing to split on one problem: the data-parallel
@@ -276,6 +276,8 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
     P.rho = P.W % P.g;
   }
   P.ws_bytes = P.dp_grid ? 0 : ws_bytes(P.S, P.S > 0 ? P.g : 0, bm, bn);
+  // the fixup addresses all partial slots with 32-bit buffer offsets
+  if (P.S > 0 && P.g * bm * bn * 4 > kMaxIndex) return SK_ERR_UNSUPPORTED;
   P.group_m = resolve_group_m(cfg->group_m, P);
   *out = std::move(P);
   return SK_OK;

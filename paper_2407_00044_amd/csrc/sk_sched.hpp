@@ -51,9 +51,14 @@ SK_HD void tile_coords(int64_t u, int32_t tm, int32_t tn, int32_t group_m,
 }
 
 // Cost of one partial tile (store, wait, load, add) in MAC iterations of
-// the same tile, measured on MI355X: about 4 up to 256x128 tiles, about 8
-// for 256x256.
-SK_HD int64_t fixup_iters(int64_t bm, int64_t bn) { return imax(4, bm * bn / 8192); }
+// the same tile, measured on MI355X.  16-bit and e4m3 iterations (64 / 128
+// K-values): about 4 up to 256x128 tiles, about 8 for 256x256.  An FP32
+// iteration (32 K-values on the FP32 matrix cores) takes ~4.5x as long
+// (2.5 vs 0.55 us for a lone 128x128 workgroup), so there a partial tile
+// costs about one iteration.
+SK_HD int64_t fixup_iters(int64_t bm, int64_t bn, int64_t bk) {
+  return bk == 32 ? imax(1, bm * bn / 32768) : imax(4, bm * bn / 8192);
+}
 
 // Split point S for T tiles (W_all MAC iterations in all) on g workgroups.
 // Hybrid (mode 0): the two-tile rule.  Auto (mode 3): the same, except that

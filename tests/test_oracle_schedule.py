@@ -157,15 +157,15 @@ def test_grid_floor_invariants():
                 if plan.T and plan.W:
                     # no workgroup below the floor unless the grid is one WG
                     im = -(-sum(plan.iters) // plan.T)
-                    mm = m or -(-im // sch.auto_split(im, sch.fixup_cost(bm, bn)))
+                    mm = m or -(-im // sch.auto_split(im, sch.fixup_cost(bm, bn, bk)))
                     assert plan.g == g or plan.g == 1 or sum(plan.iters) // plan.g >= mm
 
 
 def test_auto_mode_cost_rule():
-    # The worked example (9 tiles of 4 iterations, 4 workgroups): Stream-K
-    # would need b + ceil(b/8) + 4 = 9 + 2 + 4 = 15 iteration times against
-    # 3 waves x 4 = 12 for data-parallel, so auto mode splits nothing;
-    # hybrid keeps its two-tile rule (S = 5).
+    # The worked example (9 tiles of 4 FP32 iterations, 4 workgroups):
+    # Stream-K would need b + ceil(b/8) + 1 = 9 + 2 + 1 = 12 iteration times,
+    # no fewer than 3 waves x 4 = 12 for data-parallel, so auto mode splits
+    # nothing; hybrid keeps its two-tile rule (S = 5).
     assert sch.make_plan([(384, 384, 128)], 128, 128, 32, 4, sch.MODE_AUTO).S == 0
     assert sch.make_plan([(384, 384, 128)], 128, 128, 32, 4, sch.MODE_HYBRID).S == 5
     # 3840x4096x4096, 256x128 tiles: 480 tiles x 64 iterations on 256:
@@ -186,8 +186,14 @@ def test_auto_mode_cost_rule():
     # long K, few tiles: 6 tiles x 50 on g' = 17: 18 + 3 + 4 = 25 < 50 -> split
     p = sch.make_plan([(607, 187, 3155)], 256, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
     assert (p.g, p.S) == (17, 6)
-    assert [sch.fixup_cost(*t) for t in [(64, 128), (128, 128), (256, 128), (256, 256)]] == [
+    assert [sch.fixup_cost(*t, 64) for t in [(64, 128), (128, 128), (256, 128), (256, 256)]] == [
         4, 4, 4, 8]
+    assert sch.fixup_cost(128, 128, 128) == 4 and sch.fixup_cost(128, 128, 32) == 1
+    # FP32 512^3 on 128x128x32: 16 tiles of 16 iterations; f = 1, c = 4
+    # (1 * 4^2 <= 16 < 1 * 5^2), m = 4, g' = 256 // 4 = 64 workgroups: every
+    # tile in 4 pieces of 4 iterations
+    p = sch.make_plan([(512, 512, 512)], 128, 128, 32, 256, sch.MODE_SK, min_iters=0)
+    assert (p.g, p.q, p.rho) == (64, 4, 0)
 
 
 def test_group_m_tile_order_is_a_bijection():
