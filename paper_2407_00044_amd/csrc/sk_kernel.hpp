@@ -1114,43 +1114,32 @@ __device__ __forceinline__ void store_partial(const Acc<C>& acc, float* slot, in
       }
 }
 
-// acc += the partial tiles of peers 1..npeers (slots first, first + BM*BN,
-// ...), in increasing peer order, element by element in FP32.  The loads
-// run one block ahead, also across peers: the next peer's first block is in
-// flight while the current peer's last block is added, so the load latency
-// is exposed once, not once per peer.
 template <typename C>
-__device__ __forceinline__ void add_partials(Acc<C>& acc, const float* first, int npeers,
-                                             int tid) {
+__device__ __forceinline__ void add_partial(Acc<C>& acc, const float* slot, int tid) {
   constexpr int NB = C::FM * C::FN;
-  static_assert(NB % 2 == 0, "a peer's first block reuses buffer 0");
   asm volatile("" : "+v"(tid));   // addresses are formed here, not hoisted
-  const __amdgpu_buffer_rsrc_t rs =
-      make_rsrc((const char*)first, (int64_t)npeers * C::BM * C::BN * 4);
-  auto load_blk = [&](int y, int b, u32x4 (&dst)[4]) {
-    const int base = y * (C::BM * C::BN * 4);   // bytes; g slots stay below 2^31 (host check)
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc((const char*)slot, (int64_t)C::BM * C::BN * 4);
+  auto load_blk = [&](int b, u32x4 (&dst)[4]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      dst[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, base + ((b * 4 + q) * C::NT + tid) * 16,
-                                                     0, kCpolDevice);
+      dst[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, ((b * 4 + q) * C::NT + tid) * 16, 0,
+                                                     kCpolDevice);
   };
+  // block b+1 is in flight while block b is added
   u32x4 buf[2][4];
-  load_blk(0, 0, buf[0]);
-  for (int y = 0; y < npeers; ++y) {
+  load_blk(0, buf[0]);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      if (b + 1 < NB) load_blk(y, b + 1, buf[(b + 1) & 1]);
-      else if (y + 1 < npeers) load_blk(y + 1, 0, buf[0]);
-      __builtin_amdgcn_sched_barrier(0);
-      const int i = b / C::FN, j = b % C::FN;
+  for (int b = 0; b < NB; ++b) {
+    if (b + 1 < NB) load_blk(b + 1, buf[(b + 1) & 1]);
+    __builtin_amdgcn_sched_barrier(0);
+    const int i = b / C::FN, j = b % C::FN;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const v4f v = __builtin_bit_cast(v4f, buf[b & 1][q]);
+    for (int q = 0; q < 4; ++q) {
+      const v4f v = __builtin_bit_cast(v4f, buf[b & 1][q]);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc.a[i][j][4 * q + e] += v[e];
-      }
-      __builtin_amdgcn_sched_barrier(0);
+      for (int e = 0; e < 4; ++e) acc.a[i][j][4 * q + e] += v[e];
     }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -1327,7 +1316,8 @@ __global__ __launch_bounds__(C::NT, 1) void sk_gemm_kernel(KParams P) {
     }
     if (w.role == R_FINISH) {
       wait_arrivals(P, P.flags + w.tr.t, w.npeers);
-      add_partials<C>(acc, P.slots + (x + 1) * (int64_t)(C::BM * C::BN), w.npeers, tid);
+      for (int y = 1; y <= w.npeers; ++y)
+        add_partial<C>(acc, P.slots + (x + y) * (int64_t)(C::BM * C::BN), tid);
       if (tid == 0)
         __hip_atomic_store(P.flags + w.tr.t, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
