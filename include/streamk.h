@@ -88,9 +88,11 @@ typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
  *                   no persistence, no fixup, no workspace.
  *   SK_MODE_AUTO    SK_MODE_HYBRID, except that S = 0 (no tile is split)
  *                   when Stream-K's even share b = ceil(W_all/g), plus an
- *                   eighth for lost L2 reuse, plus one partial tile (f =
- *                   max(4, BM*BN/8192) MAC iterations of fixup) is no
- *                   shorter than the data-parallel waves:
+ *                   eighth for lost L2 reuse, plus one partial tile (f MAC
+ *                   iterations of fixup: max(4, BM*BN/8192) for 16-bit and
+ *                   e4m3 tiles, max(1, BM*BN/32768) for FP32, whose
+ *                   iterations take ~4.5x longer) is no shorter than the
+ *                   data-parallel waves:
  *                   b + ceil(b/8) + f >= ceil(T/g) * ceil(W_all/T), W_all =
  *                   MAC iterations of all tiles, g after the grid floor.
  *                   Constants measured on MI355X; not in the report. */
@@ -152,8 +154,8 @@ typedef struct {
                           that a split tile has few contributors when the
                           problem is small.  0 = automatic: m =
                           ceil(I / c), I = ceil(W_all / T), c the largest
-                          integer >= 1 with f c^2 <= I, f = max(4,
-                          BM*BN/8192); 1 = keep g.
+                          integer >= 1 with f c^2 <= I, f the fixup cost
+                          of SK_MODE_AUTO; 1 = keep g.
                           sk_plan_info.g reports g'. */
 } sk_config;
 
