@@ -207,3 +207,22 @@ def test_mn_major_odd_edges_nan_padding(dtype, a_col, b_col):
         for mode, g in [("sk", 9), ("dp", 0)]:
             check(M, N, K, dtype, a_col, b_col, sk.Config(tile=tile, mode=mode, num_cu=g),
                   seed=41, pad_nan=True)
+
+
+@pytest.mark.parametrize("dtype,bound", [("f32", 1e-6), ("f16", 1e-3), ("bf16", 8e-3),
+                                         ("e4m3", 0.1)])
+def test_error_against_unrounded_inputs_reported(dtype, bound):
+    # parity is judged against the FP64 product of the rounded inputs the GPU
+    # sees; the error against the product of the unrounded FP64 draws is
+    # reported beside it and stays within the input format's rounding
+    # (unit roundoff 2^-24, 2^-11, 2^-8, 2^-4)
+    M, N, K = 300, 260, 520
+    A, B = make_inputs(M, N, K, dtype, False, True, 61, "uniform")
+    C = run(A, B, sk.Config(tile=TILES[dtype][0], mode="sk", num_cu=23))
+    got = as64(C)
+    err = rel_err(got, oracle(A, B, M, N, K))
+    err_u = rel_err(got, oracle_unrounded(A, B))
+    print(f"{dtype} {M}x{N}x{K}: rel err vs rounded-input oracle {err:.3e}, "
+          f"vs unrounded inputs {err_u:.3e}", flush=True)
+    assert err <= TOL[dtype]
+    assert err_u <= bound
