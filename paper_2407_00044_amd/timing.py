@@ -26,17 +26,24 @@ def graph(fn, reps):
 
 
 def time_all(fns, reps, rounds=None):
-    """Milliseconds per call of each fn, by rotated graph replays (median of
-    `rounds` rounds, default 2 * len(fns) + 1)."""
+    """Milliseconds per call of each fn (median over `rounds` rounds, default
+    2 * len(fns) + 1).  Round r replays the graphs starting at a rotating
+    offset, and every other round in reverse order, so each fn runs in every
+    position and after each of its neighbours: under a power limit the clock
+    a kernel gets depends on what ran just before it."""
     graphs = [graph(fn, reps) for fn in fns]
-    rounds = rounds or 2 * len(fns) + 1
+    n = len(graphs)
+    rounds = rounds or 2 * n + 1
     times = [[] for _ in fns]
     s = torch.cuda.Event(enable_timing=True)
     e = torch.cuda.Event(enable_timing=True)
-    for _ in range(rounds):
-        for i, g in enumerate(graphs):
+    for r in range(rounds):
+        order = [(r // 2 + k) % n for k in range(n)]
+        if r % 2:
+            order.reverse()
+        for i in order:
             s.record()
-            g.replay()
+            graphs[i].replay()
             e.record()
             torch.cuda.synchronize()
             times[i].append(s.elapsed_time(e) / reps)
