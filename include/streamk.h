@@ -88,12 +88,12 @@ typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
  *                   no persistence, no fixup, no workspace.
  *   SK_MODE_AUTO    SK_MODE_HYBRID, except that S = 0 (no tile is split)
  *                   when Stream-K's even share b = ceil(W_all/g), plus an
- *                   eighth for lost L2 reuse, plus one partial tile (f MAC
+ *                   quarter for lost L2 reuse, plus one partial tile (f MAC
  *                   iterations of fixup: max(4, BM*BN/8192) for 16-bit and
  *                   e4m3 tiles, max(1, BM*BN/32768) for FP32, whose
  *                   iterations take ~4.5x longer) is no shorter than the
  *                   data-parallel waves:
- *                   b + ceil(b/8) + f >= ceil(T/g) * ceil(W_all/T), W_all =
+ *                   b + ceil(b/4) + f >= ceil(T/g) * ceil(W_all/T), W_all =
  *                   MAC iterations of all tiles, g after the grid floor.
  *                   Constants measured on MI355X; not in the report. */
 typedef enum {

@@ -44,9 +44,9 @@ applied):
       one workgroup per tile.  Hybrid ("two-tile SK + DP"): S = 0 when
       T mod g == 0, else min(T, T mod g + g).  Auto mode (not in the report):
       the hybrid rule, and S = 0 also when Stream-K cannot beat the
-      data-parallel waves under the cost model of step (2b) with an eighth
+      data-parallel waves under the cost model of step (2b) with a quarter
       added for the L2 reuse that workgroups at different k-phases lose:
-      with b = ceil(W_all / g), when b + ceil(b / 8) + f >=
+      with b = ceil(W_all / g), when b + ceil(b / 4) + f >=
       ceil(T / g) * ceil(W_all / T).  An explicit
       dp_tiles >= 0 sets S = T - min(dp_tiles, T).  Auto mode with S = 0 on a
       single problem launches the DP grid (one workgroup per tile) instead of
@@ -178,7 +178,7 @@ def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
         S = 0 if (g == 0 or T % g == 0) else min(T, T % g + g)
         W_all = sum(iters)
         b = cdiv(W_all, g) if g > 0 else 0
-        if mode == MODE_AUTO and S > 0 and b + cdiv(b, 8) + f >= cdiv(T, g) * cdiv(W_all, T):
+        if mode == MODE_AUTO and S > 0 and b + cdiv(b, 4) + f >= cdiv(T, g) * cdiv(W_all, T):
             S = 0
     if mode != MODE_DP and dp_tiles >= 0:
         S = T - min(dp_tiles, T)

@@ -163,27 +163,30 @@ def test_grid_floor_invariants():
 
 def test_auto_mode_cost_rule():
     # The worked example (9 tiles of 4 FP32 iterations, 4 workgroups):
-    # Stream-K would need b + ceil(b/8) + 1 = 9 + 2 + 1 = 12 iteration times,
-    # no fewer than 3 waves x 4 = 12 for data-parallel, so auto mode splits
+    # Stream-K would need b + ceil(b/4) + 1 = 9 + 3 + 1 = 13 iteration times
+    # against 3 waves x 4 = 12 for data-parallel, so auto mode splits
     # nothing; hybrid keeps its two-tile rule (S = 5).
     assert sch.make_plan([(384, 384, 128)], 128, 128, 32, 4, sch.MODE_AUTO).S == 0
     assert sch.make_plan([(384, 384, 128)], 128, 128, 32, 4, sch.MODE_HYBRID).S == 5
     # 3840x4096x4096, 256x128 tiles: 480 tiles x 64 iterations on 256:
-    # 120 + 15 + 4 = 139 >= 2 x 64 = 128 -> data-parallel, and with nothing
+    # 120 + 30 + 4 = 154 >= 2 x 64 = 128 -> data-parallel, and with nothing
     # split on a single problem the launch is the DP grid (480 workgroups)
     p = sch.make_plan([(3840, 4096, 4096)], 256, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
     assert (p.S, p.W, p.g, p.dp_grid) == (0, 0, 480, True)
     # ... but a grouped launch stays on the persistent grid
     p = sch.make_plan([(3840, 4096, 4096)] * 2, 256, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
     assert (p.S, p.g, p.dp_grid) == (0, 256, False)
-    # 2190x3876x1024 on 128x128: 558 tiles x 16 iterations on 256: b = 35,
-    # 35 + 5 + 4 = 44 < 3 x 16 = 48 -> two-tile rule, S = 558 mod 256 + 256
-    p = sch.make_plan([(2190, 3876, 1024)], 128, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
+    # 2190x3876x2048 on 128x128: 558 tiles x 32 iterations on 256: b = 70,
+    # 70 + 18 + 4 = 92 < 3 x 32 = 96 -> two-tile rule, S = 558 mod 256 + 256
+    p = sch.make_plan([(2190, 3876, 2048)], 128, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
     assert (p.T, p.S) == (558, 302)
-    # ... but on 256x256 (fixup 8): 144 tiles, b = 9, 9 + 2 + 8 >= 16 -> DP
+    # with K = 1024 (16 iterations): b = 35, 35 + 9 + 4 = 48 >= 48 -> DP
+    p = sch.make_plan([(2190, 3876, 1024)], 128, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
+    assert (p.T, p.S, p.dp_grid) == (558, 0, True)
+    # ... and on 256x256 (fixup 8): 144 tiles, b = 9, 9 + 3 + 8 >= 16 -> DP
     p = sch.make_plan([(2190, 3876, 1024)], 256, 256, 64, 256, sch.MODE_AUTO, min_iters=0)
     assert p.S == 0
-    # long K, few tiles: 6 tiles x 50 on g' = 17: 18 + 3 + 4 = 25 < 50 -> split
+    # long K, few tiles: 6 tiles x 50 on g' = 17: 18 + 5 + 4 = 27 < 50 -> split
     p = sch.make_plan([(607, 187, 3155)], 256, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
     assert (p.g, p.S) == (17, 6)
     assert [sch.fixup_cost(*t, 64) for t in [(64, 128), (128, 128), (256, 128), (256, 256)]] == [
