@@ -93,7 +93,9 @@ typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
  *                   e4m3 tiles, max(1, BM*BN/32768) for FP32, whose
  *                   iterations take ~4.5x longer) is no shorter than the
  *                   data-parallel waves:
- *                   b + ceil(b/4) + f >= ceil(T/g) * ceil(W_all/T), W_all =
+ *                   b + ceil(b/4) + f >= ceil(T/g) * ceil(W_all/T) (FP32
+ *                   iterations, too slow for the L2 loss to show: b + f >=
+ *                   ...), W_all =
  *                   MAC iterations of all tiles, g after the grid floor.
  *                   Constants measured on MI355X; not in the report. */
 typedef enum {

@@ -45,9 +45,10 @@ applied):
       T mod g == 0, else min(T, T mod g + g).  Auto mode (not in the report):
       the hybrid rule, and S = 0 also when Stream-K cannot beat the
       data-parallel waves under the cost model of step (2b) with a quarter
-      added for the L2 reuse that workgroups at different k-phases lose:
-      with b = ceil(W_all / g), when b + ceil(b / 4) + f >=
-      ceil(T / g) * ceil(W_all / T).  An explicit
+      added for the L2 reuse that workgroups at different k-phases lose
+      (nothing for FP32 iterations, which move too few bytes per clock for
+      that loss to show): with b = ceil(W_all / g), when
+      b + ceil(b / 4) + f >= ceil(T / g) * ceil(W_all / T) (FP32: b + f).  An explicit
       dp_tiles >= 0 sets S = T - min(dp_tiles, T).  Auto mode with S = 0 on a
       single problem launches the DP grid (one workgroup per tile) instead of
       handing whole tiles round-robin to the persistent workgroups.
@@ -178,7 +179,8 @@ def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
         S = 0 if (g == 0 or T % g == 0) else min(T, T % g + g)
         W_all = sum(iters)
         b = cdiv(W_all, g) if g > 0 else 0
-        if mode == MODE_AUTO and S > 0 and b + cdiv(b, 4) + f >= cdiv(T, g) * cdiv(W_all, T):
+        l2 = 0 if block_k == 32 else cdiv(b, 4)
+        if mode == MODE_AUTO and S > 0 and b + l2 + f >= cdiv(T, g) * cdiv(W_all, T):
             S = 0
     if mode != MODE_DP and dp_tiles >= 0:
         S = T - min(dp_tiles, T)

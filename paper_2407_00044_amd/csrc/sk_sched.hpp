@@ -63,11 +63,12 @@ SK_HD int64_t fixup_iters(int64_t bm, int64_t bn, int64_t bk) {
 // Split point S for T tiles (W_all MAC iterations in all) on g workgroups.
 // Hybrid (mode 0): the two-tile rule.  Auto (mode 3): the same, except that
 // no tile is split when Stream-K's even share b = ceil(W_all/g), a quarter
-// more for the L2 reuse lost by workgroups at different k-phases, plus one
-// partial tile is no shorter than the data-parallel waves:
-// b + ceil(b/4) + fix >= ceil(T/g) * ceil(W_all/T).
+// more for the L2 reuse lost by workgroups at different k-phases (l2 = 1;
+// FP32 iterations move too few bytes per clock for that loss to show:
+// l2 = 0), plus one partial tile is no shorter than the data-parallel waves:
+// b + l2*ceil(b/4) + fix >= ceil(T/g) * ceil(W_all/T).
 SK_HD int64_t split_point(int64_t T, int64_t W_all, int64_t g, int32_t mode, int64_t dp_tiles,
-                          int64_t fix) {
+                          int64_t fix, int64_t l2) {
   int64_t S;
   if (mode == 2) return 0;                 // baseline DP grid
   if (mode == 1) {
@@ -76,7 +77,7 @@ SK_HD int64_t split_point(int64_t T, int64_t W_all, int64_t g, int32_t mode, int
     S = (g <= 0 || T % g == 0) ? 0 : imin(T, T % g + g);
     if (mode == 3 && S > 0) {
       const int64_t b = cdiv(W_all, g);
-      if (b + cdiv(b, 4) + fix >= cdiv(T, g) * cdiv(W_all, T)) S = 0;
+      if (b + l2 * cdiv(b, 4) + fix >= cdiv(T, g) * cdiv(W_all, T)) S = 0;
     }
   }
   if (dp_tiles >= 0) S = T - imin(dp_tiles, T);

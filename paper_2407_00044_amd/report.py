@@ -1,7 +1,8 @@
 """Timings of the other workloads of record, beside the FP16 3840x4096x4096
 headline of bench.py: FP32 512^3 split over 256 workgroups, the BF16 linear
-layer's forward, dX and dW products, and the 48-problem FP8 grouped GEMM
-(tile and schedule from the autotuner).
+layer's forward, dX and dW products, the 48-problem FP8 grouped GEMM
+(tile and schedule from the autotuner), and the headline shape in each input
+type with its MFMA peak.
 Each Stream-K launch is timed against its data-parallel comparator with
 graph replays (warm-up, rotated order, median; see timing.time_all).
 
@@ -133,6 +134,39 @@ def c5(dev, reps=5, tile=None):
             "grouped_sk_frac_of_roofline": round(t_roof / t_sk, 4)}
 
 
+PEAK = {torch.float32: 157.3, torch.float16: 2516.6, torch.bfloat16: 2516.6,
+        torch.float8_e4m3fn: 5033.2}      # dense MFMA TFLOP/s at 2.4 GHz
+
+
+def per_dtype(dev, reps=5, shape=(3840, 4096, 4096)):
+    """The headline shape in every input type (A row-major, B column-major,
+    FP32 output), default tile: Stream-K (two-tile hybrid), the auto policy
+    and the data-parallel grid, with each type's dense MFMA peak."""
+    M, N, K = shape
+    ws = api.Workspace(dev)
+    ws.get(96 << 20, torch.cuda.current_stream().cuda_stream)
+    out = torch.empty((M, N), device=dev)
+    fl = 2.0 * M * N * K
+    res = {"workload": f"{M}x{N}x{K}, A row-major, B column-major, FP32 output"}
+    for dt in (torch.float32, torch.float16, torch.bfloat16, torch.float8_e4m3fn):
+        a = _uniform((M, K), 7, dev)
+        b = _uniform((N, K), 8, dev)
+        A = a.to(dt)
+        B = b.to(dt).t()
+        tile = api.default_tile(M, N, K, dt)
+        cfgs = {"stream_k": api.Config(tile=tile, mode="hybrid"),
+                "auto": api.Config(tile=tile, mode="auto"),
+                "dp": api.Config(tile=tile, mode="dp")}
+        ts = _time_all([(lambda c: (lambda: api.gemm(A, B, out=out, config=c, workspace=ws)))(c)
+                        for c in cfgs.values()], reps)
+        row = {"tile": list(tile)}
+        for n, t in zip(cfgs, ts):
+            row[n] = {"tflops": _tf(fl, t), "pct_peak": round(100 * fl / t / 1e9 / PEAK[dt], 2)}
+        res[str(dt).split(".")[-1]] = row
+        del A, B
+    return res
+
+
 def padding(dev, reps=10, tile=(256, 128)):
     """The report's padding experiment (Methodology, Results, Table 1) on
     FP16: each shape run unpadded (edges through out-of-range loads and
@@ -223,7 +257,7 @@ def hybrid_variants(dev, reps=10, tile=(256, 128)):
 
 def run_all(dev, extra=False):
     out = {}
-    todo = [("c1", c1), ("c4", c4), ("c5", c5)]
+    todo = [("c1", c1), ("c4", c4), ("c5", c5), ("per_dtype", per_dtype)]
     if extra:
         todo += [("padding", padding), ("compute_units", compute_units),
                  ("hybrid_variants", hybrid_variants)]

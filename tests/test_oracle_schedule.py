@@ -162,12 +162,19 @@ def test_grid_floor_invariants():
 
 
 def test_auto_mode_cost_rule():
-    # The worked example (9 tiles of 4 FP32 iterations, 4 workgroups):
-    # Stream-K would need b + ceil(b/4) + 1 = 9 + 3 + 1 = 13 iteration times
+    # The worked example (9 tiles of 4 16-bit iterations, 4 workgroups):
+    # Stream-K would need b + ceil(b/4) + 4 = 9 + 3 + 4 = 16 iteration times
     # against 3 waves x 4 = 12 for data-parallel, so auto mode splits
     # nothing; hybrid keeps its two-tile rule (S = 5).
-    assert sch.make_plan([(384, 384, 128)], 128, 128, 32, 4, sch.MODE_AUTO).S == 0
-    assert sch.make_plan([(384, 384, 128)], 128, 128, 32, 4, sch.MODE_HYBRID).S == 5
+    assert sch.make_plan([(384, 384, 256)], 128, 128, 64, 4, sch.MODE_AUTO).S == 0
+    assert sch.make_plan([(384, 384, 256)], 128, 128, 64, 4, sch.MODE_HYBRID).S == 5
+    # FP32 iterations (32 K-values) carry no L2 term and f = 1: the same
+    # 9 tiles x 4 iterations need 9 + 1 = 10 < 12 -> two-tile rule (S = 5)
+    assert sch.make_plan([(384, 384, 128)], 128, 128, 32, 4, sch.MODE_AUTO).S == 5
+    # FP32 3840x4096x4096 on 128x128x32: 960 tiles x 128 on 256: 480 + 1 =
+    # 481 < 4 x 128 = 512 -> split (S = 960 mod 256 + 256 = 448)
+    p = sch.make_plan([(3840, 4096, 4096)], 128, 128, 32, 256, sch.MODE_AUTO, min_iters=0)
+    assert (p.T, p.S) == (960, 448)
     # 3840x4096x4096, 256x128 tiles: 480 tiles x 64 iterations on 256:
     # 120 + 30 + 4 = 154 >= 2 x 64 = 128 -> data-parallel, and with nothing
     # split on a single problem the launch is the DP grid (480 workgroups)
