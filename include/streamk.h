@@ -97,6 +97,9 @@ typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
  *                   iterations, too slow for the L2 loss to show: b + f >=
  *                   ...), W_all =
  *                   MAC iterations of all tiles, g after the grid floor.
+ *                   When the data-parallel launch is one partial wave
+ *                   (T < g) and the floor did not shrink g, the left side
+ *                   is taken 9/8 times (T busy workgroups outrun g).
  *                   Constants measured on MI355X; not in the report. */
 typedef enum {
   SK_MODE_HYBRID = 0, SK_MODE_SK = 1, SK_MODE_DP = 2, SK_MODE_AUTO = 3

@@ -48,7 +48,11 @@ applied):
       added for the L2 reuse that workgroups at different k-phases lose
       (nothing for FP32 iterations, which move too few bytes per clock for
       that loss to show): with b = ceil(W_all / g), when
-      b + ceil(b / 4) + f >= ceil(T / g) * ceil(W_all / T) (FP32: b + f).  An explicit
+      b + ceil(b / 4) + f >= ceil(T / g) * ceil(W_all / T) (FP32: b + f).
+      When the DP launch would be one partial wave (T < g') and the floor
+      left g' = g, the Stream-K side is taken 9/8 times (measured: T busy
+      workgroups outrun g busy ones, and predicted gains under ~12% were
+      losses there).  An explicit
       dp_tiles >= 0 sets S = T - min(dp_tiles, T).  Auto mode with S = 0 on a
       single problem launches the DP grid (one workgroup per tile) instead of
       handing whole tiles round-robin to the persistent workgroups.
@@ -168,6 +172,7 @@ def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
             iters.append(I)
     T = len(local)
     f = fixup_cost(block_m, block_n, block_k)
+    g_full = g
     if mode != MODE_DP:
         g = grid_floor(g, iters, min_iters, f)
     if mode == MODE_DP:
@@ -180,8 +185,12 @@ def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
         W_all = sum(iters)
         b = cdiv(W_all, g) if g > 0 else 0
         l2 = 0 if block_k == 32 else cdiv(b, 4)
-        if mode == MODE_AUTO and S > 0 and b + l2 + f >= cdiv(T, g) * cdiv(W_all, T):
-            S = 0
+        if mode == MODE_AUTO and S > 0:
+            sk_cost = b + l2 + f
+            if T < g and g == g_full:         # one partial data-parallel wave
+                sk_cost = sk_cost * 9 / 8
+            if sk_cost >= cdiv(T, g) * cdiv(W_all, T):
+                S = 0
     if mode != MODE_DP and dp_tiles >= 0:
         S = T - min(dp_tiles, T)
     dp_grid = mode == MODE_DP or (mode == MODE_AUTO and S == 0 and len(problems) == 1)

@@ -251,7 +251,7 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
     for (int32_t i = 0; i < n; ++i) W_all += (int64_t)P.descs[i].tm * P.descs[i].tn * P.descs[i].I;
     const int64_t fix = fixup_iters(bm, bn, bk);
     P.g = grid_floor(g, T, W_all, cfg->min_iters, fix);
-    P.S = split_point(T, W_all, P.g, cfg->mode, cfg->dp_tiles, fix, bk == 32 ? 0 : 1);
+    P.S = split_point(T, W_all, P.g, cfg->mode, cfg->dp_tiles, fix, bk == 32 ? 0 : 1, g);
     // auto mode with nothing to split on one problem: the data-parallel
     // grid itself (the hardware hands out tiles as workgroups finish, which
     // beats a fixed round-robin of whole tiles over persistent workgroups)

@@ -66,9 +66,13 @@ SK_HD int64_t fixup_iters(int64_t bm, int64_t bn, int64_t bk) {
 // more for the L2 reuse lost by workgroups at different k-phases (l2 = 1;
 // FP32 iterations move too few bytes per clock for that loss to show:
 // l2 = 0), plus one partial tile is no shorter than the data-parallel waves:
-// b + l2*ceil(b/4) + fix >= ceil(T/g) * ceil(W_all/T).
+// b + l2*ceil(b/4) + fix >= ceil(T/g) * ceil(W_all/T).  When the
+// data-parallel grid is one partial wave (T < g) of a launch the grid floor
+// did not shrink (g == g_full), that cost is taken 9/8 times: the T busy
+// workgroups of the data-parallel launch run faster than g busy Stream-K
+// ones (measured: a predicted gain under ~12% was a loss there).
 SK_HD int64_t split_point(int64_t T, int64_t W_all, int64_t g, int32_t mode, int64_t dp_tiles,
-                          int64_t fix, int64_t l2) {
+                          int64_t fix, int64_t l2, int64_t g_full) {
   int64_t S;
   if (mode == 2) return 0;                 // baseline DP grid
   if (mode == 1) {
@@ -77,7 +81,10 @@ SK_HD int64_t split_point(int64_t T, int64_t W_all, int64_t g, int32_t mode, int
     S = (g <= 0 || T % g == 0) ? 0 : imin(T, T % g + g);
     if (mode == 3 && S > 0) {
       const int64_t b = cdiv(W_all, g);
-      if (b + l2 * cdiv(b, 4) + fix >= cdiv(T, g) * cdiv(W_all, T)) S = 0;
+      const int64_t sk = b + l2 * cdiv(b, 4) + fix;
+      const int64_t dp = cdiv(T, g) * cdiv(W_all, T);
+      const bool one_wave = T < g && g == g_full;
+      if ((one_wave ? 9 * sk : 8 * sk) >= 8 * dp) S = 0;
     }
   }
   if (dp_tiles >= 0) S = T - imin(dp_tiles, T);

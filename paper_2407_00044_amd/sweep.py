@@ -1,4 +1,4 @@
-"""BF16 shape sweep: Stream-K vs equal-tile data-parallel tiling.
+"""Shape sweep (BF16 by default): Stream-K vs equal-tile data-parallel tiling.
 
 64 shapes with M, N log-uniform in [128, 8192] and K log-uniform in
 [128, 16384] (seeded); A row-major, B column-major with leading dimensions
@@ -14,8 +14,12 @@ of each schedule, the predicted quantization loss of one-tile-per-workgroup
 tiling 1 - T / (ceil(T/g) * g) and the measured ratio t_DP / t_SK.
 
     python -m paper_2407_00044_amd.sweep [--n 64] [--reps 10] [--tune] [--all-tiles]
+                                         [--dtype bf16|f16|f32|e4m3]
 
---all-tiles also times every f16/bf16 tile of the menu under both schedules
+--dtype runs the same shapes with another input type (leading dimensions
+rounded to 16 bytes of that type; e4m3 with unit scales); the per-shape
+roofline then takes that type's dense MFMA peak.
+--all-tiles also times every 256/128-row tile of the menu for the type under both schedules
 and auto mode in row-major tile order (per-shape "tiles" entries), the data
 behind the default-tile and tile-order rules.
 --tune also runs the autotuner on each shape and reports the tuned best, and
@@ -40,22 +44,30 @@ def gmean(xs):
 ALL_TILES = [(256, 256), (256, 128), (128, 128)]
 
 
-def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False):
+DTYPES = {"bf16": torch.bfloat16, "f16": torch.float16, "f32": torch.float32,
+          "e4m3": torch.float8_e4m3fn}
+ELEM = {torch.bfloat16: 2, torch.float16: 2, torch.float32: 4, torch.float8_e4m3fn: 1}
+PEAK = {torch.bfloat16: 2516.6, torch.float16: 2516.6, torch.float32: 157.3,
+        torch.float8_e4m3fn: 5033.2}
+
+
+def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False,
+        dtype=torch.bfloat16):
     dev = torch.device("cuda", torch.cuda.current_device())
-    cus, _ = api.device_query(api.Config(tile=(256, 128)), torch.bfloat16)
+    cus, _ = api.device_query(api.Config(tile=(128, 128)), dtype)
     rows = []
     ws = api.Workspace(dev)
     ws.get(96 << 20, torch.cuda.current_stream().cuda_stream)   # before any capture
     for idx, (M, N, K) in enumerate(synth.sweep_shapes(seed, n)):
         gen = torch.Generator(device=dev)
         gen.manual_seed(300 + idx)
-        lda = synth.ld_aligned(K, 2)
-        ldb = synth.ld_aligned(K, 2)
-        A = torch.randn((M, lda), generator=gen, device=dev).to(torch.bfloat16)[:, :K]
-        B = torch.randn((N, ldb), generator=gen, device=dev).to(torch.bfloat16)[:, :K].t()
+        lda = synth.ld_aligned(K, ELEM[dtype])
+        ldb = synth.ld_aligned(K, ELEM[dtype])
+        A = torch.randn((M, lda), generator=gen, device=dev).to(dtype)[:, :K]
+        B = torch.randn((N, ldb), generator=gen, device=dev).to(dtype)[:, :K].t()
         C = (torch.rand((M, N), generator=gen, device=dev) * 2 - 1)
         outC = torch.empty_like(C)
-        tile = api.default_tile(M, N, K, torch.bfloat16)
+        tile = api.default_tile(M, N, K, dtype)
         cfg_sk = api.Config(tile=tile, mode="auto")
         cfg_hy = api.Config(tile=tile, mode="hybrid")
         cfg_dp = api.Config(tile=tile, mode="dp")
@@ -63,13 +75,14 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False)
         def go(cfg):
             return lambda: api.gemm(A, B, C, beta=0.5, out=outC, config=cfg, workspace=ws)
         t_sk, t_hy, t_dp = _time_all([go(cfg_sk), go(cfg_hy), go(cfg_dp)], reps)
-        p = api.plan([(M, N, K)], torch.bfloat16, cfg_sk)
+        p = api.plan([(M, N, K)], dtype, cfg_sk)
         T = p["T"]
         q_eff = T / (math.ceil(T / cus) * cus)
         flops = 2.0 * M * N * K
-        # per-shape roofline: BF16 MFMA peak or HBM bandwidth for A, B, C_in
-        # and C_out (FP32), whichever bounds it
-        roof = min(2516.6, flops / (2 * M * K + 2 * K * N + 8 * M * N) * 8.0)
+        # per-shape roofline: the input type's dense MFMA peak or HBM
+        # bandwidth (8 TB/s) for A, B, C_in and C_out (FP32), whichever bounds it
+        e = ELEM[dtype]
+        roof = min(PEAK[dtype], flops / (e * M * K + e * K * N + 8 * M * N) * 8.0)
         row = {"M": M, "N": N, "K": K, "tile": list(tile), "T": T, "S": p["S"],
                "roofline_tflops": roof,
                "sk_tflops": flops / t_sk / 1e9, "hybrid_tflops": flops / t_hy / 1e9,
@@ -77,12 +90,12 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False)
                "dp_quant_eff": q_eff, "t_dp_over_t_sk": t_dp / t_sk}
         if all_tiles:
             row["tiles"] = {}
-            for t in ALL_TILES:
+            for t in [x[:2] for x in api.supported_tiles(dtype) if x[:2] in ALL_TILES]:
                 key = f"{t[0]}x{t[1]}"
                 ts, tr, td = _time_all([go(api.Config(tile=t, mode="auto")),
                                         go(api.Config(tile=t, mode="auto", group_m=0)),
                                         go(api.Config(tile=t, mode="dp"))], reps)
-                pt = api.plan([(M, N, K)], torch.bfloat16, api.Config(tile=t, mode="auto"))
+                pt = api.plan([(M, N, K)], dtype, api.Config(tile=t, mode="auto"))
                 row["tiles"][key] = {"sk": flops / ts / 1e9, "sk_rowmajor": flops / tr / 1e9,
                                      "dp": flops / td / 1e9, "T": pt["T"], "S": pt["S"],
                                      "g": pt["g"], "group_m": pt["group_m"]}
@@ -126,9 +139,10 @@ def main():
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--all-tiles", action="store_true")
+    ap.add_argument("--dtype", choices=sorted(DTYPES), default="bf16")
     a = ap.parse_args()
     t0 = time.time()
-    run(a.n, a.reps, a.tune, all_tiles=a.all_tiles)
+    run(a.n, a.reps, a.tune, all_tiles=a.all_tiles, dtype=DTYPES[a.dtype])
     print(f"# sweep done in {time.time() - t0:.1f} s", file=sys.stderr)
 
 

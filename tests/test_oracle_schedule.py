@@ -193,6 +193,19 @@ def test_auto_mode_cost_rule():
     # ... and on 256x256 (fixup 8): 144 tiles, b = 9, 9 + 3 + 8 >= 16 -> DP
     p = sch.make_plan([(2190, 3876, 1024)], 256, 256, 64, 256, sch.MODE_AUTO, min_iters=0)
     assert p.S == 0
+    # one partial data-parallel wave on the full grid: e4m3 6160x303x2722 on
+    # 128x128x128, 147 tiles x 22 on g' = 256 (floor m = 11 leaves 294 > 256):
+    # b = 13, (13 + 4 + 4) * 9/8 = 23.6 >= 22 -> DP (21 alone would split)
+    p = sch.make_plan([(6160, 303, 2722)], 128, 128, 128, 256, sch.MODE_AUTO, min_iters=0)
+    assert (p.T, p.g, p.S, p.dp_grid) == (147, 147, 0, True)
+    # the same shape in BF16 (43 iterations): b = 25, (25 + 7 + 4) * 9/8 =
+    # 40.5 < 43 -> split
+    p = sch.make_plan([(6160, 303, 2722)], 128, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
+    assert (p.T, p.g, p.S) == (147, 256, 147)
+    # T < g' but the floor shrank the grid (g' = 759 // 12 = 63): no 9/8;
+    # b = 13, 13 + 4 + 4 = 21 < 23 -> split
+    p = sch.make_plan([(1286, 292, 1415)], 128, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
+    assert (p.T, p.g, p.S) == (33, 63, 33)
     # long K, few tiles: 6 tiles x 50 on g' = 17: 18 + 5 + 4 = 27 < 50 -> split
     p = sch.make_plan([(607, 187, 3155)], 256, 128, 64, 256, sch.MODE_AUTO, min_iters=0)
     assert (p.g, p.S) == (17, 6)
