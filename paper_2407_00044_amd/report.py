@@ -255,12 +255,20 @@ def hybrid_variants(dev, reps=10, tile=(256, 128)):
     return out
 
 
-def run_all(dev, extra=False):
+def run_all(dev, extra=False, only=None, c5_tile=None):
+    """Every configuration (`extra` adds the experiments), or the named ones;
+    c5_tile runs c5 in auto mode on that tile instead of the tuner's pick."""
     out = {}
-    todo = [("c1", c1), ("c4", c4), ("c5", c5), ("per_dtype", per_dtype)]
-    if extra:
+    todo = [("c1", c1), ("c4", c4), ("c5", lambda d: c5(d, tile=c5_tile)),
+            ("per_dtype", per_dtype)]
+    if extra or only:
         todo += [("padding", padding), ("compute_units", compute_units),
                  ("hybrid_variants", hybrid_variants)]
+    if only:
+        unknown = set(only) - {n for n, _ in todo}
+        if unknown:
+            raise SystemExit(f"unknown configuration(s): {sorted(unknown)}")
+        todo = [(n, f) for n, f in todo if n in only]
     for name, fn in todo:
         out[name] = fn(dev)
         print(f"# {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
@@ -268,5 +276,18 @@ def run_all(dev, extra=False):
     return out
 
 
+def main():
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--extra", action="store_true", help="also the report's experiments")
+    ap.add_argument("--only", default="", help="comma-separated names, e.g. c1,c5")
+    ap.add_argument("--c5-tile", default="", help="e.g. 128x128: no tuner for c5")
+    a = ap.parse_args()
+    only = [x for x in a.only.split(",") if x] or None
+    tile = tuple(int(v) for v in a.c5_tile.split("x")) if a.c5_tile else None
+    print(json.dumps(run_all(torch.device("cuda", 0), extra=a.extra, only=only,
+                             c5_tile=tile)))
+
+
 if __name__ == "__main__":
-    print(json.dumps(run_all(torch.device("cuda", 0), extra="--extra" in sys.argv)))
+    main()
