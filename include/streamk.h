@@ -168,7 +168,8 @@ typedef struct {
 typedef struct {
   int32_t wg;        /* logical workgroup id (tile id for SK_MODE_DP) */
   int32_t problem;   /* index into the problem array */
-  int32_t tile;      /* global tile index (problem-major) */
+  int32_t tile;      /* global tile index (problem-major, problems in the
+                        grouped order of sk_plan) */
   int32_t tile_m, tile_n;   /* tile coordinates inside the problem */
   int32_t k_begin, k_end;   /* MAC iterations [k_begin, k_end) of the tile */
   int32_t role;      /* sk_role */
@@ -202,9 +203,12 @@ sk_status sk_device_query(int32_t* num_cu, int32_t* max_wg_per_cu,
 sk_status sk_supported_tiles(int32_t dtype_ab, int32_t* out, int32_t capacity,
                              int32_t* count);
 
-/* Host-only.  Schedule parameters of `nprobs` problems (concatenated in the
- * given order, as in a grouped launch) under `cfg`.  cfg->num_cu must be > 0
- * when no HIP device is present. */
+/* Host-only.  Schedule parameters of `nprobs` problems (concatenated as in
+ * a grouped launch: by MAC iterations per tile, ceil(K / block_k), largest
+ * first, ties in the given order, so that whole tiles dealt round-robin to
+ * the persistent workgroups balance; SK_MODE_DP keeps the given order; a
+ * reading for grouped launches, which the report does not treat) under `cfg`.  cfg->num_cu must be > 0 when no
+ * HIP device is present. */
 sk_status sk_plan(const sk_problem* probs, int32_t nprobs,
                   const sk_config* cfg, sk_plan_info* info);
 

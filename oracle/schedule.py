@@ -16,7 +16,11 @@ applied):
       tiles, I_p = max(1, ceil(K/BK)) MAC-loop iterations per tile.  (A K = 0
       problem keeps one empty iteration per tile so that its tiles still reach
       the epilogue C = beta*Cin.)
-  (2) Tiles are numbered problem-major; inside a problem tile u maps to
+  (2) Tiles are numbered problem-major, the problems taken by I_p, largest
+      first, ties in the given order (a reading for grouped launches, which
+      the report does not treat: whole tiles then alternate evenly between
+      the persistent workgroups, longest first; DP mode keeps the given
+      order); inside a problem tile u maps to
       (tm, tn) row-major, or, with group_m > 0, band-wise: bands of group_m
       tile rows, walked down the rows first, then across the columns.
       group_m = -1 (automatic; a locality reading, not in the report) is
@@ -161,7 +165,11 @@ def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
               dp_tiles=-1, group_m=0, min_iters=1):
     """Steps (1)-(5) for a list of (M, N, K) problems."""
     local, iters, first = [], [], None
-    for p, (M, N, K) in enumerate(problems):
+    order = list(range(len(problems)))
+    if mode != MODE_DP:                              # stable: ties keep their order
+        order.sort(key=lambda p: -max(1, cdiv(problems[p][2], block_k)))
+    for p in order:
+        M, N, K = problems[p]
         tm = cdiv(M, block_m) if M > 0 else 0
         tn = cdiv(N, block_n) if N > 0 else 0
         I = max(1, cdiv(K, block_k))
@@ -299,15 +307,21 @@ def check(problems, block_m, block_n, block_k, g, mode, segs, dp_tiles=-1,
     onto each problem's tile grid; a workgroup's SK ranges are contiguous in
     the global iteration order.
     """
-    # Independent recomputation of the tile grid (no call into make_plan).
+    # Independent recomputation of the tile grid (no call into make_plan):
+    # step (2)'s order, as one pass per distinct I from the largest down.
     grid = {}
     tile_list = []
-    for p, (M, N, K) in enumerate(problems):
-        tm = cdiv(M, block_m) if M > 0 else 0
-        tn = cdiv(N, block_n) if N > 0 else 0
-        I = max(1, cdiv(K, block_k))
-        for _ in range(tm * tn):
-            tile_list.append((p, I, tm, tn))
+    per_tile_iters = [max(1, cdiv(K, block_k)) for _, _, K in problems]
+    passes = [None] if mode == MODE_DP else sorted(set(per_tile_iters), reverse=True)
+    for want in passes:
+        for p, (M, N, K) in enumerate(problems):
+            I = per_tile_iters[p]
+            if want is not None and I != want:
+                continue
+            tm = cdiv(M, block_m) if M > 0 else 0
+            tn = cdiv(N, block_n) if N > 0 else 0
+            for _ in range(tm * tn):
+                tile_list.append((p, I, tm, tn))
     T = len(tile_list)
     seen_coords = defaultdict(set)
 

@@ -51,6 +51,7 @@ struct Plan {
   int32_t group_m = 0;           // resolved tile order
   bool dp_grid = false;          // one workgroup per tile, no fixup
   std::vector<ProbDesc> descs;   // pointers left null by plan_problems
+  std::vector<int32_t> order;    // descs[i] describes caller problem order[i]
 };
 
 // Per-device facts are queried once and cached (these runtime queries cost
@@ -222,11 +223,23 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
   for (int32_t i = 0; i < n; ++i)
     if (!offsets_fit(probs[i], bm, bn)) return SK_ERR_UNSUPPORTED;
 
+  // Global tile order of a grouped persistent launch: problems by MAC
+  // iterations per tile, most first, ties in the caller's order.  Whole
+  // tiles left to the persistent round-robin then alternate evenly between
+  // the workgroups (longest-first list scheduling); an even Stream-K split
+  // does not depend on the order.  The data-parallel grid keeps the
+  // caller's order (the hardware hands its workgroups out as CUs free up).
   Plan P;
+  P.order.resize(n);
+  for (int32_t i = 0; i < n; ++i) P.order[i] = i;
+  auto iters_of = [&](int32_t i) { return std::max<int64_t>(1, cdiv(probs[i].K, bk)); };
+  if (cfg->mode != SK_MODE_DP)
+    std::stable_sort(P.order.begin(), P.order.end(),
+                     [&](int32_t a, int32_t b) { return iters_of(a) > iters_of(b); });
   P.descs.resize(n);
   int64_t T = 0;
   for (int32_t i = 0; i < n; ++i) {
-    const sk_problem& p = probs[i];
+    const sk_problem& p = probs[P.order[i]];
     ProbDesc& d = P.descs[i];
     memset(&d, 0, sizeof(d));
     d.M = p.M; d.N = p.N; d.K = p.K;
@@ -301,7 +314,7 @@ static void host_segments(const Plan& P, const sk_config* cfg, std::vector<sk_se
     const ProbDesc& d = P.descs[p];
     sk_segment s;
     s.wg = (int32_t)x;
-    s.problem = p;
+    s.problem = P.order[p];
     s.tile = (int32_t)t;
     tile_coords(u, d.tm, d.tn, P.group_m, &s.tile_m, &s.tile_n);
     s.k_begin = kb;
@@ -581,10 +594,11 @@ sk_status sk_grouped_prepare(const sk_problem* probs, const void* const* A,
   const int eb = elem_bytes(probs[0].dtype_ab);
   int32_t all_aligned = 1;
   for (int32_t i = 0; i < nprobs; ++i) {
-    const sk_problem& p = probs[i];
+    const int32_t j = P.order[i];
+    const sk_problem& p = probs[j];
     ProbDesc& d = P.descs[i];
-    d.A = A[i]; d.B = B[i]; d.Cout = C_out[i];
-    d.Cin = C_in ? C_in[i] : nullptr;
+    d.A = A[j]; d.B = B[j]; d.Cout = C_out[j];
+    d.Cin = C_in ? C_in[j] : nullptr;
     const bool empty = p.M == 0 || p.N == 0;
     if (!empty) {
       if (d.Cout == nullptr) return SK_ERR_INVALID_ARG;

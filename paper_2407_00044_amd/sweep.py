@@ -115,6 +115,8 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False,
                "dp_min": min(dp), "dp_geomean": gmean(dp),
                "hybrid_min": min(hy), "hybrid_geomean": gmean(hy),
                "sk_beats_dp_geomean": gmean(sk) > gmean(dp), "sk_beats_dp_min": min(sk) > min(dp),
+               # the slowest shape often runs the identical DP launch in both legs
+               "sk_min_over_dp_min": min(sk) / min(dp),
                "mean_predicted_quant_loss": sum(1 - r["dp_quant_eff"] for r in rows) / len(rows),
                "sk_geomean_frac_of_roofline": gmean([r["sk_tflops"] / r["roofline_tflops"]
                                                      for r in rows]),

@@ -219,6 +219,30 @@ def test_auto_mode_cost_rule():
     assert (p.g, p.q, p.rho) == (64, 4, 0)
 
 
+def test_grouped_tile_order_longest_first():
+    # step (2): problems by iterations per tile, largest first, ties in the
+    # given order (K = 64, 256, 128, 256 on BK = 64 -> I = 1, 4, 2, 4)
+    probs = [(128, 128, 64), (128, 256, 256), (256, 128, 128), (128, 128, 256)]
+    p = sch.make_plan(probs, 128, 128, 64, 4, sch.MODE_HYBRID)
+    assert [t[0] for t in p.tiles] == [1, 1, 3, 2, 2, 0]
+    assert p.iters == [4, 4, 4, 2, 2, 1]
+    # the data-parallel grid keeps the given order
+    p = sch.make_plan(probs, 128, 128, 64, 4, sch.MODE_DP)
+    assert [t[0] for t in p.tiles] == [0, 1, 1, 2, 2, 3]
+    # whole tiles dealt round-robin in that order: every workgroup's load is
+    # within the largest I of every other's (the k-th tile of workgroup x is
+    # at least the k-th of x + 1, and at most the (k-1)-th of x + 1)
+    rng = random.Random(8)
+    for _ in range(60):
+        probs = [(rng.randint(1, 900), rng.randint(1, 900), rng.choice([64, 500, 2048, 4096]))
+                 for _ in range(rng.randint(2, 9))]
+        g = rng.choice([3, 7, 16, 64])
+        p = sch.make_plan(probs, 128, 128, 64, g, sch.MODE_HYBRID, dp_tiles=10 ** 6)
+        assert p.S == 0
+        load = [sum(p.iters[x::g]) for x in range(g)]
+        assert max(load) - min(load) <= max(p.iters)
+
+
 def test_group_m_tile_order_is_a_bijection():
     for tm, tn, gm in [(5, 3, 2), (7, 4, 3), (8, 8, 4), (1, 9, 4), (6, 1, 8)]:
         coords = [sch.tile_coords(u, tm, tn, gm) for u in range(tm * tn)]
