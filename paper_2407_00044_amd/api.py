@@ -61,7 +61,9 @@ def default_tile(M, N, K, dtype, cus=256):
     256x256 (f16/bf16, any layout) pays once it yields ~0.55 tiles per CU, or
     once its MAC iterations reach 32 per CU, where Stream-K spreads a few
     long-K tiles over every CU; 256x128 pays from ~0.9 tiles per CU; 128x128
-    is best below."""
+    is best below.  e4m3 (measured on the same shapes in e4m3): no 256x256
+    (it lost on most shapes), and 256x128 also once its MAC iterations reach
+    32 per CU."""
     code = DTYPE_CODES[dtype]
     if code == _abi.SK_F32:
         return (128, 128)
@@ -72,7 +74,10 @@ def default_tile(M, N, K, dtype, cus=256):
     if code in (_abi.SK_F16, _abi.SK_BF16) and M >= 256 and N >= 256 and \
             (t256 * 100 >= cus * 55 or t256 * iters >= 32 * cus):
         return (256, 256)
-    if M >= 256 and -(-M // 256) * -(-N // 128) * 10 >= cus * 9:
+    t256x128 = -(-M // 256) * -(-N // 128)
+    if M >= 256 and t256x128 * 10 >= cus * 9:
+        return (256, 128)
+    if code == _abi.SK_F8E4M3 and M >= 256 and t256x128 * iters >= 32 * cus:
         return (256, 128)
     return (128, 128)
 

@@ -169,6 +169,10 @@ def test_default_tile_rule():
     assert sk.default_tile(2048, 2048, 4096, bf) == (128, 128)
     assert sk.default_tile(512, 512, 512, torch.float32) == (128, 128)
     assert sk.default_tile(48, 1024, 2048, torch.float8_e4m3fn) == (64, 128)
+    e4 = torch.float8_e4m3fn
+    assert sk.default_tile(4826, 1341, 13813, e4) == (256, 128)    # 209 tiles x 108 iterations
+    assert sk.default_tile(2073, 2069, 1620, e4) == (128, 128)     # 153 tiles x 13 iterations
+    assert sk.default_tile(3840, 4096, 4096, e4) == (256, 128)
 
 
 def test_tuner_cache_unwritable_location_is_harmless(monkeypatch, tmp_path):
