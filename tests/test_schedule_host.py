@@ -57,10 +57,19 @@ def test_sweep_shapes():
         compare([(M, N, K)], torch.bfloat16, (128, 128), 256, "auto", group_m=-1)
 
 
+def test_auto_decisions_on_sweep_shapes_every_type():
+    # the split / no-split decisions the sweeps measure: every shape, every
+    # input type, on the default tile and the full grid
+    for dt in BK:
+        for M, N, K in synth.sweep_shapes():
+            tile = sk.default_tile(M, N, K, dt)
+            compare([(M, N, K)], dt, tile, 256, "auto", group_m=-1)
+
+
 def test_grouped_sets():
     shapes = synth.grouped_shapes()
     for tile in [(128, 128), (64, 128), (256, 128)]:
-        for mode in ["sk", "hybrid", "dp"]:
+        for mode in ["sk", "hybrid", "dp", "auto"]:
             compare(shapes, torch.float8_e4m3fn, tile, 256, mode)
     r = random.Random(3)
     for _ in range(40):
