@@ -87,7 +87,7 @@ typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
  *   SK_MODE_DP      baseline data-parallel grid: one workgroup per tile,
  *                   no persistence, no fixup, no workspace.
  *   SK_MODE_AUTO    SK_MODE_HYBRID, except that S = 0 (no tile is split)
- *                   when Stream-K's even share b = ceil(W_all/g), plus an
+ *                   when Stream-K's even share b = ceil(W_all/g), plus a
  *                   quarter for lost L2 reuse, plus one partial tile (f MAC
  *                   iterations of fixup: max(4, BM*BN/8192) for 16-bit and
  *                   e4m3 tiles, max(1, BM*BN/32768) for FP32, whose
@@ -95,8 +95,8 @@ typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
  *                   data-parallel waves:
  *                   b + ceil(b/4) + f >= ceil(T/g) * ceil(W_all/T) (FP32
  *                   iterations, too slow for the L2 loss to show: b + f >=
- *                   ...), W_all =
- *                   MAC iterations of all tiles, g after the grid floor.
+ *                   ...), W_all = MAC iterations of all tiles, g after the
+ *                   grid floor.
  *                   When the data-parallel launch is one partial wave
  *                   (T < g) and the floor did not shrink g, the left side
  *                   is taken 9/8 times (T busy workgroups outrun g).
@@ -203,12 +203,13 @@ sk_status sk_device_query(int32_t* num_cu, int32_t* max_wg_per_cu,
 sk_status sk_supported_tiles(int32_t dtype_ab, int32_t* out, int32_t capacity,
                              int32_t* count);
 
-/* Host-only.  Schedule parameters of `nprobs` problems (concatenated as in
- * a grouped launch: by MAC iterations per tile, ceil(K / block_k), largest
- * first, ties in the given order, so that whole tiles dealt round-robin to
- * the persistent workgroups balance; SK_MODE_DP keeps the given order; a
- * reading for grouped launches, which the report does not treat) under `cfg`.  cfg->num_cu must be > 0 when no
- * HIP device is present. */
+/* Host-only.  Schedule parameters of `nprobs` problems under `cfg`.  The
+ * problems are concatenated as in a grouped launch: ordered by MAC
+ * iterations per tile, ceil(K / block_k), largest first, ties in the given
+ * order, so that whole tiles dealt round-robin to the persistent workgroups
+ * balance (SK_MODE_DP keeps the given order; a reading for grouped
+ * launches, which the report does not treat).  cfg->num_cu must be > 0
+ * when no HIP device is present. */
 sk_status sk_plan(const sk_problem* probs, int32_t nprobs,
                   const sk_config* cfg, sk_plan_info* info);
 
