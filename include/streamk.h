@@ -79,7 +79,8 @@ typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
 
 /* How output tiles are distributed (Background section):
  *   SK_MODE_HYBRID  data-parallel + Stream-K: tiles [S, T) are whole tiles
- *                   handed round-robin to the persistent workgroups, tiles
+ *                   dealt to the persistent workgroups in rounds of g
+ *                   (position x, or g-1-x in odd rounds), tiles
  *                   [0, S) are split by MAC iterations; S = 0 when T is a
  *                   multiple of g, else min(T, T mod g + g) ("two-tile" rule),
  *                   unless sk_config.dp_tiles >= 0 sets S = T - dp_tiles.
@@ -206,9 +207,10 @@ sk_status sk_supported_tiles(int32_t dtype_ab, int32_t* out, int32_t capacity,
 /* Host-only.  Schedule parameters of `nprobs` problems under `cfg`.  The
  * problems are concatenated as in a grouped launch: ordered by MAC
  * iterations per tile, ceil(K / block_k), largest first, ties in the given
- * order, so that whole tiles dealt round-robin to the persistent workgroups
- * balance (SK_MODE_DP keeps the given order; a reading for grouped
- * launches, which the report does not treat).  cfg->num_cu must be > 0
+ * order, so that the whole tiles dealt to the persistent workgroups (in
+ * rounds of g, at position x in even rounds and g-1-x in odd ones) balance
+ * (SK_MODE_DP keeps the given order; a reading for grouped launches, which
+ * the report does not treat).  cfg->num_cu must be > 0
  * when no HIP device is present. */
 sk_status sk_plan(const sk_problem* probs, int32_t nprobs,
                   const sk_config* cfg, sk_plan_info* info);

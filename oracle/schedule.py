@@ -70,8 +70,11 @@ applied):
   (7) The FINISH owner of a split tile waits for the PARTIAL contributions of
       workgroups x+1 .. y, where y owns the tile's last iteration;
       npeers = y - x.
-  (8) DP tile S + j is processed by workgroup j mod g after all of its SK
-      segments, in increasing j.
+  (8) The DP tiles are dealt in rounds of g after all SK segments: in round
+      r workgroup x takes tile S + r*g + x when r is even and
+      S + r*g + (g-1-x) when r is odd (a reading: with step (2)'s
+      longest-first order this evens out the workgroups' loads), while the
+      tile exists.
 """
 from bisect import bisect_right
 from collections import defaultdict
@@ -267,9 +270,15 @@ def simulate(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
                 role, npeers = PARTIAL, 0
             segs.append(Segment(x, p, t, r, c, kb, ke, role, npeers))
             it = plan.J[t] + ke
-        for t in range(plan.S + x, plan.T, plan.g):
+        rnd = 0
+        while True:
+            pos = x if rnd % 2 == 0 else plan.g - 1 - x
+            t = plan.S + rnd * plan.g + pos
+            if t >= plan.T:
+                break
             p, r, c = plan.tiles[t]
             segs.append(Segment(x, p, t, r, c, 0, plan.iters[t], DP, 0))
+            rnd += 1
     return plan, segs
 
 
@@ -424,7 +433,8 @@ def check(problems, block_m, block_n, block_k, g, mode, segs, dp_tiles=-1,
             if [s.tile for s in dp_x] != sorted(s.tile for s in dp_x):
                 _fail(f"DP tiles of workgroup {x} out of order")
             for s in dp_x:
-                if (s.tile - S) % g != x:
+                rnd, pos = divmod(s.tile - S, g)
+                if pos != (x if rnd % 2 == 0 else g - 1 - x):
                     _fail(f"DP tile {s.tile} on workgroup {x}")
         if total != W:
             _fail("I2: iteration counts do not sum to W")

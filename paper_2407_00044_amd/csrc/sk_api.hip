@@ -351,7 +351,9 @@ static void host_segments(const Plan& P, const sk_config* cfg, std::vector<sk_se
       emit(x, p, d.tile_start + u, u, kb, ke, role, npeers);
       it = J + ke;
     }
-    for (int64_t t = P.S + x; t < P.T; t += P.g) {
+    for (int64_t r = 0;; ++r) {          // position x, or g-1-x in odd rounds
+      const int64_t t = P.S + r * P.g + ((r & 1) ? P.g - 1 - x : x);
+      if (t >= P.T) break;
       int32_t p = host_find_problem(P, t, false);
       emit(x, p, t, t - P.descs[p].tile_start, 0, P.descs[p].I, SK_ROLE_DP, 0);
     }

@@ -1251,10 +1251,12 @@ __global__ __launch_bounds__(C::NT, 1) void sk_gemm_kernel(KParams P) {
   const int tid = threadIdx.x;
   const int64_t b = blockIdx.x;
 
-  // Work of this workgroup: Stream-K iterations [it, e), then data-parallel
-  // tiles dp_t, dp_t + dp_step, ... below T.  The baseline grid runs exactly
-  // one data-parallel tile per workgroup.
-  int64_t x, it, e, dp_t, dp_step;
+  // Work of this workgroup: Stream-K iterations [it, e), then one
+  // data-parallel tile per round of g tiles below T, taken at position x in
+  // even rounds and g-1-x in odd ones (a tile list sorted longest first then
+  // evens out).  The baseline grid runs exactly one data-parallel tile per
+  // workgroup.
+  int64_t x, it, e, dp_t, dp_step, dp_r = 0;
   if (P.dp_grid) {
     x = logical_id(b, P.T, P.xcd_remap, 0);
     it = e = 0;
@@ -1292,7 +1294,12 @@ __global__ __launch_bounds__(C::NT, 1) void sk_gemm_kernel(KParams P) {
       w.ke = pd.I;
       w.role = R_DP;
       w.npeers = 0;
-      dp_t += dp_step;
+      if (P.dp_grid) {
+        dp_t += dp_step;
+      } else {
+        ++dp_r;
+        dp_t = P.S + dp_r * P.g + ((dp_r & 1) ? P.g - 1 - x : x);
+      }
     } else {
       break;
     }

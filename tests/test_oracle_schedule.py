@@ -229,18 +229,29 @@ def test_grouped_tile_order_longest_first():
     # the data-parallel grid keeps the given order
     p = sch.make_plan(probs, 128, 128, 64, 4, sch.MODE_DP)
     assert [t[0] for t in p.tiles] == [0, 1, 1, 2, 2, 3]
-    # whole tiles dealt round-robin in that order: every workgroup's load is
-    # within the largest I of every other's (the k-th tile of workgroup x is
-    # at least the k-th of x + 1, and at most the (k-1)-th of x + 1)
+    # whole tiles dealt in that order (step (8)): every workgroup's load is
+    # within the largest I of every other's
     rng = random.Random(8)
     for _ in range(60):
         probs = [(rng.randint(1, 900), rng.randint(1, 900), rng.choice([64, 500, 2048, 4096]))
                  for _ in range(rng.randint(2, 9))]
         g = rng.choice([3, 7, 16, 64])
-        p = sch.make_plan(probs, 128, 128, 64, g, sch.MODE_HYBRID, dp_tiles=10 ** 6)
+        p, segs = sch.simulate(probs, 128, 128, 64, g, sch.MODE_HYBRID, dp_tiles=10 ** 6)
         assert p.S == 0
-        load = [sum(p.iters[x::g]) for x in range(g)]
+        load = [0] * g
+        for s in segs:
+            load[s.wg] += s.k_end - s.k_begin
+        assert sum(load) == sum(p.iters)
         assert max(load) - min(load) <= max(p.iters)
+
+
+def test_dp_tiles_dealt_back_and_forth():
+    # step (8): 10 DP tiles on 4 workgroups: rounds 0..3 at positions
+    # x, 3-x, x, 3-x (the last round holds tiles 8 and 9 only)
+    p, segs = sch.simulate([(128 * 10, 128, 64)], 128, 128, 64, 4, sch.MODE_HYBRID,
+                           dp_tiles=10)
+    got = {x: [s.tile for s in segs if s.wg == x] for x in range(4)}
+    assert got == {0: [0, 7, 8], 1: [1, 6, 9], 2: [2, 5], 3: [3, 4]}
 
 
 def test_group_m_tile_order_is_a_bijection():
