@@ -35,6 +35,10 @@ CASES = [
     (1000, 700, 900, "f16", (128, 128), "hybrid", 256, 7),
     (1713, 1597, 14203, "bf16", (128, 128), "auto", 256, 0),
     (1000, 700, 900, "bf16", (128, 128), "auto", 256, 0),
+    # persistent data-parallel rounds (odd rounds taken back to front):
+    # 48 tiles on 4 workgroups = 12 rounds; on 7: 13 split tiles + 5 rounds
+    (1000, 700, 900, "bf16", (128, 128), "hybrid", 4, 1),
+    (1000, 700, 900, "e4m3", (128, 128), "hybrid", 7, 1),
 ]
 
 
