@@ -59,7 +59,7 @@ applied):
       losses there).  An explicit
       dp_tiles >= 0 sets S = T - min(dp_tiles, T).  Auto mode with S = 0 on a
       single problem launches the DP grid (one workgroup per tile) instead of
-      handing whole tiles round-robin to the persistent workgroups.
+      dealing whole tiles to the persistent workgroups (step (8)).
   (4) Iteration space of the SK tiles: J_0 = 0, J_{t+1} = J_t + I_t, W = J_S.
   (5) Even split over g persistent workgroups: q = W // g, rho = W % g;
       workgroup x owns [s_x, e_x) with s_x = x*q + min(x, rho) and
