@@ -187,6 +187,9 @@ typedef struct {
   int64_t workspace_bytes;
   int64_t max_iters; /* largest per-tile iteration count */
   int64_t group_m;   /* tile order used (group_m = -1 resolved) */
+  int64_t dp_grid;   /* 1: the launch is the data-parallel grid (one
+                        workgroup per tile: SK_MODE_DP, or SK_MODE_AUTO with
+                        nothing to split on one problem) */
 } sk_plan_info;
 
 /* Returns a static English description of a status code. */
@@ -215,6 +218,11 @@ sk_status sk_supported_tiles(int32_t dtype_ab, int32_t* out, int32_t capacity,
 sk_status sk_plan(const sk_problem* probs, int32_t nprobs,
                   const sk_config* cfg, sk_plan_info* info);
 
+/* Host-only.  The order in which a launch concatenates the problems:
+ * order[i] is the caller's index of the i-th problem (nprobs entries). */
+sk_status sk_plan_order(const sk_problem* probs, int32_t nprobs,
+                        const sk_config* cfg, int32_t* order);
+
 /* Host-only.  The complete schedule: for each logical workgroup in order,
  * its Stream-K segments in processing order, then its data-parallel tiles
  * in increasing tile order.  With out == NULL only *count is set; with too
@@ -223,16 +231,26 @@ sk_status sk_schedule(const sk_problem* probs, int32_t nprobs,
                       const sk_config* cfg, sk_segment* out, int64_t capacity,
                       int64_t* count);
 
-/* Bytes of workspace a launch of `probs` under `cfg` needs: an error word,
- * one int32 ready flag per Stream-K tile and one FP32 partial-tile slot per
- * persistent workgroup.  0 for SK_MODE_DP. */
+/* Bytes of workspace a launch of `probs` under `cfg` needs.  The layout
+ * has fixed offsets, the same for every problem and config:
+ *   [0, 256)        header: error word, epoch word, done counter;
+ *   [256, 16640)    one 32-bit token per persistent workgroup (at most 4096);
+ *   [16640, ...)    g FP32 partial tiles of block_m x block_n.
+ * A workgroup that leaves a partial tile writes the launch's tag (epoch + 1)
+ * into its token; the tile's finisher waits for that tag; the last workgroup
+ * of a launch advances the epoch.  Tokens of earlier launches therefore
+ * never match, whatever problems, tiles or workgroup counts the workspace
+ * served before.  Only launches that split tiles (S > 0) use more than the
+ * 256-byte header: 0 for SK_MODE_DP and the auto mode's data-parallel grid.
+ */
 sk_status sk_workspace_size(const sk_problem* probs, int32_t nprobs,
                             const sk_config* cfg, size_t* bytes);
 
 /* Zeroes `bytes` of workspace on `hip_stream` with a fill kernel (safe to
- * record into a HIP graph).  Required once before a workspace's first use and
- * after an SK_ERR_DEVICE_TIMEOUT; afterwards the flags return to zero at the
- * end of every launch by themselves. */
+ * record into a HIP graph).  Required once before a workspace's first use;
+ * afterwards every launch leaves the header consistent by itself, also one
+ * whose fixup wait timed out (SK_ERR_DEVICE_TIMEOUT: that launch's output is
+ * invalid, later launches on the workspace are not affected). */
 sk_status sk_workspace_init(void* workspace, size_t bytes, void* hip_stream);
 
 /* One GEMM: C_out = alpha*scale_a*scale_b*A*B + beta*C_in.
@@ -276,9 +294,14 @@ sk_status sk_check_device_error(void* workspace, size_t ws_bytes,
 
 /* ---- Grouped GEMM: one persistent launch over several problems ----------
  * The MAC iterations of all problems' Stream-K tiles are counted together
- * and split evenly over the persistent workgroups; problems are
- * concatenated in the given order.  All problems share dtype_ab, dtype_c,
- * layout_a and layout_b. */
+ * and split evenly over the persistent workgroups (Background section: even
+ * work units over all cores, here over the tiles of every problem).
+ * Problems are concatenated in the order sk_plan_order reports: by MAC
+ * iterations per tile, largest first, ties in the given order (SK_MODE_DP:
+ * the given order).  All problems share dtype_ab, dtype_c, layout_a and
+ * layout_b.  The launch entry point takes a host plan plus device
+ * descriptors (rather than a bare descriptor array and a config) so that a
+ * captured launch replays exactly the schedule that was prepared. */
 
 /* Host-side plan of a grouped launch, filled by sk_grouped_prepare. */
 typedef struct {
@@ -291,6 +314,7 @@ typedef struct {
   int32_t xcd_remap, group_m;
   int64_t spin_limit;
   int32_t all_aligned;
+  int64_t max_iters;            /* largest per-tile iteration count */
 } sk_grouped_plan;
 
 /* Bytes of device descriptor memory sk_grouped_prepare needs. */
@@ -312,6 +336,14 @@ sk_status sk_grouped_prepare(const sk_problem* probs, const void* const* A,
  * asynchronous and capturable into a HIP graph. */
 sk_status sk_gemm_grouped(const sk_grouped_plan* plan, const void* dev_desc,
                           void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* sk_gemm_grouped with the debug hooks of sk_gemm_debug: a device trace of
+ * the segments run (segment.problem is the caller's problem index) and
+ * per-iteration coverage counts (cover_stride >= plan->max_iters).  For
+ * tests; never used for timing. */
+sk_status sk_gemm_grouped_debug(const sk_grouped_plan* plan, const void* dev_desc,
+                                void* workspace, size_t ws_bytes, const sk_debug* dbg,
+                                void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -9,57 +9,29 @@ leaves cores idle whenever the tile count is not a multiple of the core count
 (its Figure 1 example runs at 75% utilisation), and Stream-K instead divides
 the multiply-accumulate work into even-sized units spread over all cores.
 The report gives no equations or pseudocode, so the schedule below is the
-reading used throughout this project (each numbered step is named where it is
-applied):
+reading used throughout this project.
+
+The simulator is a function of the launch it describes.  Its inputs are the
+problems, the tile shape, and the launch parameters a caller has resolved:
+the workgroup count g, the split point S, the tile order (group_m), the
+order in which the problems are concatenated and the rule that deals whole
+tiles.  How a library chooses those parameters (grid sizes, cost models,
+orderings tuned on one machine) is policy, not part of the method, and is
+not computed here.  Each numbered step is named where it is applied:
 
   (1) Per problem p: tm = ceil(M/BM), tn = ceil(N/BN), T_p = tm*tn output
       tiles, I_p = max(1, ceil(K/BK)) MAC-loop iterations per tile.  (A K = 0
       problem keeps one empty iteration per tile so that its tiles still reach
       the epilogue C = beta*Cin.)
-  (2) Tiles are numbered problem-major, the problems taken by I_p, largest
-      first, ties in the given order (a reading for grouped launches, which
-      the report does not treat: whole tiles then alternate evenly between
-      the persistent workgroups, longest first; DP mode keeps the given
-      order); inside a problem tile u maps to
-      (tm, tn) row-major, or, with group_m > 0, band-wise: bands of group_m
-      tile rows, walked down the rows first, then across the columns.
-      group_m = -1 (automatic; a locality reading, not in the report) is
-      resolved after step (5): with Stream-K tiles, D = q / gcd(q, I) for the
-      first problem that has tiles (I iterations, tm tile rows) and group_m
-      is the largest divisor of D not above tm (workgroups whose ranges start
-      at the same k-phase of their tiles then sit in one tile row); otherwise
-      group_m = 8.
-  (2b) Grid floor (not in the report; a reading that keeps split tiles from
-      having dozens of contributors when the problem is small): with
-      min_iters = m > 1 a Stream-K or hybrid launch uses
-      g' = min(g, max(1, W_all // m)) workgroups, W_all = sum of I over all T
-      tiles, so that no workgroup gets much less than m iterations.  m = 0
-      selects m = ceil(I_mean / c) with I_mean = ceil(W_all / T) and c the
-      largest integer >= 1 with f c^2 <= I_mean: if one partial tile costs
-      about f MAC iterations (store, wait, load and add; measured:
-      f = max(4, BM*BN/8192) for 16-bit and e4m3 iterations, f = max(1,
-      BM*BN/32768) for FP32 iterations of 32 K-values, which take ~4.5x as
-      long), a tile of I iterations split into c pieces
-      takes about I/c + f(c - 1) iteration times, least near c = sqrt(I/f);
-      with c = 1 tiles are not split at all.  m = 1 keeps g.  Steps (3)-(5)
-      use g'.
-  (3) Split point S over the T = sum T_p tiles: tiles [0,S) are Stream-K
-      tiles, [S,T) data-parallel tiles.  SK mode: S = T.  DP mode: S = 0 with
-      one workgroup per tile.  Hybrid ("two-tile SK + DP"): S = 0 when
-      T mod g == 0, else min(T, T mod g + g).  Auto mode (not in the report):
-      the hybrid rule, and S = 0 also when Stream-K cannot beat the
-      data-parallel waves under the cost model of step (2b) with a quarter
-      added for the L2 reuse that workgroups at different k-phases lose
-      (nothing for FP32 iterations, which move too few bytes per clock for
-      that loss to show): with b = ceil(W_all / g), when
-      b + ceil(b / 4) + f >= ceil(T / g) * ceil(W_all / T) (FP32: b + f).
-      When the DP launch would be one partial wave (T < g') and the floor
-      left g' = g, the Stream-K side is taken 9/8 times (measured: T busy
-      workgroups outrun g busy ones, and predicted gains under ~12% were
-      losses there).  An explicit
-      dp_tiles >= 0 sets S = T - min(dp_tiles, T).  Auto mode with S = 0 on a
-      single problem launches the DP grid (one workgroup per tile) instead of
-      dealing whole tiles to the persistent workgroups (step (8)).
+  (2) Tiles are numbered problem-major, the problems concatenated in a given
+      order (default: the order of the list); inside a problem tile u maps
+      to (tm, tn) row-major, or, with group_m > 0, band-wise: bands of
+      group_m tile rows, walked down the rows first, then across the columns.
+  (3) Split point S: tiles [0,S) are Stream-K tiles, [S,T) whole tiles.
+      The readings of the report's hybrid: all Stream-K (S = T), the
+      data-parallel baseline (S = 0, one workgroup per tile) and the
+      "two-tile" data-parallel + Stream-K rule S = 0 when T mod g == 0, else
+      min(T, T mod g + g) (split_for_mode); any S in [0, T] is simulated.
   (4) Iteration space of the SK tiles: J_0 = 0, J_{t+1} = J_t + I_t, W = J_S.
   (5) Even split over g persistent workgroups: q = W // g, rho = W % g;
       workgroup x owns [s_x, e_x) with s_x = x*q + min(x, rho) and
@@ -70,20 +42,19 @@ applied):
   (7) The FINISH owner of a split tile waits for the PARTIAL contributions of
       workgroups x+1 .. y, where y owns the tile's last iteration;
       npeers = y - x.
-  (8) The DP tiles are dealt in rounds of g after all SK segments: in round
-      r workgroup x takes tile S + r*g + x when r is even and
-      S + r*g + (g-1-x) when r is odd (a reading: with step (2)'s
-      longest-first order this evens out the workgroups' loads), while the
-      tile exists.
+  (8) The whole tiles [S, T) are dealt in rounds of g after all SK segments:
+      in round r, workgroup x takes tile S + r*g + x ("cyclic") or, under the
+      "serpentine" rule, S + r*g + (g-1-x) in odd rounds, while the tile
+      exists.  In the data-parallel baseline workgroup t runs tile t alone.
 """
 from bisect import bisect_right
 from collections import defaultdict
-from math import gcd
 from dataclasses import dataclass
 
 FULL, FINISH, PARTIAL, DP = 0, 1, 2, 3
 ROLE_NAMES = {FULL: "FULL", FINISH: "FINISH", PARTIAL: "PARTIAL", DP: "DP"}
-MODE_HYBRID, MODE_SK, MODE_DP, MODE_AUTO = 0, 1, 2, 3
+MODE_HYBRID, MODE_SK, MODE_DP = 0, 1, 2
+CYCLIC, SERPENTINE = "cyclic", "serpentine"
 
 
 @dataclass(frozen=True)
@@ -117,6 +88,41 @@ def tile_coords(u, tm, tn, group_m):
     return band * group_m + v % h, v // h
 
 
+def two_tile_split(T, g):
+    """Step (3): the data-parallel + Stream-K "two-tile" rule."""
+    if g <= 0 or T % g == 0:
+        return 0
+    return min(T, T % g + g)
+
+
+def split_for_mode(T, g, mode, dp_tiles=-1):
+    """Step (3) for the report's three decompositions; dp_tiles >= 0 keeps
+    that many whole tiles at the end (S = T - dp_tiles)."""
+    if mode == MODE_DP:
+        return 0
+    S = T if mode == MODE_SK else two_tile_split(T, g)
+    if dp_tiles >= 0:
+        S = T - min(dp_tiles, T)
+    return S
+
+
+def tile_grid(problems, block_m, block_n, block_k, order=None):
+    """Steps (1)-(2) without coordinates: (problem, u, tm, tn, I) per global
+    tile, problems concatenated in `order`."""
+    order = list(range(len(problems))) if order is None else list(order)
+    if sorted(order) != list(range(len(problems))):
+        raise ValueError("order must be a permutation of the problems")
+    out = []
+    for p in order:
+        M, N, K = problems[p]
+        tm = cdiv(M, block_m) if M > 0 else 0
+        tn = cdiv(N, block_n) if N > 0 else 0
+        I = max(1, cdiv(K, block_k))
+        for u in range(tm * tn):
+            out.append((p, u, tm, tn, I))
+    return out
+
+
 @dataclass
 class Plan:
     """Schedule parameters of steps (1)-(5)."""
@@ -129,99 +135,34 @@ class Plan:
     q: int
     rho: int
     J: list              # prefix sums over the SK tiles, len S+1
-    dp_grid: bool        # DP mode: one workgroup per tile
+    dp_grid: bool        # data-parallel baseline: one workgroup per tile
     group_m: int = 0     # tile order used
 
 
-def fixup_cost(block_m, block_n, block_k):
-    """Step (2b): MAC iterations one partial tile costs (measured): FP32
-    iterations (32 K-values) are ~4.5x longer than 16-bit / e4m3 ones."""
-    if block_k == 32:
-        return max(1, block_m * block_n // 32768)
-    return max(4, block_m * block_n // 8192)
-
-
-def auto_split(I_mean, f=4):
-    """Largest c >= 1 with f c^2 <= I_mean, by plain search."""
-    c = 1
-    while f * (c + 1) * (c + 1) <= I_mean:
-        c += 1
-    return c
-
-
-def grid_floor(g, iters, min_iters, f=4):
-    """Step (2b): workgroups actually launched for Stream-K/hybrid."""
-    T = len(iters)
-    W_all = sum(iters)
-    if T == 0 or W_all == 0:
-        return g
-    m = min_iters
-    if m == 0:
-        I_mean = cdiv(W_all, T)
-        m = cdiv(I_mean, auto_split(I_mean, f))
-    if m <= 1:
-        return g
-    return min(g, max(1, W_all // m))
-
-
-def make_plan(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
-              dp_tiles=-1, group_m=0, min_iters=1):
-    """Steps (1)-(5) for a list of (M, N, K) problems."""
-    local, iters, first = [], [], None
-    order = list(range(len(problems)))
-    if mode != MODE_DP:                              # stable: ties keep their order
-        order.sort(key=lambda p: -max(1, cdiv(problems[p][2], block_k)))
-    for p in order:
-        M, N, K = problems[p]
-        tm = cdiv(M, block_m) if M > 0 else 0
-        tn = cdiv(N, block_n) if N > 0 else 0
-        I = max(1, cdiv(K, block_k))
-        if tm * tn > 0 and first is None:
-            first = (I, tm)
-        for u in range(tm * tn):
-            local.append((p, u, tm, tn))
-            iters.append(I)
-    T = len(local)
-    f = fixup_cost(block_m, block_n, block_k)
-    g_full = g
-    if mode != MODE_DP:
-        g = grid_floor(g, iters, min_iters, f)
-    if mode == MODE_DP:
-        S = 0
-        g = T
-    elif mode == MODE_SK:
-        S = T
-    else:
-        S = 0 if (g == 0 or T % g == 0) else min(T, T % g + g)
-        W_all = sum(iters)
-        b = cdiv(W_all, g) if g > 0 else 0
-        l2 = 0 if block_k == 32 else cdiv(b, 4)
-        if mode == MODE_AUTO and S > 0:
-            sk_cost = b + l2 + f
-            if T < g and g == g_full:         # one partial data-parallel wave
-                sk_cost = sk_cost * 9 / 8
-            if sk_cost >= cdiv(T, g) * cdiv(W_all, T):
-                S = 0
-    if mode != MODE_DP and dp_tiles >= 0:
-        S = T - min(dp_tiles, T)
-    dp_grid = mode == MODE_DP or (mode == MODE_AUTO and S == 0 and len(problems) == 1)
+def make_plan(problems, block_m, block_n, block_k, g, S, group_m=0, order=None,
+              dp_grid=False):
+    """Steps (1)-(5) for a list of (M, N, K) problems and resolved launch
+    parameters: g workgroups, S Stream-K tiles, tile order group_m >= 0,
+    problem order.  dp_grid: the baseline grid (S must be 0; g = T)."""
+    grid = tile_grid(problems, block_m, block_n, block_k, order)
+    T = len(grid)
+    if not 0 <= S <= T:
+        raise ValueError(f"S = {S} outside [0, {T}]")
+    if group_m < 0:
+        raise ValueError("group_m must be resolved (>= 0)")
     if dp_grid:
+        if S != 0:
+            raise ValueError("the data-parallel grid splits no tile")
         g = T
+    elif g <= 0:
+        raise ValueError("g must be positive")
+    iters = [I for *_, I in grid]
+    tiles = [(p,) + tile_coords(u, tm, tn, group_m) for p, u, tm, tn, _ in grid]
     J = [0]
     for t in range(S):
         J.append(J[-1] + iters[t])
     W = J[-1]
     q, rho = (W // g, W % g) if g > 0 else (0, 0)
-    if group_m < 0:
-        if S > 0 and q > 0:
-            D = q // gcd(q, first[0])
-            group_m = max(G for G in range(1, min(D, first[1]) + 1) if D % G == 0)
-        else:
-            group_m = 8
-    tiles = []
-    for p, u, tm, tn in local:
-        r, c = tile_coords(u, tm, tn, group_m)
-        tiles.append((p, r, c))
     return Plan(tiles, iters, T, S, W, g, q, rho, J, dp_grid, group_m)
 
 
@@ -241,12 +182,20 @@ def owner(plan, it):
     raise ValueError(f"iteration {it} has no owner")
 
 
-def simulate(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
-             dp_tiles=-1, group_m=0, min_iters=1):
+def dealt_position(rnd, x, g, deal):
+    """Step (8): offset inside round `rnd` of the tile workgroup x takes."""
+    if deal == CYCLIC:
+        return x
+    if deal == SERPENTINE:
+        return x if rnd % 2 == 0 else g - 1 - x
+    raise ValueError(f"unknown dealing rule {deal!r}")
+
+
+def simulate(problems, block_m, block_n, block_k, g, S, group_m=0, order=None,
+             dp_grid=False, deal=CYCLIC):
     """Segments of every workgroup, in workgroup order and, inside a
     workgroup, in processing order (steps (6)-(8))."""
-    plan = make_plan(problems, block_m, block_n, block_k, g, mode, dp_tiles,
-                     group_m, min_iters)
+    plan = make_plan(problems, block_m, block_n, block_k, g, S, group_m, order, dp_grid)
     segs = []
     if plan.dp_grid:
         for t, (p, r, c) in enumerate(plan.tiles):
@@ -272,14 +221,22 @@ def simulate(problems, block_m, block_n, block_k, g, mode=MODE_HYBRID,
             it = plan.J[t] + ke
         rnd = 0
         while True:
-            pos = x if rnd % 2 == 0 else plan.g - 1 - x
-            t = plan.S + rnd * plan.g + pos
+            t = plan.S + rnd * plan.g + dealt_position(rnd, x, plan.g, deal)
             if t >= plan.T:
                 break
             p, r, c = plan.tiles[t]
             segs.append(Segment(x, p, t, r, c, 0, plan.iters[t], DP, 0))
             rnd += 1
     return plan, segs
+
+
+def simulate_mode(problems, block_m, block_n, block_k, g, mode, dp_tiles=-1, group_m=0,
+                  order=None, deal=CYCLIC):
+    """simulate() with S from one of the report's decompositions (step (3))."""
+    T = len(tile_grid(problems, block_m, block_n, block_k, order))
+    S = split_for_mode(T, g, mode, dp_tiles)
+    return simulate(problems, block_m, block_n, block_k, g, S, group_m, order,
+                    mode == MODE_DP, deal)
 
 
 # ---------------------------------------------------------------------------
@@ -296,55 +253,50 @@ def _fail(msg):
     raise ScheduleError(msg)
 
 
-def check(problems, block_m, block_n, block_k, g, mode, segs, dp_tiles=-1,
-          group_m=0):
+def check(problems, block_m, block_n, block_k, g, segs, order=None, dp_grid=False,
+          deal=CYCLIC):
     """Raise ScheduleError unless ``segs`` satisfies invariants I1-I8.
 
-    I1 every (SK tile, k-iteration) and every DP tile is covered exactly once
+    I1 every (SK tile, k-iteration) and every whole tile is covered exactly
+       once
     I2 every workgroup's SK iteration count is q or q+1 and they sum to W
     I3 a workgroup has at most one PARTIAL (its first SK segment) and at most
-       one FINISH (its last SK segment); SK segments precede DP segments
+       one FINISH (its last SK segment); SK segments precede whole tiles
     I4 a FINISH waits only on higher workgroups, whose contribution to the
        tile is their first segment, and the contributions tile [0, I_t)
        contiguously in increasing workgroup order (no wait cycles)
     I5 a split tile has exactly one FINISH, with npeers = contributors - 1
     I6 slots used <= g (one per PARTIAL workgroup), flags used <= S
     I7 #FULL + #FINISH == S
-    I8 single-problem hybrid with S >= g: split tiles have 2 contributors;
-       DP mode: no SK segments
+    I8 one problem with S >= g: every workgroup owns at least one tile's
+       iterations, so a split tile has exactly 2 contributors; the
+       data-parallel grid has no SK segments
     plus: roles agree with (k_begin, k_end); tile coordinates are a bijection
     onto each problem's tile grid; a workgroup's SK ranges are contiguous in
-    the global iteration order.
+    the global iteration order; whole tiles follow the dealing rule.
     """
-    # Independent recomputation of the tile grid (no call into make_plan):
-    # step (2)'s order, as one pass per distinct I from the largest down.
-    grid = {}
+    # Independent recomputation of the tile grid (no call into make_plan).
+    order = list(range(len(problems))) if order is None else list(order)
     tile_list = []
-    per_tile_iters = [max(1, cdiv(K, block_k)) for _, _, K in problems]
-    passes = [None] if mode == MODE_DP else sorted(set(per_tile_iters), reverse=True)
-    for want in passes:
-        for p, (M, N, K) in enumerate(problems):
-            I = per_tile_iters[p]
-            if want is not None and I != want:
-                continue
-            tm = cdiv(M, block_m) if M > 0 else 0
-            tn = cdiv(N, block_n) if N > 0 else 0
-            for _ in range(tm * tn):
-                tile_list.append((p, I, tm, tn))
+    for p in order:
+        M, N, K = problems[p]
+        tm = cdiv(M, block_m) if M > 0 else 0
+        tn = cdiv(N, block_n) if N > 0 else 0
+        I = max(1, cdiv(K, block_k))
+        tile_list.extend([(p, I, tm, tn)] * (tm * tn))
     T = len(tile_list)
+    grid = {}
     seen_coords = defaultdict(set)
 
     sk = [s for s in segs if s.role != DP]
     dp = [s for s in segs if s.role == DP]
-    if mode == MODE_DP:
+    if dp_grid:
         if sk:
-            _fail("I8: DP mode produced SK segments")
+            _fail("I8: the data-parallel grid produced SK segments")
         S = 0
     else:
         sk_tiles = {s.tile for s in sk}
         S = (max(sk_tiles) + 1) if sk_tiles else 0
-        if mode == MODE_SK and dp_tiles < 0 and S != T:
-            _fail(f"SK mode must make every tile an SK tile (S={S}, T={T})")
 
     for s in segs:
         if not (0 <= s.tile < T):
@@ -384,11 +336,11 @@ def check(problems, block_m, block_n, block_k, g, mode, segs, dp_tiles=-1,
     dp_count = defaultdict(int)
     for s in dp:
         if s.tile < S:
-            _fail("DP segment on an SK tile")
+            _fail("whole-tile segment on an SK tile")
         dp_count[s.tile] += 1
     for t in range(S, T):
         if dp_count[t] != 1:
-            _fail(f"I1: DP tile {t} covered {dp_count[t]} times")
+            _fail(f"I1: whole tile {t} covered {dp_count[t]} times")
     if len(grid) != T:
         _fail("not every tile appears")
 
@@ -397,10 +349,10 @@ def check(problems, block_m, block_n, block_k, g, mode, segs, dp_tiles=-1,
     for s in segs:
         by_wg[s.wg].append(s)
     W = sum(tile_list[t][1] for t in range(S))
-    if mode == MODE_DP:
+    if dp_grid:
         for s in dp:
             if s.wg != s.tile:
-                _fail("DP mode: workgroup t must process tile t")
+                _fail("data-parallel grid: workgroup t must process tile t")
     else:
         if any(not (0 <= x < g) for x in by_wg):
             _fail("workgroup id out of range")
@@ -416,7 +368,7 @@ def check(problems, block_m, block_n, block_k, g, mode, segs, dp_tiles=-1,
             sk_x = [s for s in lst if s.role != DP]
             dp_x = [s for s in lst if s.role == DP]
             if lst[:len(sk_x)] != sk_x:
-                _fail(f"I3: workgroup {x} has DP work before SK work")
+                _fail(f"I3: workgroup {x} has whole tiles before SK work")
             n = sum(s.k_end - s.k_begin for s in sk_x)
             if n not in (q, q + 1):
                 _fail(f"I2: workgroup {x} has {n} iterations, q={q}")
@@ -431,11 +383,12 @@ def check(problems, block_m, block_n, block_k, g, mode, segs, dp_tiles=-1,
                 if s.role == FINISH and i != len(sk_x) - 1:
                     _fail(f"I3: FINISH not last in workgroup {x}")
             if [s.tile for s in dp_x] != sorted(s.tile for s in dp_x):
-                _fail(f"DP tiles of workgroup {x} out of order")
+                _fail(f"whole tiles of workgroup {x} out of order")
             for s in dp_x:
                 rnd, pos = divmod(s.tile - S, g)
-                if pos != (x if rnd % 2 == 0 else g - 1 - x):
-                    _fail(f"DP tile {s.tile} on workgroup {x}")
+                want = x if (deal == CYCLIC or rnd % 2 == 0) else g - 1 - x
+                if pos != want:
+                    _fail(f"whole tile {s.tile} on workgroup {x} ({deal} dealing)")
         if total != W:
             _fail("I2: iteration counts do not sum to W")
 
@@ -476,9 +429,8 @@ def check(problems, block_m, block_n, block_k, g, mode, segs, dp_tiles=-1,
         if k != I:
             _fail(f"I4: tile {t}: contributions stop at {k} of {I}")
         partial_wgs.extend(s.wg for s in peers)
-        if (mode in (MODE_HYBRID, MODE_AUTO) and dp_tiles < 0 and len(problems) == 1
-                and S >= g and f.npeers != 1):
-            _fail(f"I8: hybrid split tile {t} has {f.npeers + 1} contributors")
+        if len(problems) == 1 and S >= g and f.npeers != 1:
+            _fail(f"I8: split tile {t} has {f.npeers + 1} contributors with S >= g")
 
     # I6 / I7.
     if len(set(partial_wgs)) != len(partial_wgs) or len(partial_wgs) > max(g, 0):

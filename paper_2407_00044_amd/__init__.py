@@ -13,4 +13,4 @@ from ._abi import LIB_PATH, StreamKError, load  # noqa: F401
 from . import tune  # noqa: F401
 from .api import (Config, GroupedGemm, StreamKLinearFn, Workspace,  # noqa: F401
                   check_device_error, default_tile, device_query, gemm, gemm_debug,
-                  linear, plan, schedule, supported_tiles)
+                  launch_params, linear, plan, plan_order, schedule, supported_tiles)

@@ -60,7 +60,7 @@ class SkSegment(ctypes.Structure):
 class SkPlanInfo(ctypes.Structure):
     _fields_ = [("T", c_i64), ("S", c_i64), ("W", c_i64), ("g", c_i64),
                 ("q", c_i64), ("rho", c_i64), ("workspace_bytes", c_i64),
-                ("max_iters", c_i64), ("group_m", c_i64)]
+                ("max_iters", c_i64), ("group_m", c_i64), ("dp_grid", c_i64)]
 
 
 class SkDebug(ctypes.Structure):
@@ -78,7 +78,7 @@ class SkGroupedPlan(ctypes.Structure):
                 ("T", c_i64), ("S", c_i64), ("W", c_i64), ("g", c_i64),
                 ("q", c_i64), ("rho", c_i64), ("workspace_bytes", c_i64),
                 ("xcd_remap", c_i32), ("group_m", c_i32),
-                ("spin_limit", c_i64), ("all_aligned", c_i32)]
+                ("spin_limit", c_i64), ("all_aligned", c_i32), ("max_iters", c_i64)]
 
 
 P = ctypes.POINTER
@@ -90,6 +90,7 @@ PROTOTYPES = {
     "sk_device_query": (c_i32, [P(c_i32), P(c_i32), P(SkConfig), c_i32]),
     "sk_supported_tiles": (c_i32, [c_i32, P(c_i32), c_i32, P(c_i32)]),
     "sk_plan": (c_i32, [P(SkProblem), c_i32, P(SkConfig), P(SkPlanInfo)]),
+    "sk_plan_order": (c_i32, [P(SkProblem), c_i32, P(SkConfig), P(c_i32)]),
     "sk_schedule": (c_i32, [P(SkProblem), c_i32, P(SkConfig), P(SkSegment), c_i64,
                             P(c_i64)]),
     "sk_workspace_size": (c_i32, [P(SkProblem), c_i32, P(SkConfig), P(ctypes.c_size_t)]),
@@ -104,6 +105,8 @@ PROTOTYPES = {
                                    c_i32, P(SkConfig), c_vp, ctypes.c_size_t,
                                    P(SkGroupedPlan), c_vp]),
     "sk_gemm_grouped": (c_i32, [P(SkGroupedPlan), c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "sk_gemm_grouped_debug": (c_i32, [P(SkGroupedPlan), c_vp, c_vp, ctypes.c_size_t,
+                                      P(SkDebug), c_vp]),
 }
 
 _lib = None

@@ -192,7 +192,7 @@ def gemm(A, B, C=None, *, alpha=1.0, beta=0.0, out=None, out_dtype=torch.float32
 
 
 def gemm_debug(A, B, *, out_dtype=torch.float32, config, partial_delay=0, reverse_ids=0,
-               alpha=1.0, scale_a=1.0, scale_b=1.0):
+               alpha=1.0, scale_a=1.0, scale_b=1.0, workspace=None):
     """gemm() through sk_gemm_debug: returns (out, segments, cover) where
     segments is the device trace of the segments each workgroup ran (list of
     tuples in SEGMENT_FIELDS order, sorted by workgroup, SK before DP, then
@@ -212,7 +212,7 @@ def gemm_debug(A, B, *, out_dtype=torch.float32, config, partial_delay=0, revers
     dbg = SkDebug(trace.data_ptr(), cap, count.data_ptr(), cover.data_ptr(), stride,
                   partial_delay, reverse_ids)
     sp = _stream_ptr()
-    ws = Workspace(A.device)
+    ws = workspace or Workspace(A.device)
     wptr, wlen = ws.get(int(info.workspace_bytes), sp)
     check("sk_gemm_debug", lib.sk_gemm_debug(ctypes.byref(p), ctypes.c_void_p(A.data_ptr()),
                                              ctypes.c_void_p(B.data_ptr()), None,
@@ -273,6 +273,26 @@ def plan(shapes, dtype, config):
     info = SkPlanInfo()
     check("sk_plan", lib.sk_plan(probs, len(shapes), ctypes.byref(c), ctypes.byref(info)))
     return {f: int(getattr(info, f)) for f, _ in SkPlanInfo._fields_}
+
+
+def plan_order(shapes, dtype, config):
+    """Caller indices of the problems in the order a launch concatenates them."""
+    lib = load()
+    probs = _problems_array(shapes, dtype)
+    c = config.c_struct(probs[0].dtype_ab)
+    out = (ctypes.c_int32 * len(shapes))()
+    check("sk_plan_order", lib.sk_plan_order(probs, len(shapes), ctypes.byref(c), out))
+    return list(out)
+
+
+def launch_params(shapes, dtype, config):
+    """The resolved launch parameters of a problem set, as the schedule
+    simulator takes them: g, S, group_m, problem order, whether the launch
+    is the data-parallel grid, and the rule that deals whole tiles."""
+    info = plan(shapes, dtype, config)
+    return {"g": info["g"], "S": info["S"], "group_m": info["group_m"],
+            "order": plan_order(shapes, dtype, config), "dp_grid": bool(info["dp_grid"]),
+            "deal": "serpentine"}
 
 
 def schedule(shapes, dtype, config):
@@ -368,6 +388,36 @@ class GroupedGemm:
         check("sk_gemm_grouped", load().sk_gemm_grouped(
             ctypes.byref(self.plan), ctypes.c_void_p(self.desc.data_ptr()),
             ctypes.c_void_p(self.ws_ptr), self.ws_len, ctypes.c_void_p(_stream_ptr(stream))))
+
+    def run_debug(self, partial_delay=0, reverse_ids=0):
+        """run() through sk_gemm_grouped_debug: returns (segments, cover) as
+        gemm_debug does (segment problem = the caller's index)."""
+        lib = load()
+        dev = self.desc.device
+        T, g = int(self.plan.T), int(self.plan.g)
+        cap = T * 4 + g * 4 + 16
+        trace = torch.zeros((cap, 9), dtype=torch.int32, device=dev)
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+        stride = max(1, int(self.plan.max_iters))
+        cover = torch.zeros((max(1, T), stride), dtype=torch.int32, device=dev)
+        dbg = SkDebug(trace.data_ptr(), cap, count.data_ptr(), cover.data_ptr(), stride,
+                      partial_delay, reverse_ids)
+        sp = _stream_ptr()
+        check("sk_gemm_grouped_debug", lib.sk_gemm_grouped_debug(
+            ctypes.byref(self.plan), ctypes.c_void_p(self.desc.data_ptr()),
+            ctypes.c_void_p(self.ws_ptr), self.ws_len, ctypes.byref(dbg), ctypes.c_void_p(sp)))
+        if self.ws_ptr is not None:
+            code = ctypes.c_int32()
+            check("sk_check_device_error", lib.sk_check_device_error(
+                ctypes.c_void_p(self.ws_ptr), self.ws_len, ctypes.byref(code),
+                ctypes.c_void_p(sp)))
+        torch.cuda.synchronize()
+        n = int(count.item())
+        if n > cap:
+            raise RuntimeError(f"trace overflow: {n} segments > capacity {cap}")
+        rows = [tuple(int(v) for v in r) for r in trace[:n].cpu().tolist()]
+        rows.sort(key=lambda s: (s[0], s[7] == _abi.SK_ROLE_DP, s[2]))
+        return rows, cover.cpu()
 
     def capture(self):
         """A torch.cuda.CUDAGraph (a HIP graph on ROCm) holding one run()."""

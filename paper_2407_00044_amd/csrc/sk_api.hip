@@ -249,6 +249,7 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
     d.tm = (int32_t)(p.M > 0 ? cdiv(p.M, bm) : 0);
     d.tn = (int32_t)(p.N > 0 ? cdiv(p.N, bn) : 0);
     d.I = (int32_t)std::max<int64_t>(1, cdiv(p.K, bk));
+    d.user_index = P.order[i];
     d.tile_start = T;
     T += (int64_t)d.tm * d.tn;
     P.max_iters = std::max<int64_t>(P.max_iters, d.I);
@@ -289,8 +290,10 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
     P.rho = P.W % P.g;
   }
   P.ws_bytes = P.dp_grid ? 0 : ws_bytes(P.S, P.S > 0 ? P.g : 0, bm, bn);
-  // the fixup addresses all partial slots with 32-bit buffer offsets
+  // the fixup addresses all partial slots with 32-bit buffer offsets, and
+  // the workspace holds one token per persistent workgroup
   if (P.S > 0 && P.g * bm * bn * 4 > kMaxIndex) return SK_ERR_UNSUPPORTED;
+  if (!P.dp_grid && P.g > kMaxWG) return SK_ERR_UNSUPPORTED;
   P.group_m = resolve_group_m(cfg->group_m, P);
   *out = std::move(P);
   return SK_OK;
@@ -401,8 +404,10 @@ static sk_status launch(const Plan& P, const sk_config* cfg, int32_t dt, int32_t
   if (ws) {
     char* w = (char*)ws;
     kp.err = (int32_t*)w;
-    kp.flags = (int32_t*)(w + ws_flags_offset());
-    kp.slots = (float*)(w + ws_slots_offset(P.S));
+    kp.epoch = (uint32_t*)(w + 4);
+    kp.done = (uint32_t*)(w + 8);
+    kp.tokens = (uint32_t*)(w + kTokensOffset);
+    kp.slots = (float*)(w + kSlotsOffset);
   }
   if (dbg) {
     kp.trace = dbg->trace;
@@ -512,6 +517,17 @@ sk_status sk_plan(const sk_problem* probs, int32_t nprobs, const sk_config* cfg,
   info->workspace_bytes = P.ws_bytes;
   info->max_iters = P.max_iters;
   info->group_m = P.group_m;
+  info->dp_grid = P.dp_grid ? 1 : 0;
+  return SK_OK;
+}
+
+sk_status sk_plan_order(const sk_problem* probs, int32_t nprobs, const sk_config* cfg,
+                        int32_t* order) {
+  if (order == nullptr) return SK_ERR_INVALID_ARG;
+  Plan P;
+  sk_status st = plan_problems(probs, nprobs, cfg, &P);
+  if (st != SK_OK) return st;
+  for (int32_t i = 0; i < nprobs; ++i) order[i] = P.order[i];
   return SK_OK;
 }
 
@@ -632,17 +648,21 @@ sk_status sk_grouped_prepare(const sk_problem* probs, const void* const* A,
   plan->group_m = P.group_m;
   plan->spin_limit = cfg->spin_limit;
   plan->all_aligned = all_aligned;
+  plan->max_iters = P.max_iters;
   return SK_OK;
 }
 
-sk_status sk_gemm_grouped(const sk_grouped_plan* plan, const void* dev_desc, void* workspace,
-                          size_t ws_bytes_, void* stream) {
+static sk_status grouped_common(const sk_grouped_plan* plan, const void* dev_desc,
+                                void* workspace, size_t ws_bytes_, const sk_debug* dbg,
+                                void* stream) {
   if (plan == nullptr || dev_desc == nullptr || plan->nprobs <= 0) return SK_ERR_INVALID_ARG;
+  if (plan->mode < 0 || plan->mode > 3) return SK_ERR_INVALID_ARG;
   Plan P;
   P.T = plan->T; P.S = plan->S; P.W = plan->W; P.g = plan->g;
   P.q = plan->q; P.rho = plan->rho;
   P.ws_bytes = plan->workspace_bytes;
   P.group_m = plan->group_m;
+  P.max_iters = plan->max_iters;
   P.dp_grid = plan->mode == SK_MODE_DP ||
               (plan->mode == SK_MODE_AUTO && plan->S == 0 && plan->nprobs == 1);
   sk_config cfg;
@@ -653,11 +673,22 @@ sk_status sk_gemm_grouped(const sk_grouped_plan* plan, const void* dev_desc, voi
   cfg.xcd_remap = plan->xcd_remap;
   cfg.group_m = plan->group_m;
   cfg.spin_limit = plan->spin_limit;
-  if (plan->mode < 0 || plan->mode > 3) return SK_ERR_INVALID_ARG;
   cfg.mode = plan->mode;
   return launch(P, &cfg, plan->dtype_ab, plan->layout_a, plan->layout_b, plan->dtype_c, nullptr,
-                (const ProbDesc*)dev_desc, plan->nprobs, workspace, ws_bytes_, nullptr,
+                (const ProbDesc*)dev_desc, plan->nprobs, workspace, ws_bytes_, dbg,
                 (hipStream_t)stream);
+}
+
+sk_status sk_gemm_grouped(const sk_grouped_plan* plan, const void* dev_desc, void* workspace,
+                          size_t ws_bytes_, void* stream) {
+  return grouped_common(plan, dev_desc, workspace, ws_bytes_, nullptr, stream);
+}
+
+sk_status sk_gemm_grouped_debug(const sk_grouped_plan* plan, const void* dev_desc,
+                                void* workspace, size_t ws_bytes_, const sk_debug* dbg,
+                                void* stream) {
+  if (dbg == nullptr) return SK_ERR_INVALID_ARG;
+  return grouped_common(plan, dev_desc, workspace, ws_bytes_, dbg, stream);
 }
 
 }  // extern "C"

@@ -1199,7 +1199,7 @@ __device__ __forceinline__ void trace_segment(const KParams& P, int64_t x, const
   if (idx < P.trace_cap) {
     sk_segment s;
     s.wg = (int32_t)x;
-    s.problem = tr.p;
+    s.problem = prob_of(P, tr.p).user_index;
     s.tile = (int32_t)tr.t;
     s.tile_m = tr.tr;
     s.tile_n = tr.tc;
@@ -1211,15 +1211,17 @@ __device__ __forceinline__ void trace_segment(const KParams& P, int64_t x, const
   }
 }
 
-// Fixup wait: one wavefront (lane 0 of wave 0) polls the tile's arrival
-// counter with device-scope loads and backs off with s_sleep; the workgroup
-// barrier then orders every wave's (device-scope) reads of the partial
-// slots after the poll that saw all contributions.  The poll is bounded:
-// past spin_limit it raises the error word instead of hanging.
-__device__ __forceinline__ void wait_arrivals(const KParams& P, int32_t* flag, int32_t target) {
+// Fixup wait: one wavefront (lane 0 of wave 0) polls the token of peer
+// workgroup y with device-scope loads, backing off with s_sleep, until it
+// holds this launch's tag; the workgroup barrier then orders every wave's
+// (device-scope) reads of y's partial slot after the poll that saw the tag.
+// The poll is bounded: past spin_limit it raises the error word instead of
+// hanging.
+__device__ __forceinline__ void wait_token(const KParams& P, const uint32_t* token,
+                                           uint32_t tag) {
   if (threadIdx.x == 0) {
     int64_t n = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tag) {
       __builtin_amdgcn_s_sleep(2);
       if (++n > P.spin_limit) {
         __hip_atomic_store(P.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1232,11 +1234,36 @@ __device__ __forceinline__ void wait_arrivals(const KParams& P, int32_t* flag, i
 
 // Publish a partial tile: each thread waits until its device-scope stores
 // are acknowledged (visible on every XCD), the workgroup barrier collects
-// all threads, then one thread bumps the arrival counter.
-__device__ __forceinline__ void signal_arrival(int32_t* flag) {
+// all threads, then one thread writes the launch's tag into the
+// workgroup's own token (one writer per token and launch: no atomics).
+__device__ __forceinline__ void publish_token(uint32_t* token, uint32_t tag) {
   wait_vmcnt<0>();
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_store(token, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tag of the running launch: the workspace's epoch word plus one, skipping 0
+// (the value a freshly initialised token holds).
+__device__ __forceinline__ uint32_t launch_tag(const uint32_t* epoch) {
+  const uint32_t e = __hip_atomic_load(epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return e == 0xffffffffu ? 1u : e + 1u;
+}
+
+// End of a workgroup of a launch with split tiles: the last of the g
+// workgroups to get here advances the epoch to this launch's tag and clears
+// the counter.  Thread 0 waits for its own epoch load (and every other
+// memory operation of its wave) before it counts itself, so the epoch only
+// moves after every workgroup of the launch has read it.
+__device__ __forceinline__ void end_of_launch(const KParams& P, uint32_t tag) {
+  if (threadIdx.x == 0) {
+    wait_vmcnt<0>();
+    const uint32_t old = __hip_atomic_fetch_add(P.done, 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (old == (uint32_t)(P.g - 1)) {
+      __hip_atomic_store(P.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(P.epoch, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
 }
 
 // One work item of a workgroup: a Stream-K segment or a data-parallel tile.
@@ -1269,6 +1296,9 @@ __global__ __launch_bounds__(C::NT, 1) void sk_gemm_kernel(KParams P) {
     dp_t = P.S + x;
     dp_step = P.g;
   }
+  // launch tag of the fixup tokens (only lane 0 of wave 0 polls and writes)
+  const bool fixup = !P.dp_grid && P.S > 0;
+  const uint32_t tag = fixup && tid == 0 ? launch_tag(P.epoch) : 0u;
 
   while (true) {
     Item w;
@@ -1318,18 +1348,20 @@ __global__ __launch_bounds__(C::NT, 1) void sk_gemm_kernel(KParams P) {
           for (int d = 0; d < P.partial_delay; ++d) __builtin_amdgcn_s_sleep(1);
         __syncthreads();
       }
-      signal_arrival(P.flags + w.tr.t);
+      publish_token(P.tokens + x, tag);
       continue;
     }
     if (w.role == R_FINISH) {
-      wait_arrivals(P, P.flags + w.tr.t, w.npeers);
-      for (int y = 1; y <= w.npeers; ++y)
+      // peers x+1 .. x+npeers in increasing id, each added once its token
+      // carries this launch's tag
+      for (int y = 1; y <= w.npeers; ++y) {
+        wait_token(P, P.tokens + x + y, tag);
         add_partial<C>(acc, P.slots + (x + y) * (int64_t)(C::BM * C::BN), tid);
-      if (tid == 0)
-        __hip_atomic_store(P.flags + w.tr.t, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     epilogue<C>(acc, pd, P.dtype_c, m0, n0, tid);
   }
+  if (fixup) end_of_launch(P, tag);
 }
 
 }  // namespace sk

@@ -24,6 +24,8 @@ struct ProbDesc {
   int64_t tile_start;        // first global tile of this problem
   int64_t iter_start;        // global Stream-K iteration of that tile
                              // (W when the problem has no Stream-K tile)
+  int32_t user_index;        // index of the problem in the caller's array
+  int32_t pad_;
 };
 
 struct KParams {
@@ -37,7 +39,9 @@ struct KParams {
   int32_t dp_grid;           // 1: baseline grid, hardware workgroup -> tile
   int32_t reverse_ids;
   int32_t* err;              // device error word
-  int32_t* flags;            // one arrival counter per Stream-K tile
+  uint32_t* epoch;           // launches completed on this workspace
+  uint32_t* done;            // workgroups of the running launch that ended
+  uint32_t* tokens;          // per workgroup: launch tag of its partial tile
   float* slots;              // g partial tiles of BM*BN floats
   int64_t spin_limit;
   // debug hooks (nullptr when unused)
@@ -49,12 +53,20 @@ struct KParams {
   int32_t partial_delay;
 };
 
-// Workspace layout: [256 B header: error word][flags, S int32, padded to
-// 256 B][g slots of BM*BN floats].
-inline int64_t ws_flags_offset() { return 256; }
-inline int64_t ws_slots_offset(int64_t S) { return 256 + ((S * 4 + 255) / 256) * 256; }
+// Workspace layout (every offset fixed, none depends on the problem):
+//   [0, 256)            header: error word, epoch word, done counter
+//   [256, 256 + 4*kMaxWG)  one 32-bit token per persistent workgroup
+//   [kSlotsOffset, ...)  g partial tiles of BM*BN floats
+// A contributor publishes its partial tile by writing the launch's tag into
+// its own token; the tag is the epoch word plus one, and the last workgroup
+// of every launch advances the epoch, so tokens of earlier launches never
+// match and nothing has to be cleared between launches.
+constexpr int64_t kMaxWG = 4096;                       // persistent workgroups
+constexpr int64_t kHeaderBytes = 256;
+constexpr int64_t kTokensOffset = kHeaderBytes;
+constexpr int64_t kSlotsOffset = kTokensOffset + 4 * kMaxWG;   // 16640
 inline int64_t ws_bytes(int64_t S, int64_t g, int64_t bm, int64_t bn) {
-  return ws_slots_offset(S) + g * bm * bn * 4;
+  return S > 0 ? kSlotsOffset + g * bm * bn * 4 : kHeaderBytes;
 }
 
 }  // namespace sk

@@ -1,5 +1,6 @@
 """Timings of the other workloads of record, beside the FP16 3840x4096x4096
-headline of bench.py: FP32 512^3 split over 256 workgroups, the BF16 linear
+headline of bench.py: FP32 512^3 split over 256 workgroups, the 64-shape
+BF16 sweep (min and geometric mean per schedule), the BF16 linear
 layer's forward, dX and dW products, the 48-problem FP8 grouped GEMM
 (tile and schedule from the autotuner), and the headline shape in each input
 type with its MFMA peak.
@@ -126,12 +127,60 @@ def c5(dev, reps=5, tile=None):
     t_roof = sum(max(2.0 * M * N * K / 5033.2e12, (M * K + K * N + 4 * M * N) / 8.0e12)
                  for M, N, K in shapes) * 1e3
     info = g_sk.info()
+    # the persistent launch splits tiles only when the schedule gives it
+    # Stream-K tiles; with S = 0 its gain over the grouped data-parallel
+    # grid is whole-tile dealing alone
+    leg = "grouped_stream_k" if info["S"] > 0 else "grouped_persistent_whole_tiles"
     return {"workload": "48 fp8-e4m3 problems, M log-uniform [16,4096], N in {1024,2048,4096}, "
                         "K in {2048,4096,8192}", "tile": list(cfg.tile), "config": tuned,
             "gflop": round(fl / 1e9, 1), "tiles": info["T"], "stream_k_tiles": info["S"],
-            "grouped_sk_tflops": _tf(fl, t_sk), "grouped_dp_tflops": _tf(fl, t_gdp),
+            "persistent_leg": leg,
+            f"{leg}_tflops": _tf(fl, t_sk), "grouped_dp_tflops": _tf(fl, t_gdp),
             "separate_dp_tflops": _tf(fl, t_sep), "roofline_us": round(t_roof * 1e3, 1),
-            "grouped_sk_frac_of_roofline": round(t_roof / t_sk, 4)}
+            f"{leg}_frac_of_roofline": round(t_roof / t_sk, 4)}
+
+
+def c3(dev, reps=10):
+    """The 64-shape BF16 sweep (sweep.run): min and geometric-mean TFLOP/s of
+    the auto policy, the two-tile hybrid and the data-parallel grid, the
+    worst shape of each, and one compact row per shape."""
+    import io
+    from . import sweep
+    buf = io.StringIO()
+    sweep.run(n=64, reps=reps, out=buf)
+    d = json.loads(buf.getvalue())
+    sm, rows = d["summary"], d["rows"]
+
+    def worst(key):
+        r = min(rows, key=lambda r: r[key])
+        return {"shape": f"{r['M']}x{r['N']}x{r['K']}", "tflops": round(r[key], 2),
+                "dp_tflops": round(r["dp_tflops"], 2)}
+    ratio = [r["sk_tflops"] / r["dp_tflops"] for r in rows]
+    hyr = [r["hybrid_tflops"] / r["dp_tflops"] for r in rows]
+    i_auto = min(range(len(rows)), key=lambda i: ratio[i])
+    i_hy = min(range(len(rows)), key=lambda i: hyr[i])
+    return {"workload": "64 bf16 shapes, M,N log-uniform [128,8192], K log-uniform [128,16384] "
+                        "(seed 3), A row-major, B column-major, N(0,1), beta=0.5 with C_in "
+                        "U[-1,1], FP32 C, default tile per shape, graph-timed",
+            "auto_min": round(sm["sk_min"], 2), "auto_geomean": round(sm["sk_geomean"], 2),
+            "hybrid_min": round(sm["hybrid_min"], 2),
+            "hybrid_geomean": round(sm["hybrid_geomean"], 2),
+            "dp_min": round(sm["dp_min"], 2), "dp_geomean": round(sm["dp_geomean"], 2),
+            "geomean_t_dp_over_t_auto": round(sm["geomean_t_dp_over_t_sk"], 4),
+            "worst_auto": worst("sk_tflops"), "worst_hybrid": worst("hybrid_tflops"),
+            "worst_dp": worst("dp_tflops"),
+            "worst_auto_over_dp": {"shape": "{M}x{N}x{K}".format(**rows[i_auto]),
+                                   "ratio": round(ratio[i_auto], 4),
+                                   "stream_k_tiles": rows[i_auto]["S"]},
+            "worst_hybrid_over_dp": {"shape": "{M}x{N}x{K}".format(**rows[i_hy]),
+                                     "ratio": round(hyr[i_hy], 4)},
+            "shapes_split_by_auto": sum(1 for r in rows if r["S"] > 0),
+            "auto_geomean_frac_of_roofline": round(sm["sk_geomean_frac_of_roofline"], 4),
+            "rows": [[r["M"], r["N"], r["K"], f"{r['tile'][0]}x{r['tile'][1]}", r["S"],
+                      round(r["sk_tflops"], 1), round(r["hybrid_tflops"], 1),
+                      round(r["dp_tflops"], 1)] for r in rows],
+            "row_fields": ["M", "N", "K", "tile", "auto_stream_k_tiles", "auto", "hybrid",
+                           "dp"]}
 
 
 PEAK = {torch.float32: 157.3, torch.float16: 2516.6, torch.bfloat16: 2516.6,
@@ -259,7 +308,7 @@ def run_all(dev, extra=False, only=None, c5_tile=None):
     """Every configuration (`extra` adds the experiments), or the named ones;
     c5_tile runs c5 in auto mode on that tile instead of the tuner's pick."""
     out = {}
-    todo = [("c1", c1), ("c4", c4), ("c5", lambda d: c5(d, tile=c5_tile)),
+    todo = [("c1", c1), ("c3", c3), ("c4", c4), ("c5", lambda d: c5(d, tile=c5_tile)),
             ("per_dtype", per_dtype)]
     if extra or only:
         todo += [("padding", padding), ("compute_units", compute_units),

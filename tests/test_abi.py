@@ -52,7 +52,8 @@ def test_plan_closed_forms():
     p = _plan(512, 512, 512, dtype=torch.float32, tile=(128, 128), mode="sk", num_cu=256,
               min_iters=1)
     assert (p["T"], p["W"], p["q"]) == (16, 256, 1)
-    assert p["workspace_bytes"] == 256 + 256 + 256 * 128 * 128 * 4
+    # fixed layout: 256-byte header, 4096 tokens, then 256 partial tiles
+    assert p["workspace_bytes"] == 256 + 4 * 4096 + 256 * 128 * 128 * 4
     p = _plan(384, 384, 128, dtype=torch.float32, tile=(128, 128), mode="dp", num_cu=4)
     assert (p["T"], p["S"], p["g"], p["workspace_bytes"]) == (9, 0, 9, 0)
     p = _plan(8192, 4096, 11008, tile=(256, 128), num_cu=256)   # T mod g == 0: pure DP

@@ -6,9 +6,11 @@ layouts).
   so FP64 central differences of L computed with the oracle GEMM reproduce
   the analytic gradients up to rounding; the GPU backward is compared with
   those at 64x48x32 (X [64,32], W [48,32]);
-* full size BF16: X [8192,4096], W [11008,4096], dY [8192,11008]; sampled
-  rows of Y, dX and dW against the oracle, and the BF16 gradients equal the
-  round-to-nearest-even of the FP32 kernel outputs."""
+* a BF16 layer whose three products all split tiles, against the oracle
+  gradient;
+* full size BF16: X [8192,4096], W [11008,4096], dY [8192,11008]; every
+  element of Y, dX and dW against the oracle, and the BF16 gradients equal
+  the round-to-nearest-even of the FP32 kernel outputs."""
 import numpy as np
 import pytest
 import torch
@@ -43,8 +45,17 @@ def fd_grad(X, W, dY, wrt):
     return G
 
 
-@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
-def test_finite_differences_64x48x32(dtype):
+# (dtype, workgroups, grid floor): FP32 on 2 workgroups with the floor off
+# splits the backward's products (dX: K = 48, dW: K = 64, i.e. 2 iterations
+# of 32 each, one per workgroup), so the partial/finish fixup runs under the
+# finite-difference check; BF16 iterations hold 64 K-values, so at this size
+# every product is one iteration per tile and nothing can split (the split
+# BF16 backward is checked against the oracle gradient below).
+FD_CASES = [(torch.float32, 2, 1), (torch.float32, 7, 0), (torch.bfloat16, 7, 0)]
+
+
+@pytest.mark.parametrize("dtype,g,mi", FD_CASES)
+def test_finite_differences_64x48x32(dtype, g, mi):
     M, N, K = 64, 48, 32
     name = "f32" if dtype == torch.float32 else "bf16"
     X = synth.round_to(synth.normal((M, K), 41), name)
@@ -59,7 +70,13 @@ def test_finite_differences_64x48x32(dtype):
 
     Xg = X.to(dev()).requires_grad_(True)
     Wg = W.to(dev()).requires_grad_(True)
-    cfg = sk.Config(tile=(128, 128), mode="sk", num_cu=7)
+    cfg = sk.Config(tile=(128, 128), mode="sk", num_cu=g, min_iters=mi)
+    if mi == 1:
+        for shape in [(M, K, N), (N, K, M)]:            # dX, dW
+            p = sk.plan([shape], dtype, cfg)
+            assert p["S"] > 0 and p["g"] == 2 and p["W"] == 2
+            segs = sk.schedule([shape], dtype, cfg)
+            assert [s[7] for s in segs] == [1, 2]         # FINISH on 0, PARTIAL on 1
     Y = sk.linear(Xg, Wg, cfg, cfg, cfg)
     Y.backward(dY.to(dev()))
     tol = 1e-5 if dtype == torch.float32 else 1e-4
@@ -75,7 +92,36 @@ def test_finite_differences_64x48x32(dtype):
     assert torch.equal(Y.detach().cpu(), y32.cpu().to(dtype))
 
 
-def test_full_size_bf16_linear_sampled_rows():
+def test_bf16_backward_split_against_oracle_gradient():
+    # X [320, 384], W [448, 384]: forward 320x448x384 (6 iterations per
+    # tile), dX 320x384x448 (7), dW 448x384x320 (5) on 128x128 tiles and 5
+    # workgroups without a grid floor: every product splits tiles; the
+    # gradients against the oracle's FP64 products of the same rounded inputs
+    M, N, K = 320, 448, 384
+    X = synth.round_to(synth.normal((M, K), 44), "bf16")
+    W = synth.round_to(synth.normal((N, K), 45), "bf16")
+    dY = synth.round_to(synth.normal((M, N), 46), "bf16")
+    cfg = sk.Config(tile=(128, 128), mode="sk", num_cu=5, min_iters=1)
+    for shape in [(M, N, K), (M, K, N), (N, K, M)]:
+        assert sk.plan([shape], torch.bfloat16, cfg)["S"] > 0
+        assert any(s[7] == 1 for s in sk.schedule([shape], torch.bfloat16, cfg))
+    Xg = X.to(dev()).requires_grad_(True)
+    Wg = W.to(dev()).requires_grad_(True)
+    Y = sk.linear(Xg, Wg, cfg, cfg, cfg)
+    Y.backward(dY.to(dev()))
+    X64, W64, dY64 = (t.double().numpy() for t in (X, W, dY))
+    y32 = sk.gemm(Xg.detach(), Wg.detach().t(), config=cfg)
+    gx32 = sk.gemm(dY.to(dev()), Wg.detach(), config=cfg)
+    gw32 = sk.gemm(dY.to(dev()).t(), Xg.detach(), config=cfg)
+    assert og.rel_frobenius(as64(y32), og.gemm_dense(X64, W64.T)) <= 1e-4
+    assert og.rel_frobenius(as64(gx32), og.gemm_dense(dY64, W64)) <= 1e-4
+    assert og.rel_frobenius(as64(gw32), og.gemm_dense(dY64.T, X64)) <= 1e-4
+    assert torch.equal(Xg.grad.cpu(), gx32.cpu().to(torch.bfloat16))
+    assert torch.equal(Wg.grad.cpu(), gw32.cpu().to(torch.bfloat16))
+    assert torch.equal(Y.detach().cpu(), y32.cpu().to(torch.bfloat16))
+
+
+def test_full_size_bf16_linear_every_element():
     M, N, K = 8192, 11008, 4096
     X = synth.round_to(synth.normal((M, K), 4), "bf16")
     W = synth.round_to(synth.normal((N, K), 5), "bf16")
@@ -98,12 +144,11 @@ def test_full_size_bf16_linear_sampled_rows():
     X64 = X.double().numpy()
     W64 = W.double().numpy()
     dY64 = dY.double().numpy()
-    r = np.random.default_rng(7)
-    rows = np.unique(r.integers(0, M, 48))
-    ref = og.gemm(M, N, K, X64, K, False, W64, K, True, rows=rows)      # Y = X W^T
-    assert og.rel_frobenius(as64(y32)[rows], ref) <= 1e-4
-    ref = og.gemm(M, K, N, dY64, N, False, W64, K, False, rows=rows)    # dX = dY W
-    assert og.rel_frobenius(as64(dx32)[rows], ref) <= 1e-4
-    rows = np.unique(r.integers(0, N, 48))
-    ref = og.gemm(N, K, M, dY64, N, True, X64, K, False, rows=rows)     # dW = dY^T X
-    assert og.rel_frobenius(as64(dw32)[rows], ref) <= 1e-4
+    ref = og.gemm(M, N, K, X64, K, False, W64, K, True)       # Y = X W^T
+    assert og.rel_frobenius(as64(y32), ref) <= 1e-4
+    del ref
+    ref = og.gemm(M, K, N, dY64, N, False, W64, K, False)     # dX = dY W
+    assert og.rel_frobenius(as64(dx32), ref) <= 1e-4
+    del ref
+    ref = og.gemm(N, K, M, dY64, N, True, X64, K, False)      # dW = dY^T X
+    assert og.rel_frobenius(as64(dw32), ref) <= 1e-4

@@ -59,13 +59,46 @@ def check_group(ops, cfg, rows_per_problem=None, exact=False, replays=0):
 
 
 def test_grouped_schedule_matches_simulator():
+    # host schedule and the device trace of the launch both equal the
+    # simulator run on the launch parameters the library resolved
     shapes = synth.grouped_shapes()
     for tile in [(64, 128), (128, 128), (256, 128)]:
-        for mode, m in [("hybrid", sch.MODE_HYBRID), ("sk", sch.MODE_SK)]:
+        for mode in ["hybrid", "sk", "auto"]:
             cfg = sk.Config(tile=tile, mode=mode, num_cu=256)
-            _, sim = sch.simulate(shapes, tile[0], tile[1], 128, 256, m, group_m=-1,
-                                  min_iters=0)
-            assert sk.schedule(shapes, torch.float8_e4m3fn, cfg) == [s.as_tuple() for s in sim]
+            lp = sk.launch_params(shapes, torch.float8_e4m3fn, cfg)
+            _, sim = sch.simulate(shapes, tile[0], tile[1], 128, **lp)
+            want = [s.as_tuple() for s in sim]
+            assert sk.schedule(shapes, torch.float8_e4m3fn, cfg) == want
+
+
+@pytest.mark.parametrize("mode", ["hybrid", "sk", "auto"])
+def test_grouped_device_trace_matches_simulator(mode):
+    # the kernel's grouped tile lookup (binary search over the problems'
+    # iteration and tile offsets) against the simulator, segment by segment,
+    # on a 12-problem subset of the FP8 workload plus ragged and empty
+    # problems; every MAC iteration runs exactly once
+    shapes = synth.grouped_shapes()[:12] + [(0, 64, 64), (129, 257, 100), (16, 1024, 300)]
+    print(f"case grouped trace {len(shapes)} problems mode={mode}", flush=True)
+    ops = build(shapes, "e4m3", 900)
+    problems = [(A.view, B.view, out) for A, B, out in ops]
+    scales = [(A.scale, B.scale) for A, B, _ in ops]
+    cfg = sk.Config(tile=(128, 128), mode=mode, num_cu=256)
+    gg = sk.GroupedGemm(problems, config=cfg, scales=scales)
+    segs, cover = gg.run_debug()
+    lp = sk.launch_params(shapes, torch.float8_e4m3fn, cfg)
+    _, sim = sch.simulate(shapes, 128, 128, 128, **lp)
+    assert segs == [s.as_tuple() for s in sim]
+    T = int(gg.plan.T)
+    iters = [max(1, -(-K // 128)) for p in lp["order"] for (M, N, K) in [shapes[p]]
+             for _ in range(-(-M // 128) * -(-N // 128) if M and N else 0)]
+    assert len(iters) == T
+    for t, I in enumerate(iters):
+        assert torch.equal(cover[t, :I], torch.ones(I, dtype=torch.int32)), t
+    for i, (A, B, out) in enumerate(ops):
+        M, N = out.shape
+        if M and N:
+            ref = oracle(A, B, M, N, A.view.shape[1])
+            assert rel_err(as64(out), ref) <= TOL["e4m3"], i
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "e4m3", "f32"])
@@ -87,8 +120,8 @@ def test_grouped_integer_bit_exact_and_graph_replays():
 def test_c5_fp8_grouped_48_problems_graph():
     shapes = synth.grouped_shapes()
     ops = build(shapes, "e4m3", 500)
-    gg = check_group(ops, sk.Config(tile=(128, 128), mode="hybrid", num_cu=256),
-                     rows_per_problem=6, replays=10)
+    # every element of all 48 products against the oracle
+    gg = check_group(ops, sk.Config(tile=(128, 128), mode="hybrid", num_cu=256), replays=10)
     info = gg.info()
     assert info["nprobs"] == 48 and info["T"] > 0
 

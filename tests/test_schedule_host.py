@@ -1,5 +1,7 @@
 """The library's host schedule (C++, sk_schedule) equals the oracle's
-simulator bit for bit (CPU only)."""
+simulator bit for bit (CPU only).  The simulator is given the launch
+parameters the library resolved (workgroups, split point, tile order,
+problem order, dealing rule) and derives every segment itself."""
 import random
 
 import pytest
@@ -9,7 +11,6 @@ import paper_2407_00044_amd as sk
 from oracle import schedule as sch
 from paper_2407_00044_amd import synth
 
-MODES = {"sk": sch.MODE_SK, "hybrid": sch.MODE_HYBRID, "dp": sch.MODE_DP, "auto": sch.MODE_AUTO}
 BK = {torch.float32: 32, torch.float16: 64, torch.bfloat16: 64, torch.float8_e4m3fn: 128}
 
 
@@ -17,11 +18,16 @@ def compare(shapes, dtype, tile, g, mode, dp_tiles=-1, group_m=0, min_iters=0):
     cfg = sk.Config(tile=tile, mode=mode, num_cu=g, dp_tiles=dp_tiles, group_m=group_m,
                     min_iters=min_iters)
     lib_segs = sk.schedule(shapes, dtype, cfg)
-    plan, sim = sch.simulate(shapes, tile[0], tile[1], BK[dtype], g, MODES[mode], dp_tiles,
-                             group_m, min_iters)
+    lp = sk.launch_params(shapes, dtype, cfg)
+    plan, sim = sch.simulate(shapes, tile[0], tile[1], BK[dtype], **lp)
     assert lib_segs == [s.as_tuple() for s in sim]
-    info = sk.plan(shapes, dtype, cfg)
-    assert (info["g"], info["group_m"]) == (plan.g, plan.group_m)
+    sch.check(shapes, tile[0], tile[1], BK[dtype], plan.g, sim, order=lp["order"],
+              dp_grid=lp["dp_grid"], deal=lp["deal"])
+    # the report's decompositions: S as the oracle reads them
+    if mode in ("sk", "hybrid", "dp") and lp["g"] == g:
+        T = len(sch.tile_grid(shapes, tile[0], tile[1], BK[dtype]))
+        want = {"sk": sch.MODE_SK, "hybrid": sch.MODE_HYBRID, "dp": sch.MODE_DP}[mode]
+        assert lp["S"] == sch.split_for_mode(T, g, want, dp_tiles)
 
 
 @pytest.mark.parametrize("mode", ["sk", "hybrid", "dp", "auto"])
