@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import paper_2407_00044_amd as sk
-from gpu_util import as64, gpu, make_inputs, oracle, rel_err, run
+from gpu_util import as64, dev, gpu, make_inputs, oracle, rel_err, run
 from oracle import schedule as sch
 
 pytestmark = gpu
