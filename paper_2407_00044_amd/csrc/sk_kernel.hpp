@@ -188,6 +188,58 @@ struct KMajorStage {
 
   __device__ __forceinline__ void commit(char*, int) const {}
 
+  // Copies of whole iterations with the per-lane offsets formed once per
+  // tile (prep) and the iteration's K offset k0*EB passed as the scalar
+  // offset of the buffer instruction: an issue is one LDS base move and one
+  // buffer_load per copy.  Rows past the matrix keep an out-of-range offset.
+  uint32_t pre[NI];
+  __amdgpu_buffer_rsrc_t prs;
+
+  __device__ __forceinline__ void prep(const OpTile& o, int tid) {
+    const char* base = o.X + o.row0 * o.ld_b;
+    const int64_t rows_left = o.rows - o.row0;
+    prs = make_rsrc(base, (rows_left - 1) * o.ld_b + o.K * EB);
+    const int wave = uniform32(tid >> 6);
+    const int lane = tid & 63;
+    const uint32_t ld32 = (uint32_t)o.ld_b;
+    const int32_t rl = (int32_t)imin(rows_left, R);
+    const int lr = lane >> 3;
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int jj = wave * NI + j;
+      const int c = (lane & 7) ^ lr ^ (jj & 3);
+      const bool ok = jj * 8 + lr < rl;
+      pre[j] = ok ? (uint32_t)(jj * 8 + lr) * ld32 + (uint32_t)(c * 16) : kOOB;
+    }
+  }
+
+  // Whole iteration starting at K element k0 (k0 + KE <= K).  With on ==
+  // false every lane reads out of range: the copies only write zeros into L.
+  __device__ __forceinline__ void issue_pre(char* L, int64_t k0, int tid, bool on) const {
+    const int wave = uniform32(tid >> 6);
+    const int kb32 = uniform32((int32_t)(k0 * EB));
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int jj = wave * NI + j;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          prs, (__attribute__((address_space(3))) void*)(L + jj * 1024), 16,
+          (int)(on ? pre[j] : kOOB), kb32, 0, 0);
+    }
+  }
+
+  // Copy j alone (kb32: the iteration's scalar offset, as in issue_pre).
+  __device__ __forceinline__ void issue_one(char* L, int kb32, int tid, bool on, int j) const {
+    const int jj = uniform32(tid >> 6) * NI + j;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+        prs, (__attribute__((address_space(3))) void*)(L + jj * 1024), 16,
+        (int)(on ? pre[j] : kOOB), kb32, 0, 0);
+  }
+  __device__ __forceinline__ int k_offset(int64_t k0) const { return uniform32((int32_t)(k0 * EB)); }
+
+  __device__ __forceinline__ static bool whole(const OpTile& o, int64_t k0) {
+    return k0 + KE <= o.K;
+  }
+
   // Edge iterations.  Rows 16-byte aligned (K ends inside a chunk): every
   // chunk is one 16-byte load, and the elements at k >= K are zeroed in
   // registers.  The buffer then extends to the end of the 4-byte word that
@@ -490,6 +542,56 @@ struct MNMajorDMAStage {
 
   __device__ __forceinline__ void commit(char*, int) const {}
 
+  // Hoisted copies of whole iterations (see KMajorStage::prep): the k-row
+  // offset k0*ld is the scalar offset; chunks wholly past M (N) keep an
+  // out-of-range offset.
+  uint32_t pre[NI];
+  uint32_t pld;
+  __amdgpu_buffer_rsrc_t prs;
+
+  __device__ __forceinline__ void prep(const OpTile& o, int tid) {
+    prs = rsrc(o);
+    pld = (uint32_t)uniform32((int32_t)o.ld_b);
+    const int wave = uniform32(tid >> 6);
+    const int lane = tid & 63;
+    const uint32_t ld32 = (uint32_t)o.ld_b;
+    const int32_t rl = (int32_t)imin(o.rows - o.row0, R);
+    const int lk = lane / CPR;
+    const int pc = lane % CPR;
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int jj = wave * NI + j;
+      const int kr = jj * RPC + lk;
+      const int c = pc ^ tr_swizzle<EB, CPR>(kr);
+      pre[j] = c * EPC < rl ? (uint32_t)kr * ld32 + (uint32_t)(c * 16) : kOOB;
+    }
+  }
+
+  __device__ __forceinline__ void issue_pre(char* L, int64_t k0, int tid, bool on) const {
+    const int wave = uniform32(tid >> 6);
+    const int kb32 = uniform32((int32_t)((uint32_t)k0 * pld));
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int jj = wave * NI + j;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          prs, (__attribute__((address_space(3))) void*)(L + jj * 1024), 16,
+          (int)(on ? pre[j] : kOOB), kb32, 0, 0);
+    }
+  }
+
+  // Copy j alone (kb32: the iteration's scalar offset, as in issue_pre).
+  __device__ __forceinline__ void issue_one(char* L, int kb32, int tid, bool on, int j) const {
+    const int jj = uniform32(tid >> 6) * NI + j;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+        prs, (__attribute__((address_space(3))) void*)(L + jj * 1024), 16,
+        (int)(on ? pre[j] : kOOB), kb32, 0, 0);
+  }
+  __device__ __forceinline__ int k_offset(int64_t k0) const { return uniform32((int32_t)((uint32_t)k0 * pld)); }
+
+  __device__ __forceinline__ static bool whole(const OpTile& o, int64_t k0) {
+    return k0 + KE <= o.K;
+  }
+
   // Any alignment: every element loaded on its own (out-of-range offsets
   // read as zero), packed into chunks written at their swizzled positions.
   __device__ static void copy_slow(char* L, const OpTile& o, int64_t k0, int tid) {
@@ -525,6 +627,9 @@ struct MNMajorDMAStage {
 
 #ifndef SK_MN_TR
 #define SK_MN_TR 1
+#endif
+#ifndef SK_RING_TR
+#define SK_RING_TR 0
 #endif
 
 // Stage of an operand: K-contiguous, M/N-contiguous through transposing LDS
@@ -617,6 +722,12 @@ struct Cfg {
   static constexpr bool DMA = (LA == L_ROW || TRA) && (LB == L_COL || TRB) && SK_KMAJOR_DMA;
   static constexpr int NS_FIT = (160 * 1024) / STAGE;
   static constexpr int NSTAGE = DMA ? (NS_FIT > 4 ? 4 : NS_FIT) : 2;
+  // Stages refilled right after their last read (mac_loop_ring) when both
+  // operands are K-contiguous.  Transposing LDS reads take twice the LDS
+  // read instructions per step and need the two-step look-ahead of
+  // mac_loop_dma (three or more stages) or mac_loop_fast (two).
+  static constexpr bool RING = DMA && ((!TRA && !TRB) || (SK_RING_TR && STEPS == 4));
+  static constexpr int RING_LA = (TRA || TRB) ? 2 : 1;
   // LDS-direct copies issued per wave for one iteration
   static constexpr int NLOADS = (BM + BN) / (NT / 8);
   // LDS read instructions per matrix-core step
@@ -868,13 +979,67 @@ __device__ __forceinline__ void step_with_reads(Acc<C>& acc, const Frag<C::DT> (
 }
 
 
+// Fragment n of a step in the order the MFMAs of the next step consume
+// them (output blocks i-major): A0, B0 .. B(FN-1), A1 .. A(FM-1).
+template <typename C>
+__device__ __forceinline__ void read_frag_n(Frag<C::DT> (&ra)[C::FM], Frag<C::DT> (&rb)[C::FN],
+                                            const ReaderA<C>& rda, const ReaderB<C>& rdb,
+                                            const char* opA, const char* opB, int rs, int n) {
+  if (n == 0) ra[0] = rda.read(opA, 0, rs);
+  else if (n <= C::FN) rb[n - 1] = rdb.read(opB, n - 1, rs);
+  else ra[n - C::FN] = rda.read(opA, n - C::FN, rs);
+}
+
+// One matrix-core step of the ring loop with the fragments of another step
+// read and, optionally, the copies of a later iteration issued: MFMA t is
+// followed by its even share of the fragment reads and copies, and a fence
+// keeps each group in place.
+template <typename C, int CB, int CE>
+__device__ __forceinline__ void step_fenced(
+    Acc<C>& acc, const Frag<C::DT> (&fa)[C::FM], const Frag<C::DT> (&fb)[C::FN],
+    Frag<C::DT> (&ra)[C::FM], Frag<C::DT> (&rb)[C::FN], const ReaderA<C>& rda,
+    const ReaderB<C>& rdb, const char* opA, const char* opB, int rs,
+    const typename C::StageA& sa, const typename C::StageB& sb, char* dst, int64_t k0, bool on,
+    int tid) {
+  // copies CB .. CE-1 of the iteration's NA + NB (A's first)
+  constexpr int NM = C::FM * C::FN;
+  constexpr int NRF = C::FM + C::FN;
+  constexpr int NA = C::StageA::NI;
+  constexpr int NCP = CE - CB;
+  int kba = 0, kbb = 0;
+  if constexpr (NCP > 0) {
+    kba = sa.k_offset(k0);
+    kbb = sb.k_offset(k0);
+  }
+#pragma unroll
+  for (int t = 0; t < NM; ++t) {
+    mma<C::DT>(acc.a[t / C::FN][t % C::FN], fa[t / C::FN], fb[t % C::FN]);
+#pragma unroll
+    for (int n = t * NRF / NM; n < (t + 1) * NRF / NM; ++n)
+      read_frag_n<C>(ra, rb, rda, rdb, opA, opB, rs, n);
+#pragma unroll
+    for (int c = CB + t * NCP / NM; c < CB + (t + 1) * NCP / NM; ++c) {
+      if (c < NA) sa.issue_one(dst, kba, tid, on, c);
+      else sb.issue_one(dst + C::BOFF, kbb, tid, on, c - NA);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 template <int N>
 __device__ __forceinline__ void wait_vmcnt_le(int ahead_iters) {
   // wait until at most `ahead_iters` iterations' copies (N each) are in
-  // flight; ahead_iters is 0, 1 or 2
-  if (ahead_iters >= 2) wait_vmcnt<2 * N < 64 ? 2 * N : 63>();
+  // flight; ahead_iters is 0 .. 3
+  static_assert(3 * N < 64, "vmcnt range");
+  if (ahead_iters >= 3) wait_vmcnt<3 * N>();
+  else if (ahead_iters == 2) wait_vmcnt<2 * N>();
   else if (ahead_iters == 1) wait_vmcnt<N>();
   else wait_vmcnt<0>();
+}
+
+// Waits until every LDS access (and scalar load) of this wave has completed.
+__device__ __forceinline__ void wait_lgkmcnt0() {
+  __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));
 }
 
 template <typename C>
@@ -942,6 +1107,105 @@ __device__ __forceinline__ void mac_loop_dma(Acc<C>& acc, const OpTile& oa, cons
   __syncthreads();   // the stages are reused by the next segment
 }
 
+// Multi-stage MAC loop whose stages are refilled as soon as they have been
+// read (LDS-direct copies of both operands; any number of stages >= 2).
+//
+// Fragments are read LA matrix-core steps ahead of the MFMAs that use them
+// (LA = 1: two fragment buffers; LA = 2, for transposing reads, which take
+// twice the LDS instructions: four), the reads of a step spread evenly over
+// the MFMAs of the step that issues them.  Once the reads of the
+// iteration's last step are issued (before step ST-LA), nothing of stage k
+// is read again: each wave waits for its own LDS reads, then for its copies
+// of iteration k+1, and the workgroup barrier makes both facts hold for
+// every wave.  After it, the copies of iteration k+NSTAGE go into stage k,
+// spread over the MFMAs of the iteration's last LA steps, while the first
+// fragments of iteration k+1 are read.  A copy therefore has NSTAGE-1 whole
+// iterations to land, which lets a tile whose stage fills more than half of
+// the LDS (256x256: 64 KiB) keep one copy in flight behind every iteration
+// with two stages.  Every iteration in [kb, ke) must be whole (K elements
+// k*KE .. k*KE+KE-1 all below K): the copies' per-lane offsets are formed
+// once (prep) and only rows past M or N are masked.
+template <typename C>
+__device__ __forceinline__ void mac_loop_ring(Acc<C>& acc, const OpTile& oa, const OpTile& ob,
+                                              int kb, int ke, char* lds, int tid,
+                                              int32_t* cover_row) {
+  constexpr int NS = C::NSTAGE;
+  constexpr int ST = C::STEPS;
+  constexpr int LA = C::RING_LA;
+  constexpr int NBUF = LA == 1 ? 2 : 4;
+  constexpr int NCP = C::StageA::NI + C::StageB::NI;
+  static_assert(NS >= 2 && NS <= 4 && ST % NBUF == 0 && LA <= ST, "ring loop shape");
+  typename C::StageA sa;
+  typename C::StageB sb;
+  sa.prep(oa, tid);
+  sb.prep(ob, tid);
+  const int wave = uniform32(tid >> 6);
+  const int lane = tid & 63;
+  ReaderA<C> rda;
+  ReaderB<C> rdb;
+  rda.init((wave / C::WGN) * C::WM, lane);
+  rdb.init((wave % C::WGN) * C::WN, lane);
+
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    if (kb + j < ke) {
+      sa.issue_pre(lds + j * C::STAGE, (int64_t)(kb + j) * C::KE, tid, true);
+      sb.issue_pre(lds + j * C::STAGE + C::BOFF, (int64_t)(kb + j) * C::KE, tid, true);
+    }
+  }
+  // copies of iteration kb landed in every wave (later ones may be in flight)
+  wait_vmcnt_le<C::NLOADS>((int)imin(NS - 1, ke - 1 - kb));
+  __builtin_amdgcn_s_barrier();
+
+  Frag<C::DT> fa[NBUF][C::FM], fb[NBUF][C::FN];
+#pragma unroll
+  for (int s0 = 0; s0 < LA; ++s0)
+#pragma unroll
+    for (int n = 0; n < C::FM + C::FN; ++n)
+      read_frag_n<C>(fa[s0], fb[s0], rda, rdb, lds, lds + C::BOFF, s0, n);
+
+  int slot = 0;
+  for (int k = kb; k < ke; ++k) {
+    char* cur = lds + slot * C::STAGE;
+    const bool more = k + 1 < ke;
+    const int nslot = slot == NS - 1 ? 0 : slot + 1;
+    // the last iteration's look-ahead re-reads its own (landed) stage
+    const char* nxt = more ? lds + nslot * C::STAGE : cur;
+    if (cover_row != nullptr && tid == 0) atomicAdd(cover_row + k, 1);
+    // iteration k+NS refills stage k (past ke the copies read nothing and
+    // zero the stage, which no later iteration of this loop reads)
+    const int64_t kn0 = (int64_t)(k + NS) * C::KE;
+    const bool refill = k + NS < ke;
+#pragma unroll
+    for (int s = 0; s < ST; ++s) {
+      const int rs = s + LA < ST ? s + LA : s + LA - ST;     // step read ahead
+      const char* src = s + LA < ST ? cur : nxt;
+      if (s == ST - LA) {
+        // stage k is read (this wave's reads completed), and the copies of
+        // iteration k+1 landed (at most NS-2 later iterations in flight)
+        wait_lgkmcnt0();
+        wait_vmcnt_le<C::NLOADS>((int)imin(NS - 2, imax(ke - 2 - k, 0)));
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (s < ST - LA)
+        step_fenced<C, 0, 0>(acc, fa[s % NBUF], fb[s % NBUF], fa[(s + LA) % NBUF],
+                             fb[(s + LA) % NBUF], rda, rdb, src, src + C::BOFF, rs, sa, sb, cur,
+                             kn0, refill, tid);
+      else if (LA == 1 || s == ST - 2)
+        step_fenced<C, 0, (LA == 1 ? NCP : NCP / 2)>(
+            acc, fa[s % NBUF], fb[s % NBUF], fa[(s + LA) % NBUF], fb[(s + LA) % NBUF], rda, rdb,
+            src, src + C::BOFF, rs, sa, sb, cur, kn0, refill, tid);
+      else
+        step_fenced<C, NCP / 2, NCP>(acc, fa[s % NBUF], fb[s % NBUF], fa[(s + LA) % NBUF],
+                                     fb[(s + LA) % NBUF], rda, rdb, src, src + C::BOFF, rs, sa,
+                                     sb, cur, kn0, refill, tid);
+    }
+    slot = nslot;
+  }
+  __syncthreads();   // the stages are reused by the next segment
+}
+
 // One iteration through the element-wise path (edges the fast path cannot
 // take).  Called after a barrier; ends with one.
 template <typename C>
@@ -979,8 +1243,13 @@ __device__ __forceinline__ void mac_loop(Acc<C>& acc, const ProbDesc& pd, int64_
   else if (ke > kb && (C::StageA::slow(oa, (int64_t)(ke - 1) * C::KE) ||
                        C::StageB::slow(ob, (int64_t)(ke - 1) * C::KE)))
     kf = ke - 1;
+  // the ring loop takes whole iterations only: a last iteration that ends
+  // past K goes to the masked per-iteration path below
+  if constexpr (C::RING)
+    if (kf > kb && !C::StageA::whole(oa, (int64_t)(kf - 1) * C::KE)) --kf;
   if (kf > kb) {
-    if constexpr (C::DMA && C::NSTAGE >= 3) mac_loop_dma<C>(acc, oa, ob, kb, kf, lds, tid, cover_row);
+    if constexpr (C::RING) mac_loop_ring<C>(acc, oa, ob, kb, kf, lds, tid, cover_row);
+    else if constexpr (C::DMA && C::NSTAGE >= 3) mac_loop_dma<C>(acc, oa, ob, kb, kf, lds, tid, cover_row);
     else mac_loop_fast<C>(acc, oa, ob, kb, kf, lds, tid, cover_row);
   }
   for (int k = kf; k < ke; ++k) {
