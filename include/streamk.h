@@ -192,22 +192,29 @@ typedef struct {
                         nothing to split on one problem) */
 } sk_plan_info;
 
-/* Returns a static English description of a status code. */
+/* Returns a static English description of a status code (library
+ * mechanism; no passage of the report). */
 const char* sk_status_string(int32_t status);
 
 /* Device facts for the current HIP device: number of compute units, and the
  * number of workgroups of the kernel selected by (cfg tile, dtype_ab) that
- * can be resident on one CU at once.  Either output may be NULL. */
+ * can be resident on one CU at once.  Either output may be NULL.  (The
+ * persistent grid is sized from the CU count: the report's "Compute Units"
+ * argument, Methodology.) */
 sk_status sk_device_query(int32_t* num_cu, int32_t* max_wg_per_cu,
                           const sk_config* cfg, int32_t dtype_ab);
 
 /* Lists the tiles built for dtype_ab as (block_m, block_n, block_k)
  * triples in `out` (3*capacity ints; may be NULL to count).  `count`
- * receives the number of tiles. */
+ * receives the number of tiles.  (A small menu per precision: the report's
+ * Background argues one Stream-K configuration per precision suffices.) */
 sk_status sk_supported_tiles(int32_t dtype_ab, int32_t* out, int32_t capacity,
                              int32_t* count);
 
-/* Host-only.  Schedule parameters of `nprobs` problems under `cfg`.  The
+/* Host-only.  Schedule parameters of `nprobs` problems under `cfg`: tiles,
+ * iterations, the split point of the data-parallel + Stream-K hybrid and the
+ * even share q, rho of each workgroup (Background: even work units over all
+ * cores; Methodology: "Compute Units").  The
  * problems are concatenated as in a grouped launch: ordered by MAC
  * iterations per tile, ceil(K / block_k), largest first, ties in the given
  * order, so that the whole tiles dealt to the persistent workgroups (in
@@ -223,7 +230,9 @@ sk_status sk_plan(const sk_problem* probs, int32_t nprobs,
 sk_status sk_plan_order(const sk_problem* probs, int32_t nprobs,
                         const sk_config* cfg, int32_t* order);
 
-/* Host-only.  The complete schedule: for each logical workgroup in order,
+/* Host-only.  The complete schedule (Background: the MAC iterations of all
+ * tiles split evenly, a tile crossing a boundary finished by a fixup; Figure
+ * 1's data-parallel comparison is SK_MODE_DP): for each logical workgroup in order,
  * its Stream-K segments in processing order, then its data-parallel tiles
  * in increasing tile order.  With out == NULL only *count is set; with too
  * small a capacity *count is set and SK_ERR_CAPACITY returned. */
@@ -231,7 +240,8 @@ sk_status sk_schedule(const sk_problem* probs, int32_t nprobs,
                       const sk_config* cfg, sk_segment* out, int64_t capacity,
                       int64_t* count);
 
-/* Bytes of workspace a launch of `probs` under `cfg` needs.  The layout
+/* Bytes of workspace a launch of `probs` under `cfg` needs: room for the
+ * partial tiles of the fixup that finishes split tiles (Background).  The layout
  * has fixed offsets, the same for every problem and config:
  *   [0, 256)        header: error word, epoch word, done counter;
  *   [256, 16640)    one 32-bit token per persistent workgroup (at most 4096);
@@ -253,7 +263,9 @@ sk_status sk_workspace_size(const sk_problem* probs, int32_t nprobs,
  * invalid, later launches on the workspace are not affected). */
 sk_status sk_workspace_init(void* workspace, size_t bytes, void* hip_stream);
 
-/* One GEMM: C_out = alpha*scale_a*scale_b*A*B + beta*C_in.
+/* One GEMM: C_out = alpha*scale_a*scale_b*A*B + beta*C_in (the product the
+ * report studies: Introduction, Background; its M x N x K problems, Results,
+ * Table 1), on the schedule of sk_schedule.
  * workspace/ws_bytes: at least sk_workspace_size bytes, initialised once by
  * sk_workspace_init; not shared with a concurrent launch.  May be NULL for
  * SK_MODE_DP.  M == 0 or N == 0 is a no-op; K == 0 gives beta*C_in.
@@ -286,7 +298,8 @@ sk_status sk_gemm_debug(const sk_problem* p, const void* A, const void* B,
                         size_t ws_bytes, const sk_config* cfg,
                         const sk_debug* dbg, void* hip_stream);
 
-/* Reads and clears the workspace's device error word (synchronises
+/* Library mechanism (no passage of the report: its fixup wait is
+ * unbounded).  Reads and clears the workspace's device error word (synchronises
  * hip_stream).  Returns SK_ERR_DEVICE_TIMEOUT if a fixup wait of an earlier
  * launch gave up, SK_OK otherwise; *code receives the raw word if non-NULL. */
 sk_status sk_check_device_error(void* workspace, size_t ws_bytes,
