@@ -23,7 +23,9 @@
  * Pointers.     Every data pointer (A, B, C_in, C_out, workspace, device
  *               descriptors) is caller-owned device memory of the current HIP
  *               device.  The library never allocates or frees device memory
- *               and never keeps a pointer after a call returns.
+ *               and never keeps a pointer after a call returns; its only
+ *               device memory of its own is the static scratch array of
+ *               sk_gemm_noalloc.
  * Streams.      `hip_stream` is a hipStream_t passed as void* (NULL = the
  *               null stream).  Launch entry points only enqueue work and
  *               return; they do not synchronise.
@@ -301,9 +303,33 @@ sk_status sk_gemm_debug(const sk_problem* p, const void* A, const void* B,
 /* Library mechanism (no passage of the report: its fixup wait is
  * unbounded).  Reads and clears the workspace's device error word (synchronises
  * hip_stream).  Returns SK_ERR_DEVICE_TIMEOUT if a fixup wait of an earlier
- * launch gave up, SK_OK otherwise; *code receives the raw word if non-NULL. */
+ * launch gave up, SK_OK otherwise; *code receives the raw word if non-NULL.
+ * workspace NULL: the scratch of sk_gemm_noalloc on the current device
+ * (SK_OK if that entry point has not run there); ws_bytes is then ignored. */
 sk_status sk_check_device_error(void* workspace, size_t ws_bytes,
                                 int32_t* code, void* hip_stream);
+
+/* ---- Allocation-free GEMM ------------------------------------------------
+ * For callers that cannot allocate device memory or pass a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same problem, operands, config, arithmetic and schedule as
+ * sk_gemm; the workspace is instead a static device array of
+ * SK_NOALLOC_SCRATCH_BYTES per GPU (256 B header + 4096 arrival tokens +
+ * 256 partial tiles of 256x256 FP32, i.e. 64 MiB + 16.25 KiB), held by the
+ * library until the process ends.  No device memory is allocated or freed.
+ * The first call on a device looks the array up and enqueues one fill
+ * kernel on hip_stream that clears its header and tokens.
+ * Errors: SK_ERR_WORKSPACE when the plan needs more than the array
+ * (sk_workspace_size > SK_NOALLOC_SCRATCH_BYTES, e.g. more than 256
+ * persistent workgroups at 256x256), otherwise as sk_gemm.  A fixup wait
+ * that gives up is reported by sk_check_device_error(NULL, 0, ...).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams or host threads without ordering) race and give
+ * wrong results; calls ordered on one stream are safe. */
+#define SK_NOALLOC_SCRATCH_BYTES ((size_t)16640 + (size_t)256 * 256 * 256 * 4)
+sk_status sk_gemm_noalloc(const sk_problem* p, const void* A, const void* B,
+                          const void* C_in, void* C_out, const sk_config* cfg,
+                          void* hip_stream);
 
 /* ---- Grouped GEMM: one persistent launch over several problems ----------
  * The MAC iterations of all problems' Stream-K tiles are counted together

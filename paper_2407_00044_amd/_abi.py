@@ -100,6 +100,7 @@ PROTOTYPES = {
     "sk_gemm_debug": (c_i32, [P(SkProblem), c_vp, c_vp, c_vp, c_vp, c_vp,
                               ctypes.c_size_t, P(SkConfig), P(SkDebug), c_vp]),
     "sk_check_device_error": (c_i32, [c_vp, ctypes.c_size_t, P(c_i32), c_vp]),
+    "sk_gemm_noalloc": (c_i32, [P(SkProblem), c_vp, c_vp, c_vp, c_vp, P(SkConfig), c_vp]),
     "sk_grouped_desc_size": (c_i32, [c_i32, P(ctypes.c_size_t)]),
     "sk_grouped_prepare": (c_i32, [P(SkProblem), P(c_vp), P(c_vp), P(c_vp), P(c_vp),
                                    c_i32, P(SkConfig), c_vp, ctypes.c_size_t,

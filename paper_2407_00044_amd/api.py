@@ -191,6 +191,43 @@ def gemm(A, B, C=None, *, alpha=1.0, beta=0.0, out=None, out_dtype=torch.float32
     return out
 
 
+def gemm_noalloc(A, B, C=None, *, alpha=1.0, beta=0.0, out=None, out_dtype=torch.float32,
+                 scale_a=1.0, scale_b=1.0, config=None, stream=None):
+    """gemm() through sk_gemm_noalloc: the library's static per-GPU scratch
+    array is the workspace, so the call allocates no device memory (with out
+    given).  Calls that overlap on one GPU race; see include/streamk.h."""
+    lib = load()
+    if not (A.is_cuda and B.is_cuda):
+        raise ValueError("operands must be on the GPU")
+    M, N = A.shape[0], B.shape[1]
+    if out is None:
+        out = C if (C is not None and beta != 0.0) else torch.empty(
+            (M, N), dtype=out_dtype, device=A.device)
+    if beta != 0.0 and C is None:
+        raise ValueError("beta != 0 needs C")
+    p = _problem(A, B, out, alpha, beta, scale_a, scale_b)
+    cfg = config or Config(tile=default_tile(M, N, A.shape[1], A.dtype))
+    if C is not None and beta != 0.0:
+        if tuple(C.shape) != (M, N) or C.dtype != out.dtype or C.stride() != out.stride():
+            raise ValueError("C must match out in shape, dtype and strides")
+    c = cfg.c_struct(p.dtype_ab)
+    cin = C.data_ptr() if (C is not None and beta != 0.0) else None
+    check("sk_gemm_noalloc", lib.sk_gemm_noalloc(
+        ctypes.byref(p), ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+        ctypes.c_void_p(cin), ctypes.c_void_p(out.data_ptr()), ctypes.byref(c),
+        ctypes.c_void_p(_stream_ptr(stream))))
+    return out
+
+
+def check_noalloc_error(stream=None):
+    """Raise if a fixup wait of an earlier gemm_noalloc launch on this GPU
+    timed out (reads and clears the scratch's error word)."""
+    code = ctypes.c_int32()
+    check("sk_check_device_error", load().sk_check_device_error(
+        None, 0, ctypes.byref(code), ctypes.c_void_p(_stream_ptr(stream))))
+    return code.value
+
+
 def gemm_debug(A, B, *, out_dtype=torch.float32, config, partial_delay=0, reverse_ids=0,
                alpha=1.0, scale_a=1.0, scale_b=1.0, workspace=None):
     """gemm() through sk_gemm_debug: returns (out, segments, cover) where

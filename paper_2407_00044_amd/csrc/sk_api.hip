@@ -446,6 +446,46 @@ static sk_status gemm_common(const sk_problem* p, const void* A, const void* B, 
                 ws_bytes_, dbg, (hipStream_t)stream);
 }
 
+// ---------------------------------------------------------------------------
+// Workspace of sk_gemm_noalloc: a file-scope device array, one copy per GPU,
+// held until the process ends.  Its size covers every tile of the menu up to
+// 256x256 on 256 persistent workgroups.  In host code `scratch` names a
+// host-side stand-in, never the device array: the device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+constexpr int64_t kScratchBytes = kSlotsOffset + (int64_t)256 * 256 * 256 * 4;
+static_assert(kScratchBytes == SK_NOALLOC_SCRATCH_BYTES, "scratch size in the header");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch;   // device -> address of its scratch
+
+// Address of the current device's scratch.  With setup, the first call on a
+// device looks the address up and clears the header and tokens (error word,
+// epoch, done counter, arrival tokens) with a fill kernel on `stream`;
+// without, a device not yet set up yields nullptr.
+static sk_status device_scratch(hipStream_t stream, bool setup, void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SK_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(dev);
+  if (it != g_scratch.end()) {
+    *out = it->second;
+    return SK_OK;
+  }
+  *out = nullptr;
+  if (!setup) return SK_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr)
+    return SK_ERR_HIP;
+  const int64_t words = kSlotsOffset / 4;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0,
+                     stream, (uint32_t*)ptr, words);
+  if (hipGetLastError() != hipSuccess) return SK_ERR_HIP;
+  g_scratch[dev] = ptr;
+  *out = ptr;
+  return SK_OK;
+}
+
 }  // namespace sk
 
 using namespace sk;
@@ -579,9 +619,27 @@ sk_status sk_gemm_debug(const sk_problem* p, const void* A, const void* B, const
   return gemm_common(p, A, B, C_in, C_out, workspace, ws_bytes_, cfg, dbg, stream);
 }
 
+sk_status sk_gemm_noalloc(const sk_problem* p, const void* A, const void* B, const void* C_in,
+                          void* C_out, const sk_config* cfg, void* stream) {
+  void* ws = nullptr;
+  sk_status st = device_scratch((hipStream_t)stream, true, &ws);
+  if (st != SK_OK) return st;
+  return gemm_common(p, A, B, C_in, C_out, ws, (size_t)kScratchBytes, cfg, nullptr, stream);
+}
+
 sk_status sk_check_device_error(void* workspace, size_t ws_bytes_, int32_t* code,
                                 void* stream) {
-  if (workspace == nullptr || ws_bytes_ < 4) return SK_ERR_INVALID_ARG;
+  if (workspace == nullptr) {
+    // the scratch of sk_gemm_noalloc on the current device
+    sk_status st = device_scratch((hipStream_t)stream, false, &workspace);
+    if (st != SK_OK) return st;
+    if (workspace == nullptr) {
+      if (code) *code = 0;
+      return SK_OK;
+    }
+    ws_bytes_ = (size_t)kScratchBytes;
+  }
+  if (ws_bytes_ < 4) return SK_ERR_INVALID_ARG;
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SK_ERR_HIP;
   int32_t v = 0;
   if (hipMemcpy(&v, workspace, 4, hipMemcpyDeviceToHost) != hipSuccess) return SK_ERR_HIP;
