@@ -90,20 +90,12 @@ typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
  *   SK_MODE_DP      baseline data-parallel grid: one workgroup per tile,
  *                   no persistence, no fixup, no workspace.
  *   SK_MODE_AUTO    SK_MODE_HYBRID, except that S = 0 (no tile is split)
- *                   when Stream-K's even share b = ceil(W_all/g), plus a
- *                   quarter for lost L2 reuse, plus one partial tile (f MAC
- *                   iterations of fixup: max(4, BM*BN/8192) for 16-bit and
- *                   e4m3 tiles, max(1, BM*BN/32768) for FP32, whose
- *                   iterations take ~4.5x longer) is no shorter than the
- *                   data-parallel waves:
- *                   b + ceil(b/4) + f >= ceil(T/g) * ceil(W_all/T) (FP32
- *                   iterations, too slow for the L2 loss to show: b + f >=
- *                   ...), W_all = MAC iterations of all tiles, g after the
- *                   grid floor.
- *                   When the data-parallel launch is one partial wave
- *                   (T < g) and the floor did not shrink g, the left side
- *                   is taken 9/8 times (T busy workgroups outrun g).
- *                   Constants measured on MI355X; not in the report. */
+ *                   unless the launch-time model (sk_cost_model) predicts
+ *                   the launch without splits to be more than `margin`
+ *                   (1.08) times slower; with nothing split on one problem
+ *                   the launch is the data-parallel grid itself.  The
+ *                   model's constants are measured on MI355X; not in the
+ *                   report. */
 typedef enum {
   SK_MODE_HYBRID = 0, SK_MODE_SK = 1, SK_MODE_DP = 2, SK_MODE_AUTO = 3
 } sk_mode;
@@ -192,6 +184,8 @@ typedef struct {
   int64_t dp_grid;   /* 1: the launch is the data-parallel grid (one
                         workgroup per tile: SK_MODE_DP, or SK_MODE_AUTO with
                         nothing to split on one problem) */
+  double predicted_us;     /* launch-time model (sk_cost_model): this launch */
+  double predicted_dp_us;  /* ... and the data-parallel grid of the problems */
 } sk_plan_info;
 
 /* Returns a static English description of a status code (library
@@ -226,6 +220,27 @@ sk_status sk_supported_tiles(int32_t dtype_ab, int32_t* out, int32_t capacity,
  * when no HIP device is present. */
 sk_status sk_plan(const sk_problem* probs, int32_t nprobs,
                   const sk_config* cfg, sk_plan_info* info);
+
+/* Host-only.  Constants of the launch-time model that SK_MODE_AUTO uses
+ * (the report names a predictive block-to-time model as future work:
+ * Results, the Block2Time paragraph; Future Work).  A launch's predicted time
+ * is t_launch plus its slowest workgroup's time; a workgroup's time sums,
+ * over its segments in the order of sk_schedule,
+ *   t_tile + iterations * t_it(n) * (1 + l2 for Stream-K segments)
+ *   + t_cin (epilogue with beta != 0) + t_store (PARTIAL)
+ *   + npeers * t_peer (FINISH, after every peer's PARTIAL has been stored),
+ * with t_it(n) = t_it_light + (t_it_full - t_it_light) * clamp((n-64)/192,
+ * 0, 1) for n workgroups at once; a data-parallel grid of T tiles on C CUs
+ * takes ceil(T / C) waves (several problems: max(longest tile, work / C)).
+ * SK_MODE_AUTO splits tiles only when the launch without splits is
+ * predicted `margin` times slower.  constants[0..9] = t_launch, t_tile,
+ * t_it_full, t_it_light, t_store, t_peer (microseconds), l2, t_cin
+ * (microseconds), margin, and the table row's tile as block_m * 65536 +
+ * block_n (the row of the same type with the nearest tile area when
+ * (block_m, block_n) has none; f16 uses bf16's).  n >= 10.  Measured on
+ * MI355X per type and tile (paper_2407_00044_amd/calibrate.py). */
+sk_status sk_cost_model(int32_t dtype_ab, int32_t block_m, int32_t block_n,
+                        float* constants, int32_t n);
 
 /* Host-only.  The order in which a launch concatenates the problems:
  * order[i] is the caller's index of the i-th problem (nprobs entries). */

@@ -60,7 +60,8 @@ class SkSegment(ctypes.Structure):
 class SkPlanInfo(ctypes.Structure):
     _fields_ = [("T", c_i64), ("S", c_i64), ("W", c_i64), ("g", c_i64),
                 ("q", c_i64), ("rho", c_i64), ("workspace_bytes", c_i64),
-                ("max_iters", c_i64), ("group_m", c_i64), ("dp_grid", c_i64)]
+                ("max_iters", c_i64), ("group_m", c_i64), ("dp_grid", c_i64),
+                ("predicted_us", ctypes.c_double), ("predicted_dp_us", ctypes.c_double)]
 
 
 class SkDebug(ctypes.Structure):
@@ -91,6 +92,7 @@ PROTOTYPES = {
     "sk_supported_tiles": (c_i32, [c_i32, P(c_i32), c_i32, P(c_i32)]),
     "sk_plan": (c_i32, [P(SkProblem), c_i32, P(SkConfig), P(SkPlanInfo)]),
     "sk_plan_order": (c_i32, [P(SkProblem), c_i32, P(SkConfig), P(c_i32)]),
+    "sk_cost_model": (c_i32, [c_i32, c_i32, c_i32, P(ctypes.c_float), c_i32]),
     "sk_schedule": (c_i32, [P(SkProblem), c_i32, P(SkConfig), P(SkSegment), c_i64,
                             P(c_i64)]),
     "sk_workspace_size": (c_i32, [P(SkProblem), c_i32, P(SkConfig), P(ctypes.c_size_t)]),

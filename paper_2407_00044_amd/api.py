@@ -285,31 +285,49 @@ def check_device_error(workspace=None, stream=None):
 # ---------------------------------------------------------------------------
 # Host-only queries (no GPU needed when num_cu is given).
 
-def _host_problem(M, N, K, dtype, layout_a="row", layout_b="col"):
+def _host_problem(M, N, K, dtype, layout_a="row", layout_b="col", beta=0.0):
     code = DTYPE_CODES[dtype] if isinstance(dtype, torch.dtype) else dtype
     la = SK_ROW_MAJOR if layout_a == "row" else SK_COL_MAJOR
     lb = SK_ROW_MAJOR if layout_b == "row" else SK_COL_MAJOR
     lda = max(1, K if la == SK_ROW_MAJOR else M)
     ldb = max(1, N if lb == SK_ROW_MAJOR else K)
-    return SkProblem(M, N, K, la, lb, lda, ldb, max(1, N), code, _abi.SK_F32, 1.0, 0.0,
+    return SkProblem(M, N, K, la, lb, lda, ldb, max(1, N), code, _abi.SK_F32, 1.0, beta,
                      1.0, 1.0)
 
 
-def _problems_array(shapes, dtype):
+def _problems_array(shapes, dtype, beta=0.0):
     arr = (SkProblem * len(shapes))()
     for i, (M, N, K) in enumerate(shapes):
-        arr[i] = _host_problem(M, N, K, dtype)
+        arr[i] = _host_problem(M, N, K, dtype, beta=beta)
     return arr
 
 
-def plan(shapes, dtype, config):
-    """Schedule parameters (dict) of problems [(M, N, K), ...]."""
+def plan(shapes, dtype, config, beta=0.0):
+    """Schedule parameters (dict) of problems [(M, N, K), ...] (beta: of
+    every problem; it changes only the launch-time predictions)."""
     lib = load()
-    probs = _problems_array(shapes, dtype)
+    probs = _problems_array(shapes, dtype, beta)
     c = config.c_struct(probs[0].dtype_ab)
     info = SkPlanInfo()
     check("sk_plan", lib.sk_plan(probs, len(shapes), ctypes.byref(c), ctypes.byref(info)))
-    return {f: int(getattr(info, f)) for f, _ in SkPlanInfo._fields_}
+    return {f: (float(getattr(info, f)) if f.startswith("predicted") else int(getattr(info, f)))
+            for f, _ in SkPlanInfo._fields_}
+
+
+def cost_model(dtype, tile):
+    """Constants of the launch-time model the auto mode uses for (dtype,
+    tile): a dict of t_launch, t_tile, t_it_full, t_it_light, t_store,
+    t_peer (microseconds), l2, t_cin (microseconds), margin and the table
+    row's tile."""
+    code = DTYPE_CODES[dtype] if isinstance(dtype, torch.dtype) else dtype
+    out = (ctypes.c_float * 10)()
+    check("sk_cost_model", load().sk_cost_model(code, tile[0], tile[1], out, 10))
+    names = ["t_launch", "t_tile", "t_it_full", "t_it_light", "t_store", "t_peer", "l2",
+             "t_cin", "margin"]
+    d = {n: float(v) for n, v in zip(names, out)}
+    row = int(out[9])
+    d["row_tile"] = (row // 65536, row % 65536)
+    return d
 
 
 def plan_order(shapes, dtype, config):

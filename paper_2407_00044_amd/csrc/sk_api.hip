@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/streamk.h"
+#include "sk_cost.hpp"
 #include "sk_params.hpp"
 #include "sk_registry.hpp"
 #include "sk_sched.hpp"
@@ -50,6 +51,8 @@ struct Plan {
   int64_t ws_bytes = 0;
   int32_t group_m = 0;           // resolved tile order
   bool dp_grid = false;          // one workgroup per tile, no fixup
+  double pred_us = 0.0;          // launch-time model: this launch
+  double pred_dp_us = 0.0;       // ... and the data-parallel grid of the problems
   std::vector<ProbDesc> descs;   // pointers left null by plan_problems
   std::vector<int32_t> order;    // descs[i] describes caller problem order[i]
 };
@@ -119,7 +122,8 @@ static sk_status check_problem(const sk_problem& p) {
 }
 
 // Resolves g and checks the config against the tile menu.
-static sk_status resolve_config(const sk_config* cfg, int32_t dtype_ab, int64_t* g_out) {
+static sk_status resolve_config(const sk_config* cfg, int32_t dtype_ab, int64_t* g_out,
+                                int64_t* cus_out) {
   if (cfg == nullptr) return SK_ERR_INVALID_ARG;
   if (cfg->mode < 0 || cfg->mode > 3) return SK_ERR_INVALID_ARG;
   if (cfg->block_k != k_per_iter(dtype_ab)) return SK_ERR_UNSUPPORTED;
@@ -134,6 +138,7 @@ static sk_status resolve_config(const sk_config* cfg, int32_t dtype_ab, int64_t*
   }
   const int64_t wpc = cfg->wg_per_cu == 0 ? 1 : cfg->wg_per_cu;
   *g_out = (int64_t)cus * wpc;
+  *cus_out = cus;
   return SK_OK;
 }
 
@@ -205,9 +210,40 @@ static int32_t resolve_group_m(int32_t group_m, const Plan& P) {
   return 8;
 }
 
-// Tile counts, split point, iteration space and per-problem offsets.
+// Iteration space, even split, workspace and tile order of a plan whose
+// problems, tiles, g and S are set.
+static sk_status finish_plan(Plan* P, const sk_config* cfg, int64_t bm, int64_t bn) {
+  // Stream-K iteration offsets (problem-major, so J is monotone in p).
+  int64_t J = 0;
+  for (ProbDesc& d : P->descs) {
+    const int64_t ti = (int64_t)d.tm * d.tn;
+    d.iter_start = J;
+    const int64_t sk_tiles = std::max<int64_t>(0, std::min<int64_t>(ti, P->S - d.tile_start));
+    J += sk_tiles * d.I;
+  }
+  if (J > kMaxIndex) return SK_ERR_UNSUPPORTED;
+  P->W = J;
+  P->q = P->rho = 0;
+  if (!P->dp_grid && P->g > 0) {
+    P->q = P->W / P->g;
+    P->rho = P->W % P->g;
+  }
+  P->ws_bytes = P->dp_grid ? 0 : ws_bytes(P->S, P->S > 0 ? P->g : 0, bm, bn);
+  // the fixup addresses all partial slots with 32-bit buffer offsets, and
+  // the workspace holds one token per persistent workgroup
+  if (P->S > 0 && P->g * bm * bn * 4 > kMaxIndex) return SK_ERR_UNSUPPORTED;
+  if (!P->dp_grid && P->g > kMaxWG) return SK_ERR_UNSUPPORTED;
+  P->group_m = resolve_group_m(cfg->group_m, *P);
+  return SK_OK;
+}
+
+static double predict_us(const Plan& P, const CostRow& c, int64_t cus);
+
+// Tile counts, split point, iteration space and per-problem offsets.  With
+// `predict`, the launch-time model's predictions of the resolved launch and
+// of the data-parallel grid are filled in (SK_MODE_AUTO always uses them).
 static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_config* cfg,
-                               Plan* out) {
+                               Plan* out, bool predict = false) {
   if (probs == nullptr || n <= 0) return SK_ERR_INVALID_ARG;
   for (int32_t i = 0; i < n; ++i) {
     sk_status st = check_problem(probs[i]);
@@ -216,8 +252,8 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
         probs[i].layout_a != probs[0].layout_a || probs[i].layout_b != probs[0].layout_b)
       return SK_ERR_UNSUPPORTED;
   }
-  int64_t g = 0;
-  sk_status st = resolve_config(cfg, probs[0].dtype_ab, &g);
+  int64_t g = 0, cus = 0;
+  sk_status st = resolve_config(cfg, probs[0].dtype_ab, &g, &cus);
   if (st != SK_OK) return st;
   const int64_t bm = cfg->block_m, bn = cfg->block_n, bk = cfg->block_k;
   for (int32_t i = 0; i < n; ++i)
@@ -263,38 +299,50 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
   } else {
     int64_t W_all = 0;
     for (int32_t i = 0; i < n; ++i) W_all += (int64_t)P.descs[i].tm * P.descs[i].tn * P.descs[i].I;
-    const int64_t fix = fixup_iters(bm, bn, bk);
-    P.g = grid_floor(g, T, W_all, cfg->min_iters, fix);
-    P.S = split_point(T, W_all, P.g, cfg->mode, cfg->dp_tiles, fix, bk == 32 ? 0 : 1, g);
-    // auto mode with nothing to split on one problem: the data-parallel
-    // grid itself (the hardware hands out tiles as workgroups finish, which
-    // beats a fixed round-robin of whole tiles over persistent workgroups)
-    if (cfg->mode == SK_MODE_AUTO && P.S == 0 && n == 1) {
-      P.g = T;
-      P.dp_grid = true;
+    P.g = grid_floor(g, T, W_all, cfg->min_iters, fixup_iters(bm, bn, bk));
+    P.S = split_point(T, P.g, cfg->mode, cfg->dp_tiles);
+  }
+  st = finish_plan(&P, cfg, bm, bn);
+  if (st != SK_OK) return st;
+
+  const bool is_auto = cfg->mode == SK_MODE_AUTO;
+  if (is_auto || predict) {
+    const CostRow& c = *cost_row(probs[0].dtype_ab, (int32_t)bm, (int32_t)bn);
+    // the data-parallel grid of the same problems (one workgroup per tile)
+    Plan D = P;
+    D.S = 0;
+    D.g = T;
+    D.dp_grid = true;
+    st = finish_plan(&D, cfg, bm, bn);
+    if (st != SK_OK) return st;
+    P.pred_us = predict_us(P, c, cus);
+    P.pred_dp_us = predict_us(D, c, cus);
+    if (is_auto && P.S > 0) {
+      // SK_MODE_AUTO: split tiles only if the model predicts the launch
+      // without splits (the data-parallel grid for one problem, whole tiles
+      // on the persistent workgroups for several) to be kAutoMargin times
+      // slower
+      Plan A = P;
+      if (n == 1) {
+        A = D;
+        A.pred_us = P.pred_dp_us;
+      } else {
+        A.S = 0;
+        st = finish_plan(&A, cfg, bm, bn);
+        if (st != SK_OK) return st;
+        A.pred_us = predict_us(A, c, cus);
+      }
+      A.pred_dp_us = P.pred_dp_us;
+      if (!(A.pred_us > kAutoMargin * P.pred_us)) P = std::move(A);
+    } else if (is_auto && P.S == 0 && n == 1) {
+      // nothing to split on one problem: the data-parallel grid itself (the
+      // hardware hands out tiles as workgroups finish, which beats a fixed
+      // round-robin of whole tiles over persistent workgroups)
+      const double dp = P.pred_dp_us;
+      P = std::move(D);
+      P.pred_us = P.pred_dp_us = dp;
     }
   }
-  // Stream-K iteration offsets (problem-major, so J is monotone in p).
-  int64_t J = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    ProbDesc& d = P.descs[i];
-    const int64_t ti = (int64_t)d.tm * d.tn;
-    d.iter_start = J;
-    const int64_t sk_tiles = std::max<int64_t>(0, std::min<int64_t>(ti, P.S - d.tile_start));
-    J += sk_tiles * d.I;
-  }
-  if (J > kMaxIndex) return SK_ERR_UNSUPPORTED;
-  P.W = J;
-  if (!P.dp_grid && P.g > 0) {
-    P.q = P.W / P.g;
-    P.rho = P.W % P.g;
-  }
-  P.ws_bytes = P.dp_grid ? 0 : ws_bytes(P.S, P.S > 0 ? P.g : 0, bm, bn);
-  // the fixup addresses all partial slots with 32-bit buffer offsets, and
-  // the workspace holds one token per persistent workgroup
-  if (P.S > 0 && P.g * bm * bn * 4 > kMaxIndex) return SK_ERR_UNSUPPORTED;
-  if (!P.dp_grid && P.g > kMaxWG) return SK_ERR_UNSUPPORTED;
-  P.group_m = resolve_group_m(cfg->group_m, P);
   *out = std::move(P);
   return SK_OK;
 }
@@ -361,6 +409,78 @@ static void host_segments(const Plan& P, const sk_config* cfg, std::vector<sk_se
       emit(x, p, t, t - P.descs[p].tile_start, 0, P.descs[p].I, SK_ROLE_DP, 0);
     }
   }
+}
+
+// Predicted time in microseconds of the launch P under the launch-time
+// model (sk_cost.hpp): every workgroup's segments walked as the kernel walks
+// them; the launch ends with its slowest workgroup.
+static double predict_us(const Plan& P, const CostRow& c, int64_t cus) {
+  if (P.T == 0) return 0.0;
+  cus = std::max<int64_t>(1, cus);
+  auto tile_cost = [&](const ProbDesc& d, double it) {
+    return c.t_tile + d.I * it + (d.beta != 0.f ? c.t_cin : 0.0);
+  };
+  if (P.dp_grid) {
+    const double it = iter_time(c, std::min<int64_t>(P.T, cus));
+    if (P.descs.size() == 1) return c.t_launch + (double)cdiv(P.T, cus) * tile_cost(P.descs[0], it);
+    double sum = 0.0, mx = 0.0;   // several problems: work over the CUs, or the longest tile
+    for (const ProbDesc& d : P.descs) {
+      const int64_t tiles = (int64_t)d.tm * d.tn;
+      if (tiles == 0) continue;
+      const double tc = tile_cost(d, it);
+      sum += (double)tiles * tc;
+      mx = std::max(mx, tc);
+    }
+    return c.t_launch + std::max(mx, sum / (double)cus);
+  }
+  const int64_t g = P.g;
+  const double it = iter_time(c, std::min<int64_t>(g, cus));
+  const double it_sk = it * (1.0 + c.l2);
+  auto range = [&](int64_t x, int64_t* s, int64_t* e) {
+    *s = range_begin(x, P.q, P.rho);
+    *e = *s + P.q + (x < P.rho ? 1 : 0);
+  };
+  // a PARTIAL segment is its workgroup's first: when its partial is published
+  std::vector<double> ready((size_t)g, 0.0);
+  for (int64_t x = 0; x < g; ++x) {
+    int64_t s, e;
+    range(x, &s, &e);
+    if (s >= e) continue;
+    const ProbDesc& d = P.descs[host_find_problem(P, s, true)];
+    const int64_t J = d.iter_start + (s - d.iter_start) / d.I * d.I;
+    if (s > J)
+      ready[(size_t)x] = c.t_tile + (double)(std::min(e, J + d.I) - s) * it_sk + c.t_store;
+  }
+  double worst = 0.0;
+  for (int64_t x = 0; x < g; ++x) {
+    int64_t s, e;
+    range(x, &s, &e);
+    double t = 0.0;
+    for (int64_t i = s; i < e;) {
+      const ProbDesc& d = P.descs[host_find_problem(P, i, true)];
+      const int64_t J = d.iter_start + (i - d.iter_start) / d.I * d.I;
+      const int64_t kb = i - J, ke = std::min(e, J + d.I) - J;
+      t += c.t_tile + (double)(ke - kb) * it_sk;
+      if (kb > 0) {
+        t += c.t_store;                                   // PARTIAL
+      } else {
+        if (ke < d.I) {                                   // FINISH
+          const int64_t last = iter_owner(J + d.I - 1, P.q, P.rho);
+          for (int64_t y = x + 1; y <= last; ++y) t = std::max(t, ready[(size_t)y]);
+          t += (double)(last - x) * c.t_peer;
+        }
+        if (d.beta != 0.f) t += c.t_cin;
+      }
+      i = J + ke;
+    }
+    for (int64_t r = 0;; ++r) {          // whole tiles: position x, or g-1-x in odd rounds
+      const int64_t tt = P.S + r * g + ((r & 1) ? g - 1 - x : x);
+      if (tt >= P.T) break;
+      t += tile_cost(P.descs[host_find_problem(P, tt, false)], it);
+    }
+    worst = std::max(worst, t);
+  }
+  return c.t_launch + worst;
 }
 
 __global__ void fill_zero_kernel(uint32_t* p, int64_t words) {
@@ -550,9 +670,11 @@ sk_status sk_plan(const sk_problem* probs, int32_t nprobs, const sk_config* cfg,
                   sk_plan_info* info) {
   if (info == nullptr) return SK_ERR_INVALID_ARG;
   Plan P;
-  sk_status st = plan_problems(probs, nprobs, cfg, &P);
+  sk_status st = plan_problems(probs, nprobs, cfg, &P, true);
   if (st != SK_OK) return st;
   info->T = P.T; info->S = P.S; info->W = P.W; info->g = P.g;
+  info->predicted_us = P.pred_us;
+  info->predicted_dp_us = P.pred_dp_us;
   info->q = P.q; info->rho = P.rho;
   info->workspace_bytes = P.ws_bytes;
   info->max_iters = P.max_iters;
@@ -568,6 +690,18 @@ sk_status sk_plan_order(const sk_problem* probs, int32_t nprobs, const sk_config
   sk_status st = plan_problems(probs, nprobs, cfg, &P);
   if (st != SK_OK) return st;
   for (int32_t i = 0; i < nprobs; ++i) order[i] = P.order[i];
+  return SK_OK;
+}
+
+sk_status sk_cost_model(int32_t dtype_ab, int32_t block_m, int32_t block_n, float* constants,
+                        int32_t n) {
+  if (constants == nullptr || n < 10 || dtype_ab < 0 || dtype_ab > 3) return SK_ERR_INVALID_ARG;
+  const CostRow* c = cost_row(dtype_ab, block_m, block_n);
+  if (c == nullptr) return SK_ERR_UNSUPPORTED;
+  const float v[10] = {c->t_launch, c->t_tile, c->t_it_full, c->t_it_light, c->t_store,
+                       c->t_peer, c->l2, c->t_cin, (float)kAutoMargin,
+                       (float)(c->bm * 65536 + c->bn)};
+  for (int i = 0; i < 10; ++i) constants[i] = v[i];
   return SK_OK;
 }
 

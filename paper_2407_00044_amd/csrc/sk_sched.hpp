@@ -60,33 +60,15 @@ SK_HD int64_t fixup_iters(int64_t bm, int64_t bn, int64_t bk) {
   return bk == 32 ? imax(1, bm * bn / 32768) : imax(4, bm * bn / 8192);
 }
 
-// Split point S for T tiles (W_all MAC iterations in all) on g workgroups.
-// Hybrid (mode 0): the two-tile rule.  Auto (mode 3): the same, except that
-// no tile is split when Stream-K's even share b = ceil(W_all/g), a quarter
-// more for the L2 reuse lost by workgroups at different k-phases (l2 = 1;
-// FP32 iterations move too few bytes per clock for that loss to show:
-// l2 = 0), plus one partial tile is no shorter than the data-parallel waves:
-// b + l2*ceil(b/4) + fix >= ceil(T/g) * ceil(W_all/T).  When the
-// data-parallel grid is one partial wave (T < g) of a launch the grid floor
-// did not shrink (g == g_full), that cost is taken 9/8 times: the T busy
-// workgroups of the data-parallel launch run faster than g busy Stream-K
-// ones (measured: a predicted gain under ~12% was a loss there).
-SK_HD int64_t split_point(int64_t T, int64_t W_all, int64_t g, int32_t mode, int64_t dp_tiles,
-                          int64_t fix, int64_t l2, int64_t g_full) {
+// Split point S for T tiles on g workgroups.  Hybrid (mode 0) and auto
+// (mode 3, whose host policy may then keep S = 0): the two-tile rule, S = 0
+// when T is a multiple of g, else min(T, T mod g + g).  All Stream-K (mode
+// 1): S = T.  dp_tiles >= 0 overrides: S = T - dp_tiles.
+SK_HD int64_t split_point(int64_t T, int64_t g, int32_t mode, int64_t dp_tiles) {
   int64_t S;
   if (mode == 2) return 0;                 // baseline DP grid
-  if (mode == 1) {
-    S = T;                                 // all Stream-K
-  } else {
-    S = (g <= 0 || T % g == 0) ? 0 : imin(T, T % g + g);
-    if (mode == 3 && S > 0) {
-      const int64_t b = cdiv(W_all, g);
-      const int64_t sk = b + l2 * cdiv(b, 4) + fix;
-      const int64_t dp = cdiv(T, g) * cdiv(W_all, T);
-      const bool one_wave = T < g && g == g_full;
-      if ((one_wave ? 9 * sk : 8 * sk) >= 8 * dp) S = 0;
-    }
-  }
+  if (mode == 1) S = T;                    // all Stream-K
+  else S = (g <= 0 || T % g == 0) ? 0 : imin(T, T % g + g);
   if (dp_tiles >= 0) S = T - imin(dp_tiles, T);
   return S;
 }

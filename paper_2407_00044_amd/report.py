@@ -176,11 +176,19 @@ def c3(dev, reps=10):
                                      "ratio": round(hyr[i_hy], 4)},
             "shapes_split_by_auto": sum(1 for r in rows if r["S"] > 0),
             "auto_geomean_frac_of_roofline": round(sm["sk_geomean_frac_of_roofline"], 4),
+            "model": {"median_abs_err": round(sm["model_median_abs_err"], 4),
+                      "p90_abs_err": round(sm["model_p90_abs_err"], 4),
+                      "shapes_with_split_candidate": sm["model_shapes_with_split_candidate"],
+                      "choice_was_faster": sm["model_choice_was_faster"],
+                      "choice_faster_or_within_2pct": sm["model_choice_faster_or_within_2pct"]},
             "rows": [[r["M"], r["N"], r["K"], f"{r['tile'][0]}x{r['tile'][1]}", r["S"],
                       round(r["sk_tflops"], 1), round(r["hybrid_tflops"], 1),
-                      round(r["dp_tflops"], 1)] for r in rows],
+                      round(r["dp_tflops"], 1), round(r["hybrid_us"], 2),
+                      round(r["pred_hybrid_us"], 2), round(r["dp_us"], 2),
+                      round(r["pred_dp_us"], 2)] for r in rows],
             "row_fields": ["M", "N", "K", "tile", "auto_stream_k_tiles", "auto", "hybrid",
-                           "dp"]}
+                           "dp", "hybrid_us", "predicted_hybrid_us", "dp_us",
+                           "predicted_dp_us"]}
 
 
 PEAK = {torch.float32: 157.3, torch.float16: 2516.6, torch.bfloat16: 2516.6,

@@ -76,6 +76,9 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False,
             return lambda: api.gemm(A, B, C, beta=0.5, out=outC, config=cfg, workspace=ws)
         t_sk, t_hy, t_dp = _time_all([go(cfg_sk), go(cfg_hy), go(cfg_dp)], reps)
         p = api.plan([(M, N, K)], dtype, cfg_sk)
+        # the launch-time model's predictions (Block2Time-style) beside the
+        # measured times of the two launches the auto mode chooses between
+        ph = api.plan([(M, N, K)], dtype, cfg_hy, beta=0.5)
         T = p["T"]
         q_eff = T / (math.ceil(T / cus) * cus)
         flops = 2.0 * M * N * K
@@ -87,7 +90,9 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False,
                "roofline_tflops": roof,
                "sk_tflops": flops / t_sk / 1e9, "hybrid_tflops": flops / t_hy / 1e9,
                "dp_tflops": flops / t_dp / 1e9,
-               "dp_quant_eff": q_eff, "t_dp_over_t_sk": t_dp / t_sk}
+               "dp_quant_eff": q_eff, "t_dp_over_t_sk": t_dp / t_sk,
+               "hybrid_us": t_hy * 1e3, "dp_us": t_dp * 1e3, "hybrid_S": ph["S"],
+               "pred_hybrid_us": ph["predicted_us"], "pred_dp_us": ph["predicted_dp_us"]}
         if all_tiles:
             row["tiles"] = {}
             for t in [x[:2] for x in api.supported_tiles(dtype) if x[:2] in ALL_TILES]:
@@ -123,6 +128,19 @@ def run(n=64, reps=10, use_tuner=False, seed=3, out=sys.stdout, all_tiles=False,
                "dp_geomean_frac_of_roofline": gmean([r["dp_tflops"] / r["roofline_tflops"]
                                                      for r in rows]),
                "geomean_t_dp_over_t_sk": gmean([r["t_dp_over_t_sk"] for r in rows])}
+    # the model against measurement: error of each predicted time, and how
+    # often the auto mode's choice (split or not) was the faster launch
+    errs = sorted([abs(r["pred_hybrid_us"] / r["hybrid_us"] - 1) for r in rows if r["hybrid_S"] > 0]
+                  + [abs(r["pred_dp_us"] / r["dp_us"] - 1) for r in rows])
+    cand = [r for r in rows if r["hybrid_S"] > 0]
+    right = sum(1 for r in cand if (r["S"] > 0) == (r["hybrid_us"] < r["dp_us"]))
+    near = sum(1 for r in cand if (r["S"] > 0) == (r["hybrid_us"] < r["dp_us"])
+               or abs(r["hybrid_us"] / r["dp_us"] - 1) <= 0.02)
+    summary.update({"model_median_abs_err": errs[len(errs) // 2] if errs else 0.0,
+                    "model_p90_abs_err": errs[int(0.9 * (len(errs) - 1))] if errs else 0.0,
+                    "model_shapes_with_split_candidate": len(cand),
+                    "model_choice_was_faster": right,
+                    "model_choice_faster_or_within_2pct": near})
     if use_tuner:
         tb = [r["tuned"]["tflops"] for r in rows]
         # the default policy (auto mode, default tile) against the tuned best

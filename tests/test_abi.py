@@ -62,7 +62,7 @@ def test_plan_closed_forms():
     # m = 17, 17 workgroups
     p = _plan(607, 187, 3155, tile=(256, 128), num_cu=256)
     assert (p["T"], p["g"], p["q"], p["rho"]) == (6, 17, 17, 11)
-    p = _plan(607, 187, 3155, tile=(256, 128), num_cu=256, min_iters=1)
+    p = _plan(607, 187, 3155, tile=(256, 128), num_cu=256, min_iters=1, mode="hybrid")
     assert (p["g"], p["q"], p["rho"]) == (256, 1, 44)
 
 

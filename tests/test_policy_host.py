@@ -9,16 +9,19 @@ hand from the rules the header states:
   m = ceil(I_mean / c), c the largest integer >= 1 with f c^2 <= I_mean,
   f = max(4, BM*BN/8192) MAC iterations per partial tile for 16-bit and e4m3
   iterations, max(1, BM*BN/32768) for FP32 iterations;
-* SK_MODE_AUTO: no split when b + ceil(b/4) + f >= ceil(T/g') * I_mean
-  (FP32: b + f), b = ceil(W_all/g'), the left side taken 9/8 times when the
-  data-parallel launch is one partial wave on an unshrunk grid; with nothing
-  split on one problem the launch is the data-parallel grid;
+* SK_MODE_AUTO: tiles split only when the launch-time model predicts the
+  launch without splits to be `margin` times slower; the model's makespan
+  is checked against a second evaluation of its documented formula from the
+  library's schedule and constants; with nothing split on one problem the
+  launch is the data-parallel grid;
 * automatic tile order (group_m = -1): with Stream-K tiles, bands of the
   largest divisor of q/gcd(q, I) not above the tile rows; otherwise 8;
 * grouped launches: problems by iterations per tile, largest first (the
   data-parallel grid keeps the caller's order).
 """
 import random
+
+import pytest
 
 import torch
 
@@ -101,46 +104,108 @@ def test_auto_tile_order_hand_values():
     assert t(p, "q", "group_m") == (352, 22)
 
 
-def test_auto_mode_cost_rule():
-    # 9 tiles of 4 16-bit iterations on 4 workgroups: b + ceil(b/4) + 4 =
-    # 9 + 3 + 4 = 16 >= 3 waves x 4 = 12 -> no split; hybrid keeps S = 5
-    assert P((384, 384, 256), BF16, (128, 128), 4, "auto")["S"] == 0
-    assert P((384, 384, 256), BF16, (128, 128), 4, "hybrid")["S"] == 5
-    # FP32 iterations: no L2 term, f = 1: 9 + 1 = 10 < 12 -> S = 5
-    assert P((384, 384, 128), F32, (128, 128), 4, "auto")["S"] == 5
-    # FP32 3840x4096x4096 on 128x128: 960 tiles x 128 on 256: 480 + 1 <
-    # 4 x 128 -> split, S = 960 mod 256 + 256 = 448
-    p = P((3840, 4096, 4096), F32, (128, 128), 256, "auto")
-    assert t(p, "T", "S") == (960, 448)
-    # 480 tiles x 64 on 256 (256x128): 120 + 30 + 4 = 154 >= 128 -> DP grid
-    p = P((3840, 4096, 4096), F16, (256, 128), 256, "auto")
-    assert t(p, "S", "W", "g", "dp_grid") == (0, 0, 480, 1)
-    # ... a grouped launch stays on the persistent grid
+def _model_time(shapes, dtype, tile, g, mode, beta=0.0, **kw):
+    """The launch-time model of sk_cost_model, evaluated here from the
+    library's schedule and constants (a second implementation of the
+    documented formula)."""
+    cfg = sk.Config(tile=tile, mode=mode, num_cu=g, **kw)
+    c = sk.cost_model(dtype, tile)
+    plan = sk.plan(shapes, dtype, cfg, beta=beta)
+    segs = sk.schedule(shapes, dtype, cfg)
+    I = {i: max(1, -(-K // {F32: 32, F16: 64, BF16: 64, E4: 128}[dtype]))
+         for i, (_, _, K) in enumerate(shapes)}
+    cin = c["t_cin"] if beta != 0.0 else 0.0
+
+    def t_it(n):
+        f = min(1.0, max(0.0, (n - 64) / 192.0))
+        return c["t_it_light"] + (c["t_it_full"] - c["t_it_light"]) * f
+
+    if plan["dp_grid"]:
+        it = t_it(min(plan["T"], g))
+        costs = [c["t_tile"] + I[s[1]] * it + cin for s in segs]
+        if len(shapes) == 1:
+            return c["t_launch"] + -(-plan["T"] // g) * costs[0], plan
+        return c["t_launch"] + max(max(costs), sum(costs) / g), plan
+    it = t_it(min(plan["g"], g))
+    it_sk = it * (1 + c["l2"])
+    by_wg = {}
+    for s in segs:
+        by_wg.setdefault(s[0], []).append(s)
+    ready = {}
+    for x, ss in by_wg.items():
+        wg, p, tile_i, tm, tn, kb, ke, role, npeers = ss[0]
+        if role == 2:
+            ready[x] = c["t_tile"] + (ke - kb) * it_sk + c["t_store"]
+    worst = 0.0
+    for x, ss in by_wg.items():
+        t = 0.0
+        for wg, p, tile_i, tm, tn, kb, ke, role, npeers in ss:
+            if role == 3:
+                t += c["t_tile"] + I[p] * it + cin
+                continue
+            t += c["t_tile"] + (ke - kb) * it_sk
+            if role == 2:
+                t += c["t_store"]
+                continue
+            if role == 1:
+                t = max([t] + [ready[x + y] for y in range(1, npeers + 1)])
+                t += npeers * c["t_peer"]
+            t += cin
+        worst = max(worst, t)
+    return c["t_launch"] + worst, plan
+
+
+@pytest.mark.parametrize("shapes,dtype,tile,g,mode,kw", [
+    ([(512, 512, 512)], F32, (128, 128), 256, "sk", {"min_iters": 1}),
+    ([(512, 512, 512)], F32, (128, 128), 256, "hybrid", {}),
+    ([(3840, 4096, 4096)], F16, (256, 128), 256, "hybrid", {}),
+    ([(3840, 4096, 4096)], F16, (256, 128), 256, "dp", {}),
+    ([(1000, 700, 900)], BF16, (128, 128), 13, "hybrid", {"min_iters": 1}),
+    ([(1000, 700, 900)], BF16, (128, 128), 4, "hybrid", {"min_iters": 1}),
+    ([(4826, 1341, 13813)], BF16, (256, 256), 256, "hybrid", {}),
+    ([(700, 300, 2000)], E4, (64, 128), 64, "hybrid", {"min_iters": 1}),
+    ([(1000, 700, 900), (300, 200, 4000), (64, 64, 64)], BF16, (128, 128), 32, "hybrid",
+     {"min_iters": 1}),
+    ([(1000, 700, 900), (300, 200, 4000)], BF16, (128, 128), 32, "dp", {}),
+])
+def test_cost_model_matches_second_implementation(shapes, dtype, tile, g, mode, kw):
+    for beta in (0.0, 0.5):
+        want, plan = _model_time(shapes, dtype, tile, g, mode, beta, **kw)
+        assert abs(plan["predicted_us"] - want) <= 1e-6 * want, (plan["predicted_us"], want)
+        dp, _ = _model_time(shapes, dtype, tile, g, "dp", beta)
+        assert abs(plan["predicted_dp_us"] - dp) <= 1e-6 * dp
+
+
+def test_auto_mode_follows_the_model():
+    margin = sk.cost_model(BF16, (128, 128))["margin"]
+    assert margin == pytest.approx(1.08)
+    cases = [((512, 512, 512), F32, (128, 128)), ((3840, 4096, 4096), F16, (256, 128)),
+             ((3840, 4096, 4096), BF16, (256, 256)), ((1286, 292, 1415), BF16, (128, 128)),
+             ((4826, 1341, 13813), BF16, (256, 256)), ((607, 187, 3155), BF16, (256, 128)),
+             ((6160, 303, 2722), E4, (128, 128)), ((2190, 3876, 2048), BF16, (128, 128))]
+    split = []
+    for shape, dtype, tile in cases:
+        h = P(shape, dtype, tile, 256, "hybrid")
+        a = P(shape, dtype, tile, 256, "auto")
+        if h["S"] == 0:
+            assert a["S"] == 0 and a["dp_grid"] == 1
+            continue
+        # one problem: split iff the data-parallel grid is predicted
+        # `margin` times slower than the hybrid launch
+        if h["predicted_dp_us"] > margin * h["predicted_us"]:
+            assert t(a, "S", "g", "dp_grid") == (h["S"], h["g"], 0)
+            assert a["predicted_us"] == h["predicted_us"]
+            split.append(shape)
+        else:
+            assert t(a, "S", "g", "dp_grid") == (0, h["T"], 1)
+            assert a["predicted_us"] == h["predicted_dp_us"]
+    # long K on few tiles: Stream-K wins by the model (and by measurement);
+    # the headline shape on 256x128 tiles: the data-parallel grid
+    assert (512, 512, 512) in split and (4826, 1341, 13813) in split
+    assert (3840, 4096, 4096) not in split
+    # a grouped launch with nothing split stays on the persistent grid
     p = P([(3840, 4096, 4096)] * 2, F16, (256, 128), 256, "auto")
-    assert t(p, "S", "g", "dp_grid") == (0, 256, 0)
-    # 2190x3876x2048 on 128x128: 558 tiles x 32: b = 70, 70 + 18 + 4 = 92 <
-    # 96 -> two-tile rule, S = 558 mod 256 + 256 = 302
-    assert t(P((2190, 3876, 2048), BF16, (128, 128), 256, "auto"), "T", "S") == (558, 302)
-    # K = 1024 (16 iterations): b = 35, 35 + 9 + 4 = 48 >= 48 -> DP
-    p = P((2190, 3876, 1024), BF16, (128, 128), 256, "auto")
-    assert t(p, "T", "S", "dp_grid") == (558, 0, 1)
-    # ... and on 256x256 (f = 8): 144 tiles, b = 9, 9 + 3 + 8 >= 16 -> DP
-    assert P((2190, 3876, 1024), BF16, (256, 256), 256, "auto")["S"] == 0
-    # one partial data-parallel wave on the full grid: e4m3 6160x303x2722 on
-    # 128x128x128, 147 tiles x 22 (floor m = 11 leaves 294 > 256): b = 13,
-    # (13 + 4 + 4) * 9/8 = 23.6 >= 22 -> DP (21 alone would split)
-    p = P((6160, 303, 2722), E4, (128, 128), 256, "auto")
-    assert t(p, "T", "g", "S", "dp_grid") == (147, 147, 0, 1)
-    # the same shape in BF16 (43 iterations): b = 25, (25 + 7 + 4) * 9/8 =
-    # 40.5 < 43 -> split
-    assert t(P((6160, 303, 2722), BF16, (128, 128), 256, "auto"), "T", "g", "S") == (
-        147, 256, 147)
-    # T < g' but the floor shrank the grid (g' = 759 // 12 = 63): no 9/8;
-    # b = 13, 13 + 4 + 4 = 21 < 23 -> split
-    assert t(P((1286, 292, 1415), BF16, (128, 128), 256, "auto"), "T", "g", "S") == (
-        33, 63, 33)
-    # long K, few tiles: 6 tiles x 50 on g' = 17: 18 + 5 + 4 = 27 < 50
-    assert t(P((607, 187, 3155), BF16, (256, 128), 256, "auto"), "g", "S") == (17, 6)
+    assert p["dp_grid"] == 0 and p["g"] == 256
 
 
 def test_grouped_problem_order_longest_first():
