@@ -111,13 +111,18 @@ def cpu_baseline(host, M, N, K, min_seconds=10.0, max_reps=4):
 
 
 def kernel_source_hash():
-    """Hash of the sources the measured kernels are built from."""
+    """Hash of the sources the measured kernels are compiled from: the
+    kernel instantiation unit and the headers it includes (host-only files,
+    sk_api.hip and sk_cost.hpp, do not change a kernel)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2407_00044_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in ("sk_inst.hip", "sk_kernel.hpp", "sk_params.hpp", "sk_registry.hpp",
+                 "sk_sched.hpp"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + f.read())
+    with open(os.path.join(ROOT, "include", "streamk.h"), "rb") as f:
+        h.update(b"streamk.h" + f.read())
     return h.hexdigest()[:16]
 
 
