@@ -74,9 +74,12 @@ typedef enum {
 } sk_status;
 
 /* Input (A, B) element types.  SK_F8E4M3 is the OCP 8-bit e4m3 "fn" format
- * (finite, max 448) that gfx950 matrix cores consume.  Accumulation is FP32
- * for every input type. */
-typedef enum { SK_F32 = 0, SK_F16 = 1, SK_BF16 = 2, SK_F8E4M3 = 3 } sk_dtype;
+ * (finite, max 448) that gfx950 matrix cores consume.  SK_MXF8E4M3 is OCP
+ * MXFP8: e4m3 elements, and for every 32 consecutive K-values of each row of
+ * A and each column of B an E8M0 scale byte e (value 2^(e-127), e = 255 NaN)
+ * that multiplies them (sk_gemm_mx only).  Accumulation is FP32 for every
+ * input type. */
+typedef enum { SK_F32 = 0, SK_F16 = 1, SK_BF16 = 2, SK_F8E4M3 = 3, SK_MXF8E4M3 = 4 } sk_dtype;
 typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
 
 /* How output tiles are distributed (Background section):
@@ -290,6 +293,27 @@ sk_status sk_workspace_init(void* workspace, size_t bytes, void* hip_stream);
 sk_status sk_gemm(const sk_problem* p, const void* A, const void* B,
                   const void* C_in, void* C_out, void* workspace,
                   size_t ws_bytes, const sk_config* cfg, void* hip_stream);
+
+/* One MXFP8 GEMM (dtype_ab = SK_MXF8E4M3): as sk_gemm, with
+ *   C_out[i][j] = alpha*scale_a*scale_b * sum_k A[i][k] * 2^(sa[i][k/32]-127)
+ *                                   * B[k][j] * 2^(sb[j][k/32]-127) + beta*C_in
+ * where A, B hold e4m3 codes, sa[i][b] = ((const uint8_t*)scale_a)[i*ld_scale_a
+ * + b] and sb[j][b] = ((const uint8_t*)scale_b)[j*ld_scale_b + b] (device
+ * memory; one E8M0 byte per 32 K-values of row i of A / column j of B).
+ * The block scales are applied by the matrix cores (gfx950 scaled MFMA),
+ * products accumulate in FP32.  Block-scaled formats go beyond the report,
+ * whose CK kernel is one configuration per precision (Background); the
+ * scaled MX formats are the gfx950 matrix cores' own.
+ * Requirements (else SK_ERR_UNSUPPORTED): A row-major and B column-major,
+ * K a multiple of 128, A and B 16-byte aligned with lda, ldb multiples of
+ * 16.  scale_a/scale_b 4-byte aligned, ld_scale_a/ld_scale_b multiples of 4
+ * and >= K/32 (else SK_ERR_INVALID_ARG).  Single problems only (no grouped
+ * launch); sk_gemm with SK_MXF8E4M3 returns SK_ERR_INVALID_ARG. */
+sk_status sk_gemm_mx(const sk_problem* p, const void* A, const void* B,
+                     const void* scale_a, int64_t ld_scale_a, const void* scale_b,
+                     int64_t ld_scale_b, const void* C_in, void* C_out,
+                     void* workspace, size_t ws_bytes, const sk_config* cfg,
+                     void* hip_stream);
 
 /* Debug hooks of sk_gemm_debug (all device pointers may be NULL). */
 typedef struct {

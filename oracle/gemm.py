@@ -15,7 +15,9 @@ evaluated in IEEE double on the *same rounded inputs* the GPU receives: the
 bf16 / f16 / e4m3fn / f32 codes are decoded exactly to float64 by the decoders
 below, which are written from the published bit-level format definitions, not
 from any library conversion routine.  ``s_A``, ``s_B`` are the per-tensor
-scales of FP8 inputs (1 otherwise).
+scales of FP8 inputs (1 otherwise).  MXFP8 inputs (OCP MX block scaling)
+multiply each block of 32 K-values of a row of A or a column of B by a
+power-of-two E8M0 scale first (gemm_mx), which is exact in FP64.
 """
 import ctypes
 import os
@@ -108,6 +110,15 @@ def decode_f32(bits) -> np.ndarray:
     return np.ascontiguousarray(bits, dtype=np.uint32).view(np.float32).astype(np.float64)
 
 
+def decode_e8m0(bits) -> np.ndarray:
+    """uint8 OCP E8M0 scale codes -> exact float64 values.  E8M0 is an
+    8-bit biased exponent alone (no sign, no fraction): code e encodes
+    2^(e - 127) for e = 0..254, and e = 255 is NaN."""
+    e = np.asarray(bits).astype(np.int64)
+    v = np.ldexp(np.ones(e.shape, dtype=np.float64), (e - 127).astype(np.int32))
+    return np.where(e == 255, np.nan, v)
+
+
 DECODERS = {"f32": decode_f32, "f16": decode_f16, "bf16": decode_bf16,
             "e4m3": decode_e4m3fn}
 
@@ -160,6 +171,34 @@ def gemm(M, N, K, a, lda, a_col_major, b, ldb, b_col_major, alpha=1.0,
     if rc != 0:
         raise ValueError(f"oracle_gemm_f64 failed with code {rc}")
     return out
+
+
+def mx_operand(codes, ld, scales, ld_s, rows, K, block=32):
+    """An MX operand stored K-contiguous (OCP MX block scaling): element
+    (r, k) is decode_e4m3fn(codes[r*ld + k]) * decode_e8m0(scales[r*ld_s +
+    k // block]).  Returns the rows x K float64 values; each is a decoded
+    e4m3 value times a power of two, so the result is exact."""
+    x = decode_e4m3fn(np.asarray(codes).reshape(-1))
+    s = decode_e8m0(np.asarray(scales).reshape(-1))
+    out = np.empty((rows, K), dtype=np.float64)
+    for r in range(rows):
+        blk = s[r * ld_s + np.arange(K) // block]
+        out[r] = x[r * ld: r * ld + K] * blk
+    return out
+
+
+def gemm_mx(M, N, K, a_codes, lda, sa, ldsa, b_codes, ldb, sb, ldsb, alpha=1.0, beta=0.0,
+            cin=None, rows=None):
+    """MXFP8 product C = alpha * sum_k A^(i,k) B^(k,j) + beta * Cin, with A
+    row-major (row i at a_codes[i*lda]) and B column-major (column j at
+    b_codes[j*ldb]) e4m3 codes and E8M0 scales of every 32 K-values of each
+    row of A (sa[i*ldsa + k//32]) and column of B (sb[j*ldsb + k//32]):
+    A^ and B^ are the block-scaled values (mx_operand, exact), multiplied by
+    the plain FP64 product above."""
+    ahat = mx_operand(a_codes, lda, sa, ldsa, M, K)
+    bhat_t = mx_operand(b_codes, ldb, sb, ldsb, N, K)      # row j = column j of B
+    return gemm(M, N, K, ahat, K, False, bhat_t, K, True, alpha, beta, cin,
+                N if cin is not None else None, rows)
 
 
 def gemm_dense(A, B, alpha=1.0, beta=0.0, Cin=None, rows=None):

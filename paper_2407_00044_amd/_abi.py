@@ -26,7 +26,7 @@ SK_ERR_CAPACITY = -6
 SK_ERR_DEVICE_TIMEOUT = -7
 
 # dtypes / layouts / modes / roles
-SK_F32, SK_F16, SK_BF16, SK_F8E4M3 = 0, 1, 2, 3
+SK_F32, SK_F16, SK_BF16, SK_F8E4M3, SK_MXF8E4M3 = 0, 1, 2, 3, 4
 SK_ROW_MAJOR, SK_COL_MAJOR = 0, 1
 SK_MODE_HYBRID, SK_MODE_SK, SK_MODE_DP, SK_MODE_AUTO = 0, 1, 2, 3
 SK_ROLE_FULL, SK_ROLE_FINISH, SK_ROLE_PARTIAL, SK_ROLE_DP = 0, 1, 2, 3
@@ -99,6 +99,8 @@ PROTOTYPES = {
     "sk_workspace_init": (c_i32, [c_vp, ctypes.c_size_t, c_vp]),
     "sk_gemm": (c_i32, [P(SkProblem), c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t,
                         P(SkConfig), c_vp]),
+    "sk_gemm_mx": (c_i32, [P(SkProblem), c_vp, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp,
+                           c_vp, ctypes.c_size_t, P(SkConfig), c_vp]),
     "sk_gemm_debug": (c_i32, [P(SkProblem), c_vp, c_vp, c_vp, c_vp, c_vp,
                               ctypes.c_size_t, P(SkConfig), P(SkDebug), c_vp]),
     "sk_check_device_error": (c_i32, [c_vp, ctypes.c_size_t, P(c_i32), c_vp]),

@@ -18,7 +18,8 @@ DTYPE_CODES = {torch.float32: _abi.SK_F32, torch.float16: _abi.SK_F16,
                torch.bfloat16: _abi.SK_BF16, torch.float8_e4m3fn: _abi.SK_F8E4M3}
 OUT_CODES = {torch.float32: _abi.SK_F32, torch.float16: _abi.SK_F16,
              torch.bfloat16: _abi.SK_BF16}
-K_PER_ITER = {_abi.SK_F32: 32, _abi.SK_F16: 64, _abi.SK_BF16: 64, _abi.SK_F8E4M3: 128}
+K_PER_ITER = {_abi.SK_F32: 32, _abi.SK_F16: 64, _abi.SK_BF16: 64, _abi.SK_F8E4M3: 128,
+              _abi.SK_MXF8E4M3: 128}
 
 SEGMENT_FIELDS = ("wg", "problem", "tile", "tile_m", "tile_n", "k_begin", "k_end",
                   "role", "npeers")
@@ -188,6 +189,50 @@ def gemm(A, B, C=None, *, alpha=1.0, beta=0.0, out=None, out_dtype=torch.float32
                                  ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(cin),
                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(wptr),
                                  wlen, ctypes.byref(c), ctypes.c_void_p(sp)))
+    return out
+
+
+def gemm_mx(A, B, scale_a, scale_b, C=None, *, alpha=1.0, beta=0.0, out=None,
+            out_dtype=torch.float32, config=None, workspace=None, stream=None):
+    """MXFP8 GEMM through sk_gemm_mx: A (M x K, row-major) and B (K x N,
+    column-major) hold e4m3 codes (torch.float8_e4m3fn); scale_a (M x >= K/32)
+    and scale_b (N x >= K/32) hold one E8M0 byte (uint8, 2^(e-127)) per 32
+    K-values of each row of A and column of B, rows contiguous.
+    out = alpha * sum_k (A * 2^(sa-127)) (B * 2^(sb-127)) + beta * C."""
+    lib = load()
+    if A.dtype != torch.float8_e4m3fn or B.dtype != torch.float8_e4m3fn:
+        raise TypeError("MXFP8 operands are torch.float8_e4m3fn codes")
+    for s_ in (scale_a, scale_b):
+        if s_.dtype != torch.uint8 or s_.dim() != 2 or s_.stride(1) != 1 or not s_.is_cuda:
+            raise TypeError("block scales: 2-D uint8 GPU tensors with contiguous rows")
+    M, N = A.shape[0], B.shape[1]
+    if out is None:
+        out = C if (C is not None and beta != 0.0) else torch.empty(
+            (M, N), dtype=out_dtype, device=A.device)
+    if beta != 0.0 and C is None:
+        raise ValueError("beta != 0 needs C")
+    p = _problem(A, B, out, alpha, beta, 1.0, 1.0)
+    p.dtype_ab = _abi.SK_MXF8E4M3
+    if scale_a.shape[0] != M or scale_b.shape[0] != N:
+        raise ValueError("one scale row per row of A and per column of B")
+    if config is None:
+        tile = default_tile(M, N, A.shape[1], torch.float8_e4m3fn)
+        config = Config(tile=tile if tile in ((256, 128), (128, 128)) else (128, 128))
+    cfg = config
+    c = cfg.c_struct(_abi.SK_MXF8E4M3)
+    sp = _stream_ptr(stream)
+    nbytes = ctypes.c_size_t()
+    check("sk_workspace_size", lib.sk_workspace_size(ctypes.byref(p), 1, ctypes.byref(c),
+                                                      ctypes.byref(nbytes)))
+    ws = workspace or workspace_for(A.device, sp)
+    wptr, wlen = ws.get(nbytes.value, sp)
+    cin = C.data_ptr() if (C is not None and beta != 0.0) else None
+    check("sk_gemm_mx", lib.sk_gemm_mx(
+        ctypes.byref(p), ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+        ctypes.c_void_p(scale_a.data_ptr()), max(1, scale_a.stride(0)),
+        ctypes.c_void_p(scale_b.data_ptr()), max(1, scale_b.stride(0)), ctypes.c_void_p(cin),
+        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(wptr), wlen, ctypes.byref(c),
+        ctypes.c_void_p(sp)))
     return out
 
 

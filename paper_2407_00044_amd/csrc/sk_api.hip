@@ -108,7 +108,7 @@ static sk_status resident_per_cu(const KernelEntry* ke, int* per_cu) {
 static sk_status check_problem(const sk_problem& p) {
   if (p.M < 0 || p.N < 0 || p.K < 0) return SK_ERR_INVALID_ARG;
   if (p.M > kMaxIndex || p.N > kMaxIndex || p.K > kMaxIndex) return SK_ERR_UNSUPPORTED;
-  if (p.dtype_ab < 0 || p.dtype_ab > 3) return SK_ERR_UNSUPPORTED;
+  if (p.dtype_ab < 0 || p.dtype_ab > 4) return SK_ERR_UNSUPPORTED;
   if (p.dtype_c < 0 || p.dtype_c > 2) return SK_ERR_UNSUPPORTED;
   if ((p.layout_a != SK_ROW_MAJOR && p.layout_a != SK_COL_MAJOR) ||
       (p.layout_b != SK_ROW_MAJOR && p.layout_b != SK_COL_MAJOR))
@@ -547,19 +547,48 @@ static sk_status launch(const Plan& P, const sk_config* cfg, int32_t dt, int32_t
   return SK_OK;
 }
 
+// MXFP8 block scales of one problem (sk_gemm_mx).
+struct MxScales {
+  const void* sA;
+  int64_t ldsa;
+  const void* sB;
+  int64_t ldsb;
+};
+
 static sk_status gemm_common(const sk_problem* p, const void* A, const void* B, const void* Cin,
                              void* Cout, void* ws, size_t ws_bytes_, const sk_config* cfg,
-                             const sk_debug* dbg, void* stream) {
+                             const sk_debug* dbg, void* stream, const MxScales* mx = nullptr) {
   if (p == nullptr) return SK_ERR_INVALID_ARG;
+  // MXFP8 inputs need their block scales (sk_gemm_mx); others take none
+  if ((p->dtype_ab == SK_MXF8E4M3) != (mx != nullptr)) return SK_ERR_INVALID_ARG;
   Plan P;
   sk_status st = plan_problems(p, 1, cfg, &P);
   if (st != SK_OK) return st;
+  if (mx) {
+    // kernels built for K-contiguous operands, whole 128-element iterations
+    // and 16-byte loads; scales read as 4-byte words, 4 per iteration
+    if (p->layout_a != SK_ROW_MAJOR || p->layout_b != SK_COL_MAJOR || p->K % 128 != 0)
+      return SK_ERR_UNSUPPORTED;
+    if (!aligned16(A) || !aligned16(B) || p->lda % 16 != 0 || p->ldb % 16 != 0)
+      return SK_ERR_UNSUPPORTED;
+    if (p->M > 0 && p->N > 0 && p->K > 0 &&
+        (mx->sA == nullptr || mx->sB == nullptr || ((uintptr_t)mx->sA & 3) != 0 ||
+         ((uintptr_t)mx->sB & 3) != 0 || mx->ldsa % 4 != 0 || mx->ldsb % 4 != 0 ||
+         mx->ldsa < p->K / 32 || mx->ldsb < p->K / 32))
+      return SK_ERR_INVALID_ARG;
+    if ((p->M - 1) * mx->ldsa + p->K / 32 > kMaxIndex || (p->N - 1) * mx->ldsb + p->K / 32 > kMaxIndex)
+      return SK_ERR_UNSUPPORTED;
+  }
   if (p->M == 0 || p->N == 0) return SK_OK;
   if (Cout == nullptr) return SK_ERR_INVALID_ARG;
   if (p->K > 0 && (A == nullptr || B == nullptr)) return SK_ERR_INVALID_ARG;
   if (p->beta != 0.f && Cin == nullptr) return SK_ERR_INVALID_ARG;
   ProbDesc& d = P.descs[0];
   d.A = A; d.B = B; d.Cin = Cin; d.Cout = Cout;
+  if (mx) {
+    d.sA = mx->sA; d.sB = mx->sB;
+    d.ldsa = mx->ldsa; d.ldsb = mx->ldsb;
+  }
   const int eb = elem_bytes(p->dtype_ab);
   d.aligned = aligned16(A) && aligned16(B) && (p->lda * eb) % 16 == 0 && (p->ldb * eb) % 16 == 0;
   return launch(P, cfg, p->dtype_ab, p->layout_a, p->layout_b, p->dtype_c, &d, nullptr, 1, ws,
@@ -746,6 +775,14 @@ sk_status sk_gemm(const sk_problem* p, const void* A, const void* B, const void*
   return gemm_common(p, A, B, C_in, C_out, workspace, ws_bytes_, cfg, nullptr, stream);
 }
 
+sk_status sk_gemm_mx(const sk_problem* p, const void* A, const void* B, const void* scale_a,
+                     int64_t ld_scale_a, const void* scale_b, int64_t ld_scale_b,
+                     const void* C_in, void* C_out, void* workspace, size_t ws_bytes_,
+                     const sk_config* cfg, void* stream) {
+  const MxScales mx{scale_a, ld_scale_a, scale_b, ld_scale_b};
+  return gemm_common(p, A, B, C_in, C_out, workspace, ws_bytes_, cfg, nullptr, stream, &mx);
+}
+
 sk_status sk_gemm_debug(const sk_problem* p, const void* A, const void* B, const void* C_in,
                         void* C_out, void* workspace, size_t ws_bytes_, const sk_config* cfg,
                         const sk_debug* dbg, void* stream) {
@@ -800,6 +837,7 @@ sk_status sk_grouped_prepare(const sk_problem* probs, const void* const* A,
   Plan P;
   sk_status st = plan_problems(probs, nprobs, cfg, &P);
   if (st != SK_OK) return st;
+  if (probs[0].dtype_ab == SK_MXF8E4M3) return SK_ERR_UNSUPPORTED;   // single problems only
   if (desc_bytes < (size_t)nprobs * sizeof(ProbDesc)) return SK_ERR_WORKSPACE;
   const int eb = elem_bytes(probs[0].dtype_ab);
   int32_t all_aligned = 1;

@@ -20,8 +20,8 @@
 // tiles takes ceil(T / CUs) waves of one tile each.
 //
 // The constants are measured on MI355X per input type and tile by
-// paper_2407_00044_amd/calibrate.py (f16 uses the bf16 rows: same kernels,
-// same rate).  They are policy: no result depends on them, only which
+// paper_2407_00044_amd/calibrate.py (f16 uses the bf16 rows and MXFP8 the
+// e4m3 rows: same kernels, same rate).  They are policy: no result depends on them, only which
 // launch the auto mode picks.
 #pragma once
 
@@ -56,7 +56,7 @@ constexpr double kAutoMargin = 1.08;
 // Row of (input type, tile); f16 takes bf16's.  A tile without a row takes
 // the row of the same type whose tile area is closest.
 inline const CostRow* cost_row(int32_t dt, int32_t bm, int32_t bn) {
-  const int32_t d = dt == 1 ? 2 : dt;
+  const int32_t d = dt == 1 ? 2 : dt == 4 ? 3 : dt;   // f16 as bf16, MXFP8 as e4m3
   const CostRow* best = nullptr;
   int64_t best_gap = 0;
   for (const CostRow& r : kCostTable) {

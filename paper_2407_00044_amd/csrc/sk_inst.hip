@@ -18,6 +18,12 @@
 #if SK_DT == 0
 // f32: 128x128x32 (the 512^3 Stream-K configuration)
 SK_INST(128, 128, 2, 4)
+#elif SK_DT == 4
+// MXFP8 (e4m3 with E8M0 block scales): K-contiguous operands only
+#if SK_LA == 0 && SK_LB == 1
+SK_INST(256, 128, 4, 8)
+SK_INST(128, 128, 4, 8)
+#endif
 #else
 // f16 / bf16 / e4m3: large tiles for compute-bound shapes, smaller ones for
 // small or skinny problems.  Both operands are copied LDS-direct in every

@@ -48,7 +48,11 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef int v2i __attribute__((ext_vector_type(2)));
 
-enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3 };
+enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3, DT_MX8 = 4 };
+// 8-bit e4m3 elements: plain (per-tensor scales, applied in the epilogue) or
+// MXFP8 (an E8M0 scale per 32 K-values of each row of A and column of B,
+// applied by the matrix core)
+constexpr bool is_f8(int dt) { return dt == DT_F8 || dt == DT_MX8; }
 enum { L_ROW = 0, L_COL = 1 };
 enum { R_FULL = 0, R_FINISH = 1, R_PARTIAL = 2, R_DP = 3 };
 
@@ -654,7 +658,10 @@ struct StageSel<false, false, R, EB, NT> { using type = MNMajorStage<R, EB, NT>;
 // for one 32x32 output block.  Lane l reads tile row (l mod 32); lanes
 // 0-31 and 32-63 read adjacent 16-byte (32-byte for e4m3) pieces of K.
 template <int DT>
-struct Frag { u32x4 c[DT == DT_F8 ? 2 : 1]; };
+struct Frag { u32x4 c[is_f8(DT) ? 2 : 1]; };
+// MXFP8: the lane's 32 K-values and the E8M0 scale of their block
+template <>
+struct Frag<DT_MX8> { u32x4 c[2]; int32_t s; };
 
 // Per-lane LDS byte offset, inside a 32-row block, of the 16-byte piece
 // `chunk` of the lane's row (lane mod 32).  The swizzle repeats every 32
@@ -667,7 +674,7 @@ template <int DT>
 __device__ __forceinline__ Frag<DT> read_frag(const char* L, const int (&lo)[2]) {
   Frag<DT> f;
   f.c[0] = *(const u32x4*)(L + lo[0]);
-  if constexpr (DT == DT_F8) f.c[1] = *(const u32x4*)(L + lo[1]);
+  if constexpr (is_f8(DT)) f.c[1] = *(const u32x4*)(L + lo[1]);
   return f;
 }
 
@@ -690,11 +697,18 @@ __device__ __forceinline__ void mma(v16f& acc, const Frag<DT>& a, const Frag<DT>
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a.c[0]),
                                                   __builtin_bit_cast(v8bf, b.c[0]), acc, 0, 0,
                                                   0);
-  } else {
-    v8i av = __builtin_bit_cast(v8i, a);
-    v8i bv = __builtin_bit_cast(v8i, b);
+  } else if constexpr (DT == DT_F8) {
+    v8i av = __builtin_bit_cast(v8i, a.c);
+    v8i bv = __builtin_bit_cast(v8i, b.c);
     // operand format 0 (e4m3) for A and B; E8M0 scale 127 = 2^0
     acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, 127, 0, 127);
+  } else {
+    // MXFP8: each lane's 32 K-values (one block of its row of A / column of
+    // B) carry that block's E8M0 scale; the matrix core multiplies every
+    // product by 2^(sa-127) * 2^(sb-127)
+    v8i av = __builtin_bit_cast(v8i, a.c);
+    v8i bv = __builtin_bit_cast(v8i, b.c);
+    acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, a.s, 0, b.s);
   }
 }
 
@@ -703,14 +717,19 @@ template <int DT_, int LA_, int LB_, int BM_, int BN_, int WGM_, int NW_>
 struct Cfg {
   static constexpr int DT = DT_, LA = LA_, LB = LB_, BM = BM_, BN = BN_, WGM = WGM_;
   static constexpr int NW = NW_, NT = 64 * NW_;     // waves, threads per workgroup
-  static constexpr int EB = DT == DT_F32 ? 4 : DT == DT_F8 ? 1 : 2;
+  static constexpr int EB = DT == DT_F32 ? 4 : is_f8(DT) ? 1 : 2;
+  static constexpr bool MX = DT == DT_MX8;           // E8M0 block scales in the stage
   static constexpr int KE = 128 / EB;                // K elements per iteration
   static constexpr int WGN = NW / WGM;
   static constexpr int WM = BM / WGM, WN = BN / WGN; // per-wave tile
   static constexpr int FM = WM / 32, FN = WN / 32;   // 32x32 blocks per wave
-  static constexpr int STEPS = DT == DT_F8 ? 2 : 4;  // matrix-core steps per iteration
+  static constexpr int STEPS = is_f8(DT) ? 2 : 4;   // matrix-core steps per iteration
   static constexpr int BOFF = BM * 128;              // B tile offset in a stage
-  static constexpr int STAGE = (BM + BN) * 128;      // LDS bytes per stage
+  // MXFP8: after the tiles, 4 scale bytes (the iteration's 4 blocks) per
+  // row of A then per column of B, one 256-byte block per wave
+  static constexpr int SCL_A = (BM + BN) * 128;
+  static constexpr int SCL_B = SCL_A + 4 * BM;
+  static constexpr int STAGE = (BM + BN) * 128 + (MX ? NW * 256 : 0);   // LDS bytes per stage
   // M/N-contiguous 16-bit operands are read with transposing LDS reads
   // (e4m3: tiles of at least 128 rows)
   static constexpr bool TR16 = (DT == DT_F16 || DT == DT_BF16) && SK_MN_TR && SK_KMAJOR_DMA;
@@ -729,10 +748,12 @@ struct Cfg {
   static constexpr bool RING = DMA && ((!TRA && !TRB) || (SK_RING_TR && STEPS == 4));
   static constexpr int RING_LA = (TRA || TRB) ? 2 : 1;
   // LDS-direct copies issued per wave for one iteration
-  static constexpr int NLOADS = (BM + BN) / (NT / 8);
+  static constexpr int NLOADS = (BM + BN) / (NT / 8) + (MX ? 1 : 0);
+  static_assert(!MX || (LA == L_ROW && LB == L_COL && (BM + BN) * 4 <= NW * 256),
+                "MXFP8: K-contiguous operands, scale rows fit one block per wave");
   // LDS read instructions per matrix-core step
-  static constexpr int RD_K = DT == DT_F8 ? 2 : 1;   // K-contiguous fragment
-  static constexpr int RD_T = DT == DT_F8 ? 4 : 2;   // transposed fragment
+  static constexpr int RD_K = is_f8(DT) ? 2 : 1;    // K-contiguous fragment
+  static constexpr int RD_T = is_f8(DT) ? 4 : 2;    // transposed fragment
   static constexpr int NRD = FM * (TRA ? RD_T : RD_K) + FN * (TRB ? RD_T : RD_K);
   static_assert(WGM * WGN == NW && FM >= 1 && FN >= 1, "wave grid");
   static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile");
@@ -742,6 +763,47 @@ struct Cfg {
 
 template <typename C>
 struct Acc { v16f a[C::FM][C::FN]; };
+
+// MXFP8 block scales of one tile into the stage: the 4 scale bytes of an
+// iteration (its 4 blocks of 32 K-values) for each row of A, then for each
+// column of B, one 4-byte LDS-direct copy per lane.  Wave w copies rows
+// 64w .. 64w+63 of [rows of A | columns of B] into its own 256-byte block of
+// the stage; a wave past them copies zeros (out-of-range offsets) into its
+// block, so every wave issues the same number of copies per stage.  Rows
+// past M or N read as zero scales (their elements are zero too).
+template <typename C>
+struct ScaleStage {
+  static constexpr int NI = C::MX ? 1 : 0;
+  uint32_t voff;
+  __amdgpu_buffer_rsrc_t prs;
+
+  __device__ __forceinline__ void prep(const ProbDesc& pd, int64_t m0, int64_t n0, int tid) {
+    if constexpr (C::MX) {
+      const int wave = uniform32(tid >> 6);
+      const int r = 64 * wave + (tid & 63);
+      if (64 * wave < C::BM) {
+        prs = make_rsrc((const char*)pd.sA + m0 * pd.ldsa, (pd.M - m0) * pd.ldsa);
+        voff = (uint32_t)r * (uint32_t)pd.ldsa;
+      } else if (64 * wave < C::BM + C::BN) {
+        prs = make_rsrc((const char*)pd.sB + n0 * pd.ldsb, (pd.N - n0) * pd.ldsb);
+        voff = (uint32_t)(r - C::BM) * (uint32_t)pd.ldsb;
+      } else {
+        prs = make_rsrc((const char*)pd.sA, 0);
+        voff = kOOB;
+      }
+    }
+  }
+
+  // Iteration k's scale bytes into the stage at L (on == false: zeros).
+  __device__ __forceinline__ void issue(char* L, int64_t k, int tid, bool on) const {
+    if constexpr (C::MX) {
+      const int wave = uniform32(tid >> 6);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          prs, (__attribute__((address_space(3))) void*)(L + C::SCL_A + 256 * wave), 4,
+          (int)(on ? voff : kOOB), uniform32((int32_t)(4 * k)), 0, 0);
+    }
+  }
+};
 
 template <typename C>
 __device__ __forceinline__ void zero_acc(Acc<C>& acc) {
@@ -779,15 +841,26 @@ __device__ __forceinline__ void zero_acc(Acc<C>& acc) {
 //    8(p mod 2) .. +7, so lane l receives row l%32, k-rows k0 + 32(l/32) +
 //    0..7; four reads (k0 + 8r) give its 32 k-values.  The swizzle puts a
 //    group pair's eight k-rows on eight distinct 32-byte bank groups.
-template <typename C, bool TR, int NB, int R>
+//  * MXFP8 (K-contiguous): the scaled 32x32x64 matrix-core step forms block
+//    b (32 K-values) of a row from bytes 16b .. 16b+15 of both lane halves
+//    and takes its scale from lane half b (gfx950 lane layout, checked on
+//    the device with an all-ones operand and one lane's scale doubled).  So
+//    lane l takes the 16-byte pieces 4s + l/32 and 4s + 2 + l/32: block b of
+//    the step is the pieces 4s + 2b, 4s + 2b + 1, the iteration's block
+//    2s + b, whose scale lane half b reads: byte 2s + l/32 of the 4 scale
+//    bytes the stage holds for the lane's row, SREL bytes past the operand
+//    (row r's bytes at 4r).
+template <typename C, bool TR, int NB, int R, int SREL>
 struct FragReader {
   static constexpr int PITCH = R * C::EB;    // bytes per k-row (TR stage)
   int off[NB];
   int l32, half;
+  int sb;                                    // MXFP8: this lane's scale byte in block 0, step 0
 
   __device__ __forceinline__ void init(int rowbase, int lane) {
     l32 = lane & 31;
     half = lane >> 5;
+    if constexpr (C::MX) sb = SREL + 4 * (rowbase + l32) + half;
     if constexpr (TR && C::EB == 2) {
       static_assert(C::STEPS == 4, "16 k-values per step");
       const int p = lane & 15, g = lane >> 4, j = p >> 2, q = p & 3;
@@ -830,7 +903,10 @@ struct FragReader {
       f.c[0] = u32x4{lo[0], lo[1], hi[0], hi[1]};
     } else {
       int lo[2];
-      if constexpr (C::DT == DT_F8) {
+      if constexpr (C::MX) {
+        lo[0] = frag_lane_off(l32, 4 * s + half);
+        lo[1] = frag_lane_off(l32, 4 * s + 2 + half);
+      } else if constexpr (is_f8(C::DT)) {
         lo[0] = frag_lane_off(l32, 4 * s + 2 * half);
         lo[1] = frag_lane_off(l32, 4 * s + 2 * half + 1);
       } else {
@@ -838,15 +914,16 @@ struct FragReader {
         lo[1] = 0;
       }
       f = read_frag<C::DT>(op + off[i], lo);
+      if constexpr (C::MX) f.s = (int32_t)*(const uint8_t*)(op + sb + 128 * i + 2 * s);
     }
     return f;
   }
 };
 
 template <typename C>
-using ReaderA = FragReader<C, C::TRA, C::FM, C::BM>;
+using ReaderA = FragReader<C, C::TRA, C::FM, C::BM, C::SCL_A>;
 template <typename C>
-using ReaderB = FragReader<C, C::TRB, C::FN, C::BN>;
+using ReaderB = FragReader<C, C::TRB, C::FN, C::BN, C::SCL_B - C::BOFF>;
 
 template <typename C>
 __device__ __forceinline__ void read_step(Frag<C::DT> (&fa)[C::FM], Frag<C::DT> (&fb)[C::FN],
@@ -999,9 +1076,10 @@ __device__ __forceinline__ void step_fenced(
     Acc<C>& acc, const Frag<C::DT> (&fa)[C::FM], const Frag<C::DT> (&fb)[C::FN],
     Frag<C::DT> (&ra)[C::FM], Frag<C::DT> (&rb)[C::FN], const ReaderA<C>& rda,
     const ReaderB<C>& rdb, const char* opA, const char* opB, int rs,
-    const typename C::StageA& sa, const typename C::StageB& sb, char* dst, int64_t k0, bool on,
-    int tid) {
-  // copies CB .. CE-1 of the iteration's NA + NB (A's first)
+    const typename C::StageA& sa, const typename C::StageB& sb, const ScaleStage<C>& ss,
+    char* dst, int64_t k0, bool on, int tid) {
+  // copies CB .. CE-1 of the iteration's NA + NB (+1 MXFP8 scale copy): A's
+  // first, then B's, then the scales'
   constexpr int NM = C::FM * C::FN;
   constexpr int NRF = C::FM + C::FN;
   constexpr int NA = C::StageA::NI;
@@ -1020,7 +1098,8 @@ __device__ __forceinline__ void step_fenced(
 #pragma unroll
     for (int c = CB + t * NCP / NM; c < CB + (t + 1) * NCP / NM; ++c) {
       if (c < NA) sa.issue_one(dst, kba, tid, on, c);
-      else sb.issue_one(dst + C::BOFF, kbb, tid, on, c - NA);
+      else if (c < NA + C::StageB::NI) sb.issue_one(dst + C::BOFF, kbb, tid, on, c - NA);
+      else ss.issue(dst, k0 / C::KE, tid, on);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -1127,13 +1206,13 @@ __device__ __forceinline__ void mac_loop_dma(Acc<C>& acc, const OpTile& oa, cons
 // once (prep) and only rows past M or N are masked.
 template <typename C>
 __device__ __forceinline__ void mac_loop_ring(Acc<C>& acc, const OpTile& oa, const OpTile& ob,
-                                              int kb, int ke, char* lds, int tid,
-                                              int32_t* cover_row) {
+                                              const ScaleStage<C>& ss, int kb, int ke,
+                                              char* lds, int tid, int32_t* cover_row) {
   constexpr int NS = C::NSTAGE;
   constexpr int ST = C::STEPS;
   constexpr int LA = C::RING_LA;
   constexpr int NBUF = LA == 1 ? 2 : 4;
-  constexpr int NCP = C::StageA::NI + C::StageB::NI;
+  constexpr int NCP = C::StageA::NI + C::StageB::NI + ScaleStage<C>::NI;
   static_assert(NS >= 2 && NS <= 4 && ST % NBUF == 0 && LA <= ST, "ring loop shape");
   typename C::StageA sa;
   typename C::StageB sb;
@@ -1151,6 +1230,7 @@ __device__ __forceinline__ void mac_loop_ring(Acc<C>& acc, const OpTile& oa, con
     if (kb + j < ke) {
       sa.issue_pre(lds + j * C::STAGE, (int64_t)(kb + j) * C::KE, tid, true);
       sb.issue_pre(lds + j * C::STAGE + C::BOFF, (int64_t)(kb + j) * C::KE, tid, true);
+      ss.issue(lds + j * C::STAGE, kb + j, tid, true);
     }
   }
   // copies of iteration kb landed in every wave (later ones may be in flight)
@@ -1190,16 +1270,16 @@ __device__ __forceinline__ void mac_loop_ring(Acc<C>& acc, const OpTile& oa, con
       }
       if (s < ST - LA)
         step_fenced<C, 0, 0>(acc, fa[s % NBUF], fb[s % NBUF], fa[(s + LA) % NBUF],
-                             fb[(s + LA) % NBUF], rda, rdb, src, src + C::BOFF, rs, sa, sb, cur,
+                             fb[(s + LA) % NBUF], rda, rdb, src, src + C::BOFF, rs, sa, sb, ss, cur,
                              kn0, refill, tid);
       else if (LA == 1 || s == ST - 2)
         step_fenced<C, 0, (LA == 1 ? NCP : NCP / 2)>(
             acc, fa[s % NBUF], fb[s % NBUF], fa[(s + LA) % NBUF], fb[(s + LA) % NBUF], rda, rdb,
-            src, src + C::BOFF, rs, sa, sb, cur, kn0, refill, tid);
+            src, src + C::BOFF, rs, sa, sb, ss, cur, kn0, refill, tid);
       else
         step_fenced<C, NCP / 2, NCP>(acc, fa[s % NBUF], fb[s % NBUF], fa[(s + LA) % NBUF],
                                      fb[(s + LA) % NBUF], rda, rdb, src, src + C::BOFF, rs, sa,
-                                     sb, cur, kn0, refill, tid);
+                                     sb, ss, cur, kn0, refill, tid);
     }
     slot = nslot;
   }
@@ -1247,10 +1327,23 @@ __device__ __forceinline__ void mac_loop(Acc<C>& acc, const ProbDesc& pd, int64_
   // past K goes to the masked per-iteration path below
   if constexpr (C::RING)
     if (kf > kb && !C::StageA::whole(oa, (int64_t)(kf - 1) * C::KE)) --kf;
+  if constexpr (C::MX) {
+    // MXFP8 launches are K-contiguous, 16-byte aligned and K a multiple of
+    // 128 (checked on the host): every iteration is whole and fast
+    ScaleStage<C> ss;
+    ss.prep(pd, m0, n0, tid);
+    if (ke > kb) mac_loop_ring<C>(acc, oa, ob, ss, kb, ke, lds, tid, cover_row);
+    return;
+  }
   if (kf > kb) {
-    if constexpr (C::RING) mac_loop_ring<C>(acc, oa, ob, kb, kf, lds, tid, cover_row);
-    else if constexpr (C::DMA && C::NSTAGE >= 3) mac_loop_dma<C>(acc, oa, ob, kb, kf, lds, tid, cover_row);
-    else mac_loop_fast<C>(acc, oa, ob, kb, kf, lds, tid, cover_row);
+    if constexpr (C::RING) {
+      const ScaleStage<C> none{};
+      mac_loop_ring<C>(acc, oa, ob, none, kb, kf, lds, tid, cover_row);
+    } else if constexpr (C::DMA && C::NSTAGE >= 3) {
+      mac_loop_dma<C>(acc, oa, ob, kb, kf, lds, tid, cover_row);
+    } else {
+      mac_loop_fast<C>(acc, oa, ob, kb, kf, lds, tid, cover_row);
+    }
   }
   for (int k = kf; k < ke; ++k) {
     stage_slow<C>(oa, ob, (int64_t)k * C::KE, lds, tid);

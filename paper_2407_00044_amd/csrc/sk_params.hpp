@@ -26,6 +26,9 @@ struct ProbDesc {
                              // (W when the problem has no Stream-K tile)
   int32_t user_index;        // index of the problem in the caller's array
   int32_t pad_;
+  const void* sA;            // MXFP8: E8M0 scales of A, row i at sA + i * ldsa
+  const void* sB;            //        and of B, column j at sB + j * ldsb
+  int64_t ldsa, ldsb;        //        (bytes; one scale per 32 K-values)
 };
 
 struct KParams {

@@ -94,11 +94,11 @@ SK_HD int64_t logical_id(int64_t b, int64_t g, int32_t xcd_remap, int32_t revers
 
 // Elements of K per MAC iteration: 128 bytes of K for every input type.
 SK_HD int32_t k_per_iter(int32_t dtype_ab) {
-  return dtype_ab == 0 ? 32 : dtype_ab == 3 ? 128 : 64;
+  return dtype_ab == 0 ? 32 : dtype_ab >= 3 ? 128 : 64;
 }
 
 SK_HD int32_t elem_bytes(int32_t dtype) {
-  return dtype == 0 ? 4 : dtype == 3 ? 1 : 2;
+  return dtype == 0 ? 4 : dtype >= 3 ? 1 : 2;
 }
 
 }  // namespace sk

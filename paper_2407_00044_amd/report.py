@@ -224,6 +224,36 @@ def per_dtype(dev, reps=5, shape=(3840, 4096, 4096)):
     return res
 
 
+def mxfp8(dev, reps=5, shape=(3840, 4096, 4096), tile=(256, 128)):
+    """MXFP8 (e4m3 elements with an E8M0 scale per 32 K-values, applied by
+    the matrix cores) at the headline shape, beside plain e4m3 with
+    per-tensor scales on the same tile: Stream-K (two-tile hybrid), the auto
+    policy and the data-parallel grid; % of the dense FP8 MFMA peak."""
+    M, N, K = shape
+    ws = api.Workspace(dev)
+    ws.get(96 << 20, torch.cuda.current_stream().cuda_stream)
+    qa, sa = synth.mx_quantize(synth.normal((M, K), 61))
+    qb, sb = synth.mx_quantize(synth.normal((N, K), 62))
+    A, B = qa.to(dev), qb.to(dev).t()
+    SA, SB = torch.from_numpy(sa).to(dev), torch.from_numpy(sb).to(dev)
+    out = torch.empty((M, N), device=dev)
+    fl = 2.0 * M * N * K
+    cfgs = {"stream_k": api.Config(tile=tile, mode="hybrid"),
+            "auto": api.Config(tile=tile, mode="auto"),
+            "dp": api.Config(tile=tile, mode="dp")}
+    fns = [(lambda c: (lambda: api.gemm_mx(A, B, SA, SB, out=out, config=c, workspace=ws)))(c)
+           for c in cfgs.values()]
+    fns += [(lambda c: (lambda: api.gemm(A, B, out=out, config=c, workspace=ws)))(c)
+            for c in cfgs.values()]
+    ts = _time_all(fns, reps)
+    res = {"workload": f"{M}x{N}x{K}, A row-major, B column-major, FP32 output, tile "
+                       f"{tile[0]}x{tile[1]}", "mxfp8": {}, "e4m3_per_tensor": {}}
+    for i, n in enumerate(cfgs):
+        for key, t in (("mxfp8", ts[i]), ("e4m3_per_tensor", ts[i + 3])):
+            res[key][n] = {"tflops": _tf(fl, t), "pct_peak": round(100 * fl / t / 1e9 / 5033.2, 2)}
+    return res
+
+
 def padding(dev, reps=10, tile=(256, 128)):
     """The report's padding experiment (Methodology, Results, Table 1) on
     FP16: each shape run unpadded (edges through out-of-range loads and
@@ -317,7 +347,7 @@ def run_all(dev, extra=False, only=None, c5_tile=None):
     c5_tile runs c5 in auto mode on that tile instead of the tuner's pick."""
     out = {}
     todo = [("c1", c1), ("c3", c3), ("c4", c4), ("c5", lambda d: c5(d, tile=c5_tile)),
-            ("per_dtype", per_dtype)]
+            ("per_dtype", per_dtype), ("mxfp8", mxfp8)]
     if extra or only:
         todo += [("padding", padding), ("compute_units", compute_units),
                  ("hybrid_variants", hybrid_variants)]

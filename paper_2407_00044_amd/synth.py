@@ -52,6 +52,34 @@ def fp8_scaled(x64):
     return q, scale
 
 
+def mx_quantize(x64, block=32):
+    """MX quantisation of rows along K: for each block of `block` consecutive
+    K-values of a row, the shared exponent X = ceil(log2(amax / 448)) (the
+    smallest power of two that brings the block into the e4m3fn range, so
+    nothing saturates; amax 0 gives X = 0) is stored as the E8M0 code
+    X + 127, and the elements become RNE_e4m3fn(x / 2^X).  Returns (e4m3 codes
+    tensor R x K, uint8 scale array R x ceil(K/block))."""
+    x = np.asarray(x64, dtype=np.float64)
+    R, K = x.shape
+    nb = -(-K // block)
+    e = np.zeros((R, nb), dtype=np.int64)
+    q = np.empty_like(x)
+    for b in range(nb):
+        blk = x[:, b * block:(b + 1) * block]
+        amax = np.max(np.abs(blk), axis=1)
+        safe = np.where(amax > 0, amax, E4M3_MAX)
+        X = np.ceil(np.log2(safe / E4M3_MAX))
+        # guard the log's rounding: the smallest X with amax / 2^X <= 448
+        X = np.where(safe / np.ldexp(1.0, X.astype(np.int64)) > E4M3_MAX, X + 1, X)
+        X = np.where(safe / np.ldexp(1.0, (X - 1).astype(np.int64)) <= E4M3_MAX, X - 1, X)
+        X = np.clip(np.where(amax > 0, X, 0), -127, 127).astype(np.int64)
+        e[:, b] = X + 127
+        q[:, b * block:(b + 1) * block] = np.clip(blk / np.ldexp(1.0, X)[:, None], -E4M3_MAX,
+                                                  E4M3_MAX)
+    codes_t = torch.from_numpy(np.ascontiguousarray(q)).to(torch.float8_e4m3fn)
+    return codes_t, e.astype(np.uint8)
+
+
 def codes(t):
     """Raw bit patterns of a CPU tensor (uint32/uint16/uint8 numpy array)."""
     dt = {v: k for k, v in TORCH_DTYPES.items()}[t.dtype]

@@ -204,3 +204,41 @@ def test_tile_span_limit_and_large_problems():
     hyb = sk.Config(tile=(128, 128), num_cu=256, mode="hybrid").c_struct(_abi.SK_BF16)
     assert lib.sk_plan(ctypes.byref(big), 1, ctypes.byref(hyb), ctypes.byref(info)) == _abi.SK_OK
     assert info.T == 512 * 512 and info.S == 0        # T mod g == 0: pure data-parallel
+
+
+def test_mx_entry_point_host_checks():
+    # host-side rejections of sk_gemm_mx (nothing is launched, no GPU touched)
+    lib = _abi.load()
+    cfg = sk.Config(tile=(128, 128), num_cu=8).c_struct(_abi.SK_MXF8E4M3)
+
+    def prob(M, N, K, la=_abi.SK_ROW_MAJOR, lb=_abi.SK_COL_MAJOR, dt=_abi.SK_MXF8E4M3):
+        lda = K if la == _abi.SK_ROW_MAJOR else M
+        ldb = K if lb == _abi.SK_COL_MAJOR else N
+        return _abi.SkProblem(M, N, K, la, lb, lda, ldb, N, dt, _abi.SK_F32, 1.0, 0.0, 1.0, 1.0)
+
+    fake = ctypes.c_void_p(1 << 20)          # 16-byte aligned, never dereferenced
+
+    def call(p, lds=8, sa=fake, sb=fake, a=fake):
+        return lib.sk_gemm_mx(ctypes.byref(p), a, fake, sa, lds, sb, lds, None, fake, None, 0,
+                              ctypes.byref(cfg), None)
+    # K not a multiple of 128, or M/N-contiguous operands: not built
+    assert call(prob(256, 256, 192)) == _abi.SK_ERR_UNSUPPORTED
+    assert call(prob(256, 256, 256, la=_abi.SK_COL_MAJOR)) == _abi.SK_ERR_UNSUPPORTED
+    assert call(prob(256, 256, 256, lb=_abi.SK_ROW_MAJOR)) == _abi.SK_ERR_UNSUPPORTED
+    # A not 16-byte aligned: unsupported; scale pitch too short or unaligned
+    assert call(prob(256, 256, 256), a=ctypes.c_void_p((1 << 20) + 4)) == _abi.SK_ERR_UNSUPPORTED
+    assert call(prob(256, 256, 256), lds=4) == _abi.SK_ERR_INVALID_ARG
+    assert call(prob(256, 256, 256), lds=10) == _abi.SK_ERR_INVALID_ARG
+    assert call(prob(256, 256, 256), sa=None) == _abi.SK_ERR_INVALID_ARG
+    assert call(prob(256, 256, 256), sb=ctypes.c_void_p((1 << 20) + 2)) == _abi.SK_ERR_INVALID_ARG
+    # MXFP8 needs its scales: plain sk_gemm refuses it, and sk_gemm_mx
+    # refuses any other input type
+    p = prob(256, 256, 256)
+    assert lib.sk_gemm(ctypes.byref(p), fake, fake, None, fake, None, 0, ctypes.byref(cfg),
+                       None) == _abi.SK_ERR_INVALID_ARG
+    cfg8 = sk.Config(tile=(128, 128), num_cu=8).c_struct(_abi.SK_F8E4M3)
+    p8 = prob(256, 256, 256, dt=_abi.SK_F8E4M3)
+    assert lib.sk_gemm_mx(ctypes.byref(p8), fake, fake, fake, 8, fake, 8, None, fake, None, 0,
+                          ctypes.byref(cfg8), None) == _abi.SK_ERR_INVALID_ARG
+    # the tile menu: 256x128 and 128x128
+    assert sk.supported_tiles(_abi.SK_MXF8E4M3) == [(128, 128, 128), (256, 128, 128)]

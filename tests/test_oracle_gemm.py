@@ -163,3 +163,93 @@ def test_rel_frobenius_basics():
     assert og.rel_frobenius([3.0, 4.0], [3.0, 4.0]) == 0.0
     assert og.rel_frobenius([3.0, 4.0], [0.0, 0.0]) == 5.0
     assert abs(og.rel_frobenius([3.0, 5.0], [3.0, 4.0]) - 0.2) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# MXFP8 (OCP MX block scaling).
+
+def test_decode_e8m0_all_codes():
+    codes = np.arange(256, dtype=np.uint8)
+    ref = torch.from_numpy(codes).view(torch.float8_e8m0fnu).to(torch.float64).numpy()
+    got = og.decode_e8m0(codes)
+    assert np.array_equal(got, ref, equal_nan=True)
+    # the format itself: 2^(e-127), e = 255 NaN
+    assert got[127] == 1.0 and got[128] == 2.0 and got[0] == 2.0 ** -127
+    assert np.isnan(got[255]) and not np.isnan(got[:255]).any()
+
+
+def _mx_case(M, N, K, seed, ldpad=0, spad=0):
+    rng = np.random.default_rng(seed)
+    a = rng.integers(0, 256, size=(M, K + ldpad)).astype(np.uint8)
+    b = rng.integers(0, 256, size=(N, K + ldpad)).astype(np.uint8)
+    a[(a & 0x7F) == 0x7F] = 0x10            # no NaN codes
+    b[(b & 0x7F) == 0x7F] = 0x10
+    sa = rng.integers(120, 135, size=(M, K // 32 + spad)).astype(np.uint8)
+    sb = rng.integers(120, 135, size=(N, K // 32 + spad)).astype(np.uint8)
+    return a, b, sa, sb
+
+
+def test_mx_unit_scales_equal_plain_e4m3_product(oracle_built):
+    M, N, K = 7, 5, 96
+    a, b, _, _ = _mx_case(M, N, K, 1, ldpad=3)
+    one_a = np.full((M, K // 32), 127, np.uint8)
+    one_b = np.full((N, K // 32), 127, np.uint8)
+    got = og.gemm_mx(M, N, K, a, K + 3, one_a, K // 32, b, K + 3, one_b, K // 32)
+    plain = og.gemm(M, N, K, og.decode_e4m3fn(a.reshape(-1)), K + 3, False,
+                    og.decode_e4m3fn(b.reshape(-1)), K + 3, True)
+    assert np.array_equal(got, plain)
+
+
+def test_mx_brute_force_exact_rationals(oracle_built):
+    # every block-scaled element is a dyadic rational: the exact sum (with
+    # Fractions) rounded once to float64 agrees with the FP64 loop to its
+    # summation error
+    from fractions import Fraction
+    M, N, K = 3, 4, 64
+    a, b, sa, sb = _mx_case(M, N, K, 2, ldpad=0, spad=2)
+    lds = K // 32 + 2
+    got = og.gemm_mx(M, N, K, a, K, sa, lds, b, K, sb, lds)
+    ea = og.decode_e4m3fn(a.reshape(-1))
+    eb = og.decode_e4m3fn(b.reshape(-1))
+    for i in range(M):
+        for j in range(N):
+            acc = Fraction(0)
+            for k in range(K):
+                fa = Fraction(ea[i * K + k]) * Fraction(2) ** (int(sa[i, k // 32]) - 127)
+                fb = Fraction(eb[j * K + k]) * Fraction(2) ** (int(sb[j, k // 32]) - 127)
+                acc += fa * fb
+            assert abs(got[i, j] - float(acc)) <= 1e-13 * max(1.0, abs(float(acc)))
+
+
+def test_mx_block_scale_moves_one_block_by_a_power_of_two(oracle_built):
+    # raising the scale code of one block of one row of A by d multiplies
+    # that block's contribution to the row of C by 2^d and nothing else
+    M, N, K = 4, 6, 128
+    a, b, sa, sb = _mx_case(M, N, K, 3)
+    base = og.gemm_mx(M, N, K, a, K, sa, K // 32, b, K, sb, K // 32)
+    sa2 = sa.copy()
+    sa2[2, 1] += 3
+    bumped = og.gemm_mx(M, N, K, a, K, sa2, K // 32, b, K, sb, K // 32)
+    # the block's own contribution, by the oracle on that block alone
+    mask = np.zeros((M, K), np.uint8)
+    a_blk = np.where(np.arange(K)[None, :] // 32 == 1, a, 0).astype(np.uint8)
+    part = og.gemm_mx(M, N, K, a_blk, K, sa, K // 32, b, K, sb, K // 32)
+    expect = base.copy()
+    expect[2] += (2.0 ** 3 - 1.0) * part[2]
+    assert np.allclose(bumped, expect, rtol=1e-13, atol=0)
+    assert np.array_equal(np.delete(bumped, 2, axis=0), np.delete(base, 2, axis=0))
+    del mask
+
+
+def test_mx_quantize_round_trip_within_e4m3_precision():
+    from paper_2407_00044_amd import synth
+    x = np.random.default_rng(4).standard_normal((5, 256)) * np.logspace(-3, 3, 256)[None, :]
+    q, s = synth.mx_quantize(x)
+    assert q.dtype == torch.float8_e4m3fn and s.shape == (5, 8)
+    back = og.mx_operand(synth.codes(q), 256, s, 8, 5, 256)
+    rel = np.abs(back - x) / np.maximum(np.abs(x), 1e-300)
+    # e4m3 keeps 3 fraction bits: relative rounding error <= 2^-4 for values
+    # in each block's normal range; the block's smallest values may be
+    # subnormal, so check the error against the block's largest value too
+    blk_max = np.repeat(np.abs(x).reshape(5, 8, 32).max(axis=2), 32, axis=1)
+    assert np.all((rel <= 2.0 ** -4) | (np.abs(back - x) <= blk_max * 2.0 ** -9))
