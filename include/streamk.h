@@ -113,9 +113,29 @@ typedef enum {
   SK_ROLE_DP = 3        /* a whole data-parallel tile */
 } sk_role;
 
+/* Activation of the fused epilogue (beyond the report, whose GEMM is the
+ * bare product: the epilogue of a linear layer, the deep-learning use its
+ * Introduction names).  Computed in FP32 on the FP32 sum of the epilogue:
+ *   SK_ACT_RELU  max(v, 0) (NaN passes through)
+ *   SK_ACT_GELU  v * Phi(v) = 0.5 v (1 + erf(v / sqrt 2)) (the erf form)
+ *   SK_ACT_SILU  v / (1 + exp(-v)) */
+typedef enum {
+  SK_ACT_NONE = 0, SK_ACT_RELU = 1, SK_ACT_GELU = 2, SK_ACT_SILU = 3
+} sk_activation;
+
 /* One GEMM.  dtype_c is SK_F32, SK_F16 or SK_BF16 (results are rounded to
  * nearest-even from FP32).  scale_a / scale_b are the per-tensor scales of
- * FP8 inputs (use 1 otherwise).  beta == 0 means C_in is never read. */
+ * FP8 inputs (use 1 otherwise).  beta == 0 means C_in is never read.
+ *
+ * Fused epilogue: with bias and activation left zero (a zeroed tail, as a
+ * caller that predates these fields leaves it) the output is the product
+ * above.  Otherwise
+ *   C_out[i][j] = act(alpha*scale_a*scale_b*(A B)[i][j] + beta*C_in[i][j]
+ *                     + bias[j])
+ * with bias a device array of N FP32 values, 4-byte aligned (NULL: no bias),
+ * applied once per output element by the workgroup that finishes the tile
+ * (partial tiles hold raw sums).  Unknown activation codes are
+ * SK_ERR_INVALID_ARG.  The planning calls ignore both fields. */
 typedef struct {
   int64_t M, N, K;
   int32_t layout_a, layout_b;   /* sk_layout */
@@ -123,6 +143,9 @@ typedef struct {
   int32_t dtype_ab;             /* sk_dtype of A and B */
   int32_t dtype_c;              /* sk_dtype of C_in / C_out */
   float alpha, beta, scale_a, scale_b;
+  const float* bias;            /* device, N values, or NULL */
+  int32_t activation;           /* sk_activation */
+  int32_t reserved;             /* 0 */
 } sk_problem;
 
 /* Launch configuration.  block_m x block_n x block_k must be a tile built

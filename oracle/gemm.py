@@ -17,7 +17,9 @@ below, which are written from the published bit-level format definitions, not
 from any library conversion routine.  ``s_A``, ``s_B`` are the per-tensor
 scales of FP8 inputs (1 otherwise).  MXFP8 inputs (OCP MX block scaling)
 multiply each block of 32 K-values of a row of A or a column of B by a
-power-of-two E8M0 scale first (gemm_mx), which is exact in FP64.
+power-of-two E8M0 scale first (gemm_mx), which is exact in FP64.  The
+fused epilogue (bias per output column, then an activation) is applied to
+that FP64 result by ``epilogue``.
 """
 import ctypes
 import os
@@ -211,6 +213,29 @@ def gemm_dense(A, B, alpha=1.0, beta=0.0, Cin=None, rows=None):
     return gemm(M, N, K, A, K, False, B, N, False, alpha, beta,
                 None if Cin is None else np.asarray(Cin, dtype=np.float64),
                 N, rows)
+
+
+def epilogue(c, bias=None, activation="none"):
+    """Fused linear-layer epilogue applied to a product C (beyond the
+    report, whose GEMM is the bare product; the layer is the deep-learning
+    use its Introduction names): act(C[i][j] + bias[j]) in FP64, bias one
+    value per output column.  Activations by their definitions:
+    relu max(v, 0) (NaN passes through), gelu v * Phi(v) with
+    Phi(v) = (1 + erf(v / sqrt 2)) / 2 the standard normal distribution,
+    silu v * sigma(v) with sigma(v) = 1 / (1 + exp(-v))."""
+    from scipy import special
+    v = np.array(c, dtype=np.float64, copy=True)
+    if bias is not None:
+        v = v + np.asarray(bias, dtype=np.float64)[None, :]
+    if activation == "none":
+        return v
+    if activation == "relu":
+        return np.where(v < 0, 0.0, v)
+    if activation == "gelu":
+        return v * 0.5 * (1.0 + special.erf(v / np.sqrt(2.0)))
+    if activation == "silu":
+        return v * special.expit(v)
+    raise ValueError(activation)
 
 
 def rel_frobenius(x, ref) -> float:

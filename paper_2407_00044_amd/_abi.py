@@ -30,6 +30,7 @@ SK_F32, SK_F16, SK_BF16, SK_F8E4M3, SK_MXF8E4M3 = 0, 1, 2, 3, 4
 SK_ROW_MAJOR, SK_COL_MAJOR = 0, 1
 SK_MODE_HYBRID, SK_MODE_SK, SK_MODE_DP, SK_MODE_AUTO = 0, 1, 2, 3
 SK_ROLE_FULL, SK_ROLE_FINISH, SK_ROLE_PARTIAL, SK_ROLE_DP = 0, 1, 2, 3
+SK_ACT_NONE, SK_ACT_RELU, SK_ACT_GELU, SK_ACT_SILU = 0, 1, 2, 3
 
 MODES = {"hybrid": SK_MODE_HYBRID, "sk": SK_MODE_SK, "dp": SK_MODE_DP, "auto": SK_MODE_AUTO}
 
@@ -40,7 +41,8 @@ class SkProblem(ctypes.Structure):
                 ("lda", c_i64), ("ldb", c_i64), ("ldc", c_i64),
                 ("dtype_ab", c_i32), ("dtype_c", c_i32),
                 ("alpha", c_f32), ("beta", c_f32),
-                ("scale_a", c_f32), ("scale_b", c_f32)]
+                ("scale_a", c_f32), ("scale_b", c_f32),
+                ("bias", ctypes.c_void_p), ("activation", c_i32), ("reserved", c_i32)]
 
 
 class SkConfig(ctypes.Structure):

@@ -120,6 +120,24 @@ def _problem(A, B, C, alpha, beta, scale_a, scale_b, prefer=(None, None)):
                      OUT_CODES[C.dtype], alpha, beta, scale_a, scale_b)
 
 
+ACTIVATIONS = {"none": _abi.SK_ACT_NONE, "relu": _abi.SK_ACT_RELU,
+               "gelu": _abi.SK_ACT_GELU, "silu": _abi.SK_ACT_SILU}
+
+
+def _set_epilogue(p, bias, activation, device):
+    """Fused epilogue fields of a problem: bias (N FP32 values on the GPU,
+    or None) added to every row, then the activation (see ACTIVATIONS)."""
+    if activation not in ACTIVATIONS:
+        raise ValueError(f"activation must be one of {list(ACTIVATIONS)}")
+    p.activation = ACTIVATIONS[activation]
+    if bias is not None:
+        if (bias.dtype != torch.float32 or bias.dim() != 1 or bias.numel() != p.N
+                or bias.stride(0) != 1 or bias.device != device):
+            raise ValueError("bias: contiguous float32 vector of N values on the GPU")
+        p.bias = bias.data_ptr()
+    return p
+
+
 class Workspace:
     """Reusable fixup workspace for one device and stream (grows on demand;
     zeroed with the library's fill kernel whenever it is (re)allocated)."""
@@ -157,8 +175,10 @@ def _stream_ptr(stream=None):
 
 
 def gemm(A, B, C=None, *, alpha=1.0, beta=0.0, out=None, out_dtype=torch.float32,
-         scale_a=1.0, scale_b=1.0, config=None, workspace=None, stream=None):
-    """out = alpha * scale_a * scale_b * (A @ B) + beta * C on the GPU.
+         scale_a=1.0, scale_b=1.0, bias=None, activation="none", config=None,
+         workspace=None, stream=None):
+    """out = act(alpha * scale_a * scale_b * (A @ B) + beta * C + bias) on the
+    GPU (bias and act optional: the fused epilogue; see ACTIVATIONS).
 
     A (M x K) and B (K x N) may each be row- or column-major (unit stride in
     one dimension); out and C are row-major.  With C given and out None the
@@ -172,7 +192,8 @@ def gemm(A, B, C=None, *, alpha=1.0, beta=0.0, out=None, out_dtype=torch.float32
             (M, N), dtype=out_dtype, device=A.device)
     if beta != 0.0 and C is None:
         raise ValueError("beta != 0 needs C")
-    p = _problem(A, B, out, alpha, beta, scale_a, scale_b)
+    p = _set_epilogue(_problem(A, B, out, alpha, beta, scale_a, scale_b), bias, activation,
+                      A.device)
     cfg = config or Config(tile=default_tile(M, N, A.shape[1], A.dtype))
     if C is not None and beta != 0.0:
         if tuple(C.shape) != (M, N) or C.dtype != out.dtype or C.stride() != out.stride():
@@ -193,12 +214,13 @@ def gemm(A, B, C=None, *, alpha=1.0, beta=0.0, out=None, out_dtype=torch.float32
 
 
 def gemm_mx(A, B, scale_a, scale_b, C=None, *, alpha=1.0, beta=0.0, out=None,
-            out_dtype=torch.float32, config=None, workspace=None, stream=None):
+            out_dtype=torch.float32, bias=None, activation="none", config=None,
+            workspace=None, stream=None):
     """MXFP8 GEMM through sk_gemm_mx: A (M x K, row-major) and B (K x N,
     column-major) hold e4m3 codes (torch.float8_e4m3fn); scale_a (M x >= K/32)
     and scale_b (N x >= K/32) hold one E8M0 byte (uint8, 2^(e-127)) per 32
     K-values of each row of A and column of B, rows contiguous.
-    out = alpha * sum_k (A * 2^(sa-127)) (B * 2^(sb-127)) + beta * C."""
+    out = act(alpha * sum_k (A * 2^(sa-127)) (B * 2^(sb-127)) + beta * C + bias)."""
     lib = load()
     if A.dtype != torch.float8_e4m3fn or B.dtype != torch.float8_e4m3fn:
         raise TypeError("MXFP8 operands are torch.float8_e4m3fn codes")
@@ -211,7 +233,7 @@ def gemm_mx(A, B, scale_a, scale_b, C=None, *, alpha=1.0, beta=0.0, out=None,
             (M, N), dtype=out_dtype, device=A.device)
     if beta != 0.0 and C is None:
         raise ValueError("beta != 0 needs C")
-    p = _problem(A, B, out, alpha, beta, 1.0, 1.0)
+    p = _set_epilogue(_problem(A, B, out, alpha, beta, 1.0, 1.0), bias, activation, A.device)
     p.dtype_ab = _abi.SK_MXF8E4M3
     if scale_a.shape[0] != M or scale_b.shape[0] != N:
         raise ValueError("one scale row per row of A and per column of B")
@@ -237,7 +259,8 @@ def gemm_mx(A, B, scale_a, scale_b, C=None, *, alpha=1.0, beta=0.0, out=None,
 
 
 def gemm_noalloc(A, B, C=None, *, alpha=1.0, beta=0.0, out=None, out_dtype=torch.float32,
-                 scale_a=1.0, scale_b=1.0, config=None, stream=None):
+                 scale_a=1.0, scale_b=1.0, bias=None, activation="none", config=None,
+                 stream=None):
     """gemm() through sk_gemm_noalloc: the library's static per-GPU scratch
     array is the workspace, so the call allocates no device memory (with out
     given).  Calls that overlap on one GPU race; see include/streamk.h."""
@@ -250,7 +273,8 @@ def gemm_noalloc(A, B, C=None, *, alpha=1.0, beta=0.0, out=None, out_dtype=torch
             (M, N), dtype=out_dtype, device=A.device)
     if beta != 0.0 and C is None:
         raise ValueError("beta != 0 needs C")
-    p = _problem(A, B, out, alpha, beta, scale_a, scale_b)
+    p = _set_epilogue(_problem(A, B, out, alpha, beta, scale_a, scale_b), bias, activation,
+                      A.device)
     cfg = config or Config(tile=default_tile(M, N, A.shape[1], A.dtype))
     if C is not None and beta != 0.0:
         if tuple(C.shape) != (M, N) or C.dtype != out.dtype or C.stride() != out.stride():
@@ -439,14 +463,18 @@ class GroupedGemm:
     problems: list of (A, B, out) or (A, B, out, C_in, beta) tuples sharing
     the input dtype, output dtype and operand layouts.  Descriptors and the
     workspace are set up once here (not capturable); run() only launches and
-    can be captured into a HIP graph (torch.cuda.CUDAGraph)."""
+    can be captured into a HIP graph (torch.cuda.CUDAGraph).  biases: per
+    problem a float32 vector of N values or None, added before the activation
+    (one for every problem) in the fused epilogue."""
 
-    def __init__(self, problems, config=None, alpha=1.0, scales=None, stream=None):
+    def __init__(self, problems, config=None, alpha=1.0, scales=None, stream=None,
+                 biases=None, activation="none"):
         lib = load()
         n = len(problems)
         if n == 0:
             raise ValueError("no problems")
         self.problems = problems
+        self.biases = biases          # the descriptors hold their addresses
         probs = (SkProblem * n)()
         ptrs = {k: (ctypes.c_void_p * n)() for k in ("A", "B", "Cin", "Cout")}
         # the group's operand layouts, taken from its first non-empty operands
@@ -459,7 +487,9 @@ class GroupedGemm:
             Cin = pr[3] if len(pr) > 3 else None
             beta = pr[4] if len(pr) > 4 else 0.0
             sa, sb = scales[i] if scales is not None else (1.0, 1.0)
-            probs[i] = _problem(A, B, out, alpha, beta, sa, sb, prefer)
+            probs[i] = _set_epilogue(_problem(A, B, out, alpha, beta, sa, sb, prefer),
+                                     biases[i] if biases is not None else None, activation,
+                                     A.device)
             ptrs["A"][i] = A.data_ptr()
             ptrs["B"][i] = B.data_ptr()
             ptrs["Cin"][i] = Cin.data_ptr() if (Cin is not None and beta != 0.0) else None

@@ -53,7 +53,7 @@ struct Plan {
   bool dp_grid = false;          // one workgroup per tile, no fixup
   double pred_us = 0.0;          // launch-time model: this launch
   double pred_dp_us = 0.0;       // ... and the data-parallel grid of the problems
-  std::vector<ProbDesc> descs;   // pointers left null by plan_problems
+  std::vector<ProbDesc> descs;   // operand pointers left null by plan_problems
   std::vector<int32_t> order;    // descs[i] describes caller problem order[i]
 };
 
@@ -118,6 +118,9 @@ static sk_status check_problem(const sk_problem& p) {
   if (p.lda < std::max<int64_t>(1, need_a)) return SK_ERR_INVALID_ARG;
   if (p.ldb < std::max<int64_t>(1, need_b)) return SK_ERR_INVALID_ARG;
   if (p.ldc < std::max<int64_t>(1, p.N)) return SK_ERR_INVALID_ARG;
+  if (p.activation < SK_ACT_NONE || p.activation > SK_ACT_SILU || p.reserved != 0)
+    return SK_ERR_INVALID_ARG;
+  if (((uintptr_t)p.bias & 3) != 0) return SK_ERR_INVALID_ARG;
   return SK_OK;
 }
 
@@ -286,6 +289,8 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
     d.tn = (int32_t)(p.N > 0 ? cdiv(p.N, bn) : 0);
     d.I = (int32_t)std::max<int64_t>(1, cdiv(p.K, bk));
     d.user_index = P.order[i];
+    d.act = p.activation;
+    d.bias = p.bias;
     d.tile_start = T;
     T += (int64_t)d.tm * d.tn;
     P.max_iters = std::max<int64_t>(P.max_iters, d.I);
@@ -603,6 +608,7 @@ static sk_status gemm_common(const sk_problem* p, const void* A, const void* B, 
 // hipGetSymbolAddress, once per device, and only that address is used.
 constexpr int64_t kScratchBytes = kSlotsOffset + (int64_t)256 * 256 * 256 * 4;
 static_assert(kScratchBytes == SK_NOALLOC_SCRATCH_BYTES, "scratch size in the header");
+static_assert(sizeof(sk_problem) == 96, "sk_problem layout of the header");
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 static std::mutex g_scratch_mu;

@@ -1363,7 +1363,43 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
-template <typename C, int DTC>
+// Activations of the fused epilogue, in FP32, written for compact code (the
+// epilogue is unrolled over every accumulator, so each instruction here is
+// repeated per element): exp via the hardware exp2 (v_exp_f32) and
+// reciprocals via v_rcp_f32, both accurate to about one ulp.
+__device__ __forceinline__ float fast_exp(float x) {
+  return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
+}
+
+// erfc(z) for z >= 0 by the rational Chebyshev fit of Numerical Recipes in C
+// (2nd ed., section 6.2, "erfcc"): fractional error below 1.2e-7 for every z.
+__device__ __forceinline__ float erfc_nonneg(float z) {
+  const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.5f, z, 1.f));
+  float p = 0.17087277f;
+  p = __builtin_fmaf(p, t, -0.82215223f);
+  p = __builtin_fmaf(p, t, 1.48851587f);
+  p = __builtin_fmaf(p, t, -1.13520398f);
+  p = __builtin_fmaf(p, t, 0.27886807f);
+  p = __builtin_fmaf(p, t, -0.18628806f);
+  p = __builtin_fmaf(p, t, 0.09678418f);
+  p = __builtin_fmaf(p, t, 0.37409196f);
+  p = __builtin_fmaf(p, t, 1.00002368f);
+  p = __builtin_fmaf(p, t, -1.26551223f);
+  return t * fast_exp(__builtin_fmaf(-z, z, p));
+}
+
+// GELU(v) = v Phi(v) = (v/2) erfc(-v/sqrt 2): for v < 0 directly, for v >= 0
+// as v - (v/2) erfc(v/sqrt 2), so no 1 + erf cancellation for either sign.
+__device__ __forceinline__ float gelu(float v) {
+  const float h = 0.5f * v * erfc_nonneg(__builtin_fabsf(v) * 0.70710678118654752f);
+  return v < 0.f ? h : v - h;
+}
+
+__device__ __forceinline__ float silu(float v) {
+  return v * __builtin_amdgcn_rcpf(1.f + fast_exp(-v));
+}
+
+template <typename C, int DTC, bool EX>
 __device__ __forceinline__ void epilogue_t(const Acc<C>& acc, const ProbDesc& pd, int64_t m0,
                                            int64_t n0, int tid) {
   constexpr int ES = DTC == DT_F32 ? 4 : 2;           // output element size
@@ -1405,26 +1441,64 @@ __device__ __forceinline__ void epilogue_t(const Acc<C>& acc, const ProbDesc& pd
         dst[r] = __builtin_bit_cast(float, (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(in, off, 0, 0) << 16);
     }
   };
+  // fused epilogue: the bias of this lane's column in each 32-column block
+  float bias[C::FN];
+  int act = SK_ACT_NONE;
+  if constexpr (EX) {
+    act = pd.act;
+    const __amdgpu_buffer_rsrc_t br =
+        make_rsrc((const char*)(pd.bias ? (const void*)pd.bias : pd.Cout) + n0 * 4,
+                  pd.bias ? cols_left * 4 : 0);
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j)   // columns past N read 0 (and are dropped)
+      bias[j] = __builtin_bit_cast(
+          float, __builtin_amdgcn_raw_buffer_load_b32(br, (wc + 32 * j) * 4, 0, 0));
+  }
   // C_in of block b+1 is loaded while block b is finished, so only the first
-  // block's load latency is exposed.
+  // block's load latency is exposed (plain epilogue; the fused one loads each
+  // block's C_in just before it, which keeps its registers below the spill
+  // point of the 256x256 kernels).
   float cin[2][16];
-  if (use_cin) load_cin(0, cin[0]);
+  if (use_cin && !EX) load_cin(0, cin[0]);
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    if (use_cin && b + 1 < NB) load_cin(b + 1, cin[(b + 1) & 1]);
+    if constexpr (EX) {
+      if (use_cin) load_cin(b, cin[b & 1]);
+    } else {
+      if (use_cin && b + 1 < NB) load_cin(b + 1, cin[(b + 1) & 1]);
+    }
     __builtin_amdgcn_sched_barrier(0);
     const int i = b / C::FN, j = b % C::FN;
+    float v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      v[r] = use_cin ? __builtin_fmaf(alpha, acc.a[i][j][r], beta * cin[b & 1][r])
+                     : alpha * acc.a[i][j][r];
+    if constexpr (EX) {
+      // one uniform branch per block (not per element) keeps each
+      // activation's code together
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] += bias[j];
+      if (act == SK_ACT_RELU) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = v[r] < 0.f ? 0.f : v[r];
+      } else if (act == SK_ACT_GELU) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = gelu(v[r]);
+      } else if (act == SK_ACT_SILU) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = silu(v[r]);
+      }
+    }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int off = elem_off(b, r);
-      const float v = use_cin ? __builtin_fmaf(alpha, acc.a[i][j][r], beta * cin[b & 1][r])
-                              : alpha * acc.a[i][j][r];
       if constexpr (DTC == DT_F32)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), out, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v[r]), out, off, 0, 0);
       else if constexpr (DTC == DT_F16)
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (_Float16)v), out, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (_Float16)v[r]), out, off, 0, 0);
       else
-        __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16_rne(v), out, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16_rne(v[r]), out, off, 0, 0);
     }
     // one block at a time: keeps the scheduler from gathering all loads and
     // stores of the tile and the registers they would need
@@ -1433,14 +1507,24 @@ __device__ __forceinline__ void epilogue_t(const Acc<C>& acc, const ProbDesc& pd
 }
 
 // Epilogue: out = alpha_s * acc + beta * Cin (one FP32 fma when beta != 0),
-// rounded to nearest-even in the output type; out-of-range elements get an
-// offset past the buffer and are dropped by the hardware.
+// then, when the problem asks for it, + bias[column] and the activation, all
+// in FP32; rounded to nearest-even in the output type; out-of-range elements
+// get an offset past the buffer and are dropped by the hardware.
+template <typename C, bool EX>
+__device__ __forceinline__ void epilogue_c(const Acc<C>& acc, const ProbDesc& pd, int dtype_c,
+                                           int64_t m0, int64_t n0, int tid) {
+  if (dtype_c == DT_F32) epilogue_t<C, DT_F32, EX>(acc, pd, m0, n0, tid);
+  else if (dtype_c == DT_F16) epilogue_t<C, DT_F16, EX>(acc, pd, m0, n0, tid);
+  else epilogue_t<C, DT_BF16, EX>(acc, pd, m0, n0, tid);
+}
+
 template <typename C>
 __device__ __forceinline__ void epilogue(const Acc<C>& acc, const ProbDesc& pd, int dtype_c,
                                          int64_t m0, int64_t n0, int tid) {
-  if (dtype_c == DT_F32) epilogue_t<C, DT_F32>(acc, pd, m0, n0, tid);
-  else if (dtype_c == DT_F16) epilogue_t<C, DT_F16>(acc, pd, m0, n0, tid);
-  else epilogue_t<C, DT_BF16>(acc, pd, m0, n0, tid);
+  if (pd.bias != nullptr || pd.act != SK_ACT_NONE)
+    epilogue_c<C, true>(acc, pd, dtype_c, m0, n0, tid);
+  else
+    epilogue_c<C, false>(acc, pd, dtype_c, m0, n0, tid);
 }
 
 // Partial tile <-> workspace slot.  Thread t owns the same accumulator

@@ -25,10 +25,11 @@ struct ProbDesc {
   int64_t iter_start;        // global Stream-K iteration of that tile
                              // (W when the problem has no Stream-K tile)
   int32_t user_index;        // index of the problem in the caller's array
-  int32_t pad_;
+  int32_t act;               // sk_activation of the epilogue
   const void* sA;            // MXFP8: E8M0 scales of A, row i at sA + i * ldsa
   const void* sB;            //        and of B, column j at sB + j * ldsb
   int64_t ldsa, ldsb;        //        (bytes; one scale per 32 K-values)
+  const float* bias;         // N FP32 values added before the activation, or null
 };
 
 struct KParams {

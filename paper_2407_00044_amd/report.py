@@ -254,6 +254,39 @@ def mxfp8(dev, reps=5, shape=(3840, 4096, 4096), tile=(256, 128)):
     return res
 
 
+def epilogue(dev, reps=5, shape=(3840, 4096, 4096), tile=(256, 256)):
+    """Cost of the fused epilogue (bias per column, then ReLU / GELU / SiLU)
+    on BF16 at the headline shape, auto policy: the plain GEMM, each fused
+    variant, and the plain GEMM followed by torch's own bias and GELU passes
+    over C (the unfused alternative: one more read and write of C)."""
+    M, N, K = shape
+    ws = api.Workspace(dev)
+    ws.get(96 << 20, torch.cuda.current_stream().cuda_stream)
+    A = _uniform((M, K), 2, dev).bfloat16()
+    B = _uniform((N, K), 3, dev).bfloat16().t()
+    bias = _uniform((1, N), 4, dev)[0].float().contiguous()
+    out = torch.empty((M, N), device=dev)
+    fl = 2.0 * M * N * K
+    cfg = api.Config(tile=tile, mode="auto")
+
+    def fused(act, b=bias):
+        return lambda: api.gemm(A, B, out=out, bias=b, activation=act, config=cfg, workspace=ws)
+
+    def unfused():
+        api.gemm(A, B, out=out, config=cfg, workspace=ws)
+        torch.nn.functional.gelu(out.add_(bias), approximate="none")
+
+    legs = {"plain": fused("none", None), "bias": fused("none"), "bias_relu": fused("relu"),
+            "bias_gelu": fused("gelu"), "bias_silu": fused("silu"),
+            "plain_then_torch_bias_gelu": unfused}
+    ts = _time_all(list(legs.values()), reps)
+    res = {"workload": f"BF16 {M}x{N}x{K}, A row-major, B column-major, FP32 output, "
+                       f"tile {tile[0]}x{tile[1]}, auto"}
+    for n, t in zip(legs, ts):
+        res[n] = {"ms": round(t, 4), "tflops": _tf(fl, t)}
+    return res
+
+
 def padding(dev, reps=10, tile=(256, 128)):
     """The report's padding experiment (Methodology, Results, Table 1) on
     FP16: each shape run unpadded (edges through out-of-range loads and
@@ -347,7 +380,7 @@ def run_all(dev, extra=False, only=None, c5_tile=None):
     c5_tile runs c5 in auto mode on that tile instead of the tuner's pick."""
     out = {}
     todo = [("c1", c1), ("c3", c3), ("c4", c4), ("c5", lambda d: c5(d, tile=c5_tile)),
-            ("per_dtype", per_dtype), ("mxfp8", mxfp8)]
+            ("per_dtype", per_dtype), ("mxfp8", mxfp8), ("epilogue", epilogue)]
     if extra or only:
         todo += [("padding", padding), ("compute_units", compute_units),
                  ("hybrid_variants", hybrid_variants)]

@@ -96,6 +96,24 @@ def test_invalid_arguments():
     bad.dtype_c = 0
     bad.layout_a = 7
     assert call(bad) == _abi.SK_ERR_INVALID_ARG
+    bad.layout_a = 0
+    # fused epilogue: activation codes 0..3, bias 4-byte aligned, reserved 0
+    for act in (_abi.SK_ACT_RELU, _abi.SK_ACT_GELU, _abi.SK_ACT_SILU):
+        bad.activation = act
+        assert call(bad) == _abi.SK_OK
+    bad.activation = 4
+    assert call(bad) == _abi.SK_ERR_INVALID_ARG
+    bad.activation = -1
+    assert call(bad) == _abi.SK_ERR_INVALID_ARG
+    bad.activation = 0
+    bad.bias = 0x1002
+    assert call(bad) == _abi.SK_ERR_INVALID_ARG
+    bad.bias = 0x1000
+    assert call(bad) == _abi.SK_OK
+    bad.bias = None
+    bad.reserved = 1
+    assert call(bad) == _abi.SK_ERR_INVALID_ARG
+    assert ctypes.sizeof(_abi.SkProblem) == 96     # the C struct's size on x86-64
     c2 = sk.Config(tile=(96, 128), num_cu=8).c_struct(_abi.SK_BF16)
     assert call(good, c2) == _abi.SK_ERR_UNSUPPORTED          # tile not built
     c3 = sk.Config(tile=(128, 128), num_cu=8).c_struct(_abi.SK_BF16)

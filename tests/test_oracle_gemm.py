@@ -253,3 +253,59 @@ def test_mx_quantize_round_trip_within_e4m3_precision():
     # subnormal, so check the error against the block's largest value too
     blk_max = np.repeat(np.abs(x).reshape(5, 8, 32).max(axis=2), 32, axis=1)
     assert np.all((rel <= 2.0 ** -4) | (np.abs(back - x) <= blk_max * 2.0 ** -9))
+
+
+# ---------------------------------------------------------------------------
+# Fused epilogue: bias per output column, then an activation.
+
+def test_epilogue_bias_is_per_column_on_a_rank_one_product(oracle_built):
+    # C = u v^T + bias[j] on a non-square shape: a bias broadcast along the
+    # wrong axis, or dropped, fails (values exact in FP64)
+    u = np.arange(1, 6, dtype=np.float64)            # M = 5
+    v = np.arange(-3, 4, dtype=np.float64)           # N = 7
+    bias = np.array([0.5, -1, 2, 0, 8, -0.25, 3])
+    c = og.epilogue(og.gemm_dense(u[:, None], v[None, :]), bias)
+    assert np.array_equal(c, np.outer(u, v) + bias[None, :])
+    assert np.array_equal(og.epilogue(c), c)          # "none" is the identity
+
+
+def test_epilogue_relu_hand_values():
+    x = np.array([[-2.0, -0.0, 0.0, 1.5, np.inf, -np.inf, np.nan]])
+    r = og.epilogue(x, activation="relu")
+    assert np.array_equal(r[0, :6], [0, 0, 0, 1.5, np.inf, 0])
+    assert np.isnan(r[0, 6])
+
+
+def test_epilogue_gelu_normal_quantile_and_odd_part():
+    # Phi(1.959963984540054) = 0.975 (the 97.5% point of the standard
+    # normal), so GELU(z) = 0.975 z there; Phi(0) = 1/2; and since erf is odd,
+    # GELU(x) - GELU(-x) = x for every x
+    z = 1.959963984540054
+    g = og.epilogue(np.array([[z, -z, 0.0, 1.0]]), activation="gelu")[0]
+    assert abs(g[0] - 0.975 * z) <= 1e-14 * z
+    assert abs(g[1] + 0.025 * z) <= 1e-13 * z
+    assert g[2] == 0.0
+    x = np.random.default_rng(7).normal(scale=3, size=(4, 50))
+    d = og.epilogue(x, activation="gelu") - og.epilogue(-x, activation="gelu")
+    assert np.max(np.abs(d - x)) <= 1e-14 * np.max(np.abs(x))
+    # far tails: GELU -> x for large x, -> 0 for very negative x
+    t = og.epilogue(np.array([[40.0, -40.0]]), activation="gelu")[0]
+    assert t[0] == 40.0 and abs(t[1]) < 1e-300
+
+
+def test_epilogue_silu_closed_forms():
+    # sigma(ln 3) = 3/4, so SiLU(ln 3) = (3/4) ln 3; sigma(x) + sigma(-x) = 1
+    # gives SiLU(x) - SiLU(-x) = x; huge negative inputs give 0, not NaN
+    s = og.epilogue(np.array([[np.log(3.0), 0.0, -800.0, 800.0]]), activation="silu")[0]
+    assert abs(s[0] - 0.75 * np.log(3.0)) <= 1e-15
+    assert s[1] == 0.0 and s[2] == 0.0 and s[3] == 800.0
+    x = np.random.default_rng(8).normal(scale=4, size=(3, 40))
+    d = og.epilogue(x, activation="silu") - og.epilogue(-x, activation="silu")
+    assert np.max(np.abs(d - x)) <= 1e-14 * np.max(np.abs(x))
+
+
+def test_epilogue_bias_before_activation():
+    # act(c + b), not act(c) + b: with c = -1 and b = 2, relu gives 1 (the
+    # other order would give 2)
+    r = og.epilogue(np.full((2, 3), -1.0), np.full(3, 2.0), "relu")
+    assert np.array_equal(r, np.ones((2, 3)))
