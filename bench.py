@@ -110,19 +110,28 @@ def cpu_baseline(host, M, N, K, min_seconds=10.0, max_reps=4):
                       f"repetition(s), {dt:.1f} s wall"}
 
 
+def _code_only(text):
+    """C/C++ source without comments or blank lines (comments do not change
+    a kernel)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def kernel_source_hash():
-    """Hash of the sources the measured kernels are compiled from: the
-    kernel instantiation unit and the headers it includes (host-only files,
-    sk_api.hip and sk_cost.hpp, do not change a kernel)."""
+    """Hash of the code the measured kernels are compiled from: the kernel
+    instantiation unit and the headers it includes, comments left out
+    (host-only files, sk_api.hip and sk_cost.hpp, do not change a kernel)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2407_00044_amd", "csrc")
-    for name in ("sk_inst.hip", "sk_kernel.hpp", "sk_params.hpp", "sk_registry.hpp",
-                 "sk_sched.hpp"):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
-    with open(os.path.join(ROOT, "include", "streamk.h"), "rb") as f:
-        h.update(b"streamk.h" + f.read())
+    files = [os.path.join(csrc, name) for name in
+             ("sk_inst.hip", "sk_kernel.hpp", "sk_params.hpp", "sk_registry.hpp", "sk_sched.hpp")]
+    files.append(os.path.join(ROOT, "include", "streamk.h"))
+    for path in files:
+        with open(path, encoding="utf-8") as f:
+            h.update(os.path.basename(path).encode() + _code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
