@@ -325,7 +325,7 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
     if (is_auto && P.S > 0) {
       // SK_MODE_AUTO: split tiles only if the model predicts the launch
       // without splits (the data-parallel grid for one problem, whole tiles
-      // on the persistent workgroups for several) to be kAutoMargin times
+      // on the persistent workgroups for several) to be auto_margin times
       // slower
       Plan A = P;
       if (n == 1) {
@@ -338,7 +338,7 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
         A.pred_us = predict_us(A, c, cus);
       }
       A.pred_dp_us = P.pred_dp_us;
-      if (!(A.pred_us > kAutoMargin * P.pred_us)) P = std::move(A);
+      if (!(A.pred_us > auto_margin(probs[0].dtype_ab) * P.pred_us)) P = std::move(A);
     } else if (is_auto && P.S == 0 && n == 1) {
       // nothing to split on one problem: the data-parallel grid itself (the
       // hardware hands out tiles as workgroups finish, which beats a fixed
@@ -734,7 +734,7 @@ sk_status sk_cost_model(int32_t dtype_ab, int32_t block_m, int32_t block_n, floa
   const CostRow* c = cost_row(dtype_ab, block_m, block_n);
   if (c == nullptr) return SK_ERR_UNSUPPORTED;
   const float v[10] = {c->t_launch, c->t_tile, c->t_it_full, c->t_it_light, c->t_store,
-                       c->t_peer, c->l2, c->t_cin, (float)kAutoMargin,
+                       c->t_peer, c->l2, c->t_cin, (float)auto_margin(dtype_ab),
                        (float)(c->bm * 65536 + c->bn)};
   for (int i = 0; i < 10; ++i) constants[i] = v[i];
   return SK_OK;

@@ -177,14 +177,17 @@ def test_cost_model_matches_second_implementation(shapes, dtype, tile, g, mode, 
 
 
 def test_auto_mode_follows_the_model():
-    margin = sk.cost_model(BF16, (128, 128))["margin"]
-    assert margin == pytest.approx(1.08)
+    assert sk.cost_model(BF16, (128, 128))["margin"] == pytest.approx(1.08)
+    assert sk.cost_model(E4, (256, 128))["margin"] == pytest.approx(1.08)
+    assert sk.cost_model(F32, (128, 128))["margin"] == pytest.approx(1.03)
     cases = [((512, 512, 512), F32, (128, 128)), ((3840, 4096, 4096), F16, (256, 128)),
              ((3840, 4096, 4096), BF16, (256, 256)), ((1286, 292, 1415), BF16, (128, 128)),
              ((4826, 1341, 13813), BF16, (256, 256)), ((607, 187, 3155), BF16, (256, 128)),
-             ((6160, 303, 2722), E4, (128, 128)), ((2190, 3876, 2048), BF16, (128, 128))]
+             ((6160, 303, 2722), E4, (128, 128)), ((2190, 3876, 2048), BF16, (128, 128)),
+             ((3840, 4096, 4096), F32, (128, 128))]
     split = []
     for shape, dtype, tile in cases:
+        margin = sk.cost_model(dtype, tile)["margin"]
         h = P(shape, dtype, tile, 256, "hybrid")
         a = P(shape, dtype, tile, 256, "auto")
         if h["S"] == 0:
@@ -195,14 +198,17 @@ def test_auto_mode_follows_the_model():
         if h["predicted_dp_us"] > margin * h["predicted_us"]:
             assert t(a, "S", "g", "dp_grid") == (h["S"], h["g"], 0)
             assert a["predicted_us"] == h["predicted_us"]
-            split.append(shape)
+            split.append((shape, dtype))
         else:
             assert t(a, "S", "g", "dp_grid") == (0, h["T"], 1)
             assert a["predicted_us"] == h["predicted_dp_us"]
     # long K on few tiles: Stream-K wins by the model (and by measurement);
     # the headline shape on 256x128 tiles: the data-parallel grid
-    assert (512, 512, 512) in split and (4826, 1341, 13813) in split
-    assert (3840, 4096, 4096) not in split
+    assert ((512, 512, 512), F32) in split and ((4826, 1341, 13813), BF16) in split
+    # the headline shape: FP32 splits (a 5.9% predicted gain clears 1.03),
+    # the 16-bit kernels on 256x128 and 256x256 tiles do not
+    assert ((3840, 4096, 4096), F32) in split
+    assert ((3840, 4096, 4096), F16) not in split and ((3840, 4096, 4096), BF16) not in split
     # a grouped launch with nothing split stays on the persistent grid
     p = P([(3840, 4096, 4096)] * 2, F16, (256, 128), 256, "auto")
     assert p["dp_grid"] == 0 and p["g"] == 256
