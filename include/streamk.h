@@ -331,8 +331,9 @@ sk_status sk_gemm(const sk_problem* p, const void* A, const void* B,
  * Requirements (else SK_ERR_UNSUPPORTED): A row-major and B column-major,
  * K a multiple of 128, A and B 16-byte aligned with lda, ldb multiples of
  * 16.  scale_a/scale_b 4-byte aligned, ld_scale_a/ld_scale_b multiples of 4
- * and >= K/32 (else SK_ERR_INVALID_ARG).  Single problems only (no grouped
- * launch); sk_gemm with SK_MXF8E4M3 returns SK_ERR_INVALID_ARG. */
+ * and >= K/32 (else SK_ERR_INVALID_ARG).  Grouped launches:
+ * sk_grouped_prepare_mx; sk_gemm with SK_MXF8E4M3 returns
+ * SK_ERR_INVALID_ARG. */
 sk_status sk_gemm_mx(const sk_problem* p, const void* A, const void* B,
                      const void* scale_a, int64_t ld_scale_a, const void* scale_b,
                      int64_t ld_scale_b, const void* C_in, void* C_out,
@@ -433,6 +434,24 @@ sk_status sk_grouped_prepare(const sk_problem* probs, const void* const* A,
                              const sk_config* cfg, void* dev_desc,
                              size_t desc_bytes, sk_grouped_plan* plan,
                              void* hip_stream);
+
+/* sk_grouped_prepare for MXFP8 problems (dtype_ab = SK_MXF8E4M3 in every
+ * problem; beyond the report: OCP MX block scaling, as sk_gemm_mx):
+ * scale_a[i] / scale_b[i] are problem i's E8M0 scales (rows of A, columns
+ * of B, one byte per 32 K-values, ld_scale_a[i] / ld_scale_b[i] bytes
+ * apart), with sk_gemm_mx's requirements per problem (K-contiguous
+ * operands, K a multiple of 128, 16-byte aligned operands and leading
+ * dimensions, 4-byte aligned scale rows of at least K/32 bytes).
+ * sk_grouped_prepare with SK_MXF8E4M3 problems returns SK_ERR_INVALID_ARG.
+ * The plan launches with sk_gemm_grouped. */
+sk_status sk_grouped_prepare_mx(const sk_problem* probs, const void* const* A,
+                                const void* const* B, const void* const* scale_a,
+                                const int64_t* ld_scale_a, const void* const* scale_b,
+                                const int64_t* ld_scale_b, const void* const* C_in,
+                                void* const* C_out, int32_t nprobs,
+                                const sk_config* cfg, void* dev_desc,
+                                size_t desc_bytes, sk_grouped_plan* plan,
+                                void* hip_stream);
 
 /* Launches one grouped GEMM described by plan + dev_desc.  Launch only:
  * asynchronous and capturable into a HIP graph. */

@@ -111,6 +111,9 @@ PROTOTYPES = {
     "sk_grouped_prepare": (c_i32, [P(SkProblem), P(c_vp), P(c_vp), P(c_vp), P(c_vp),
                                    c_i32, P(SkConfig), c_vp, ctypes.c_size_t,
                                    P(SkGroupedPlan), c_vp]),
+    "sk_grouped_prepare_mx": (c_i32, [P(SkProblem), P(c_vp), P(c_vp), P(c_vp), P(c_i64),
+                                      P(c_vp), P(c_i64), P(c_vp), P(c_vp), c_i32, P(SkConfig),
+                                      c_vp, ctypes.c_size_t, P(SkGroupedPlan), c_vp]),
     "sk_gemm_grouped": (c_i32, [P(SkGroupedPlan), c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "sk_gemm_grouped_debug": (c_i32, [P(SkGroupedPlan), c_vp, c_vp, ctypes.c_size_t,
                                       P(SkDebug), c_vp]),

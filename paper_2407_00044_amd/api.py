@@ -465,10 +465,12 @@ class GroupedGemm:
     workspace are set up once here (not capturable); run() only launches and
     can be captured into a HIP graph (torch.cuda.CUDAGraph).  biases: per
     problem a float32 vector of N values or None, added before the activation
-    (one for every problem) in the fused epilogue."""
+    (one for every problem) in the fused epilogue.  mx_scales: MXFP8
+    problems (A, B torch.float8_e4m3fn codes, A row-major, B column-major),
+    per problem (scale_a, scale_b) as for gemm_mx."""
 
     def __init__(self, problems, config=None, alpha=1.0, scales=None, stream=None,
-                 biases=None, activation="none"):
+                 biases=None, activation="none", mx_scales=None):
         lib = load()
         n = len(problems)
         if n == 0:
@@ -490,23 +492,47 @@ class GroupedGemm:
             probs[i] = _set_epilogue(_problem(A, B, out, alpha, beta, sa, sb, prefer),
                                      biases[i] if biases is not None else None, activation,
                                      A.device)
+            if mx_scales is not None:
+                probs[i].dtype_ab = _abi.SK_MXF8E4M3
             ptrs["A"][i] = A.data_ptr()
             ptrs["B"][i] = B.data_ptr()
             ptrs["Cin"][i] = Cin.data_ptr() if (Cin is not None and beta != 0.0) else None
             ptrs["Cout"][i] = out.data_ptr()
         dev = problems[0][0].device
         M0, N0, K0 = probs[0].M, probs[0].N, probs[0].K
-        self.config = config or Config(tile=default_tile(M0, N0, K0, problems[0][0].dtype))
+        if config is None:
+            tile = default_tile(M0, N0, K0, problems[0][0].dtype)
+            if mx_scales is not None and tile not in ((256, 128), (128, 128)):
+                tile = (128, 128)         # the MXFP8 tile menu
+            config = Config(tile=tile)
+        self.config = config
         c = self.config.c_struct(probs[0].dtype_ab)
         dbytes = ctypes.c_size_t()
         check("sk_grouped_desc_size", lib.sk_grouped_desc_size(n, ctypes.byref(dbytes)))
         self.desc = torch.empty(dbytes.value, dtype=torch.uint8, device=dev)
         self.plan = SkGroupedPlan()
         sp = _stream_ptr(stream)
-        check("sk_grouped_prepare", lib.sk_grouped_prepare(
-            probs, ptrs["A"], ptrs["B"], ptrs["Cin"], ptrs["Cout"], n, ctypes.byref(c),
-            ctypes.c_void_p(self.desc.data_ptr()), dbytes.value, ctypes.byref(self.plan),
-            ctypes.c_void_p(sp)))
+        if mx_scales is None:
+            check("sk_grouped_prepare", lib.sk_grouped_prepare(
+                probs, ptrs["A"], ptrs["B"], ptrs["Cin"], ptrs["Cout"], n, ctypes.byref(c),
+                ctypes.c_void_p(self.desc.data_ptr()), dbytes.value, ctypes.byref(self.plan),
+                ctypes.c_void_p(sp)))
+        else:
+            if len(mx_scales) != n:
+                raise ValueError("one (scale_a, scale_b) pair per problem")
+            self.mx_scales = mx_scales    # the descriptors hold their addresses
+            sp_a, sp_b = (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)()
+            ld_a, ld_b = (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)()
+            for i, (s_a, s_b) in enumerate(mx_scales):
+                for t in (s_a, s_b):
+                    if t.dtype != torch.uint8 or t.dim() != 2 or t.stride(1) != 1 or not t.is_cuda:
+                        raise TypeError("block scales: 2-D uint8 GPU tensors with contiguous rows")
+                sp_a[i], ld_a[i] = s_a.data_ptr(), max(1, s_a.stride(0))
+                sp_b[i], ld_b[i] = s_b.data_ptr(), max(1, s_b.stride(0))
+            check("sk_grouped_prepare_mx", lib.sk_grouped_prepare_mx(
+                probs, ptrs["A"], ptrs["B"], sp_a, ld_a, sp_b, ld_b, ptrs["Cin"], ptrs["Cout"], n,
+                ctypes.byref(c), ctypes.c_void_p(self.desc.data_ptr()), dbytes.value,
+                ctypes.byref(self.plan), ctypes.c_void_p(sp)))
         self.workspace = Workspace(dev)
         self.ws_ptr, self.ws_len = self.workspace.get(int(self.plan.workspace_bytes), sp)
         torch.cuda.current_stream().synchronize()

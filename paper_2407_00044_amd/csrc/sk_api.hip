@@ -560,6 +560,24 @@ struct MxScales {
   int64_t ldsb;
 };
 
+// An MXFP8 problem and its operands and block scales: the kernels are built
+// for K-contiguous operands, whole 128-element iterations and 16-byte loads,
+// and read the scales as 4-byte words, 4 per iteration.
+static sk_status check_mx(const sk_problem& p, const void* A, const void* B, const MxScales& mx) {
+  if (p.layout_a != SK_ROW_MAJOR || p.layout_b != SK_COL_MAJOR || p.K % 128 != 0)
+    return SK_ERR_UNSUPPORTED;
+  if (p.M == 0 || p.N == 0 || p.K == 0) return SK_OK;
+  if (!aligned16(A) || !aligned16(B) || p.lda % 16 != 0 || p.ldb % 16 != 0)
+    return SK_ERR_UNSUPPORTED;
+  if (mx.sA == nullptr || mx.sB == nullptr || ((uintptr_t)mx.sA & 3) != 0 ||
+      ((uintptr_t)mx.sB & 3) != 0 || mx.ldsa % 4 != 0 || mx.ldsb % 4 != 0 ||
+      mx.ldsa < p.K / 32 || mx.ldsb < p.K / 32)
+    return SK_ERR_INVALID_ARG;
+  if ((p.M - 1) * mx.ldsa + p.K / 32 > kMaxIndex || (p.N - 1) * mx.ldsb + p.K / 32 > kMaxIndex)
+    return SK_ERR_UNSUPPORTED;
+  return SK_OK;
+}
+
 static sk_status gemm_common(const sk_problem* p, const void* A, const void* B, const void* Cin,
                              void* Cout, void* ws, size_t ws_bytes_, const sk_config* cfg,
                              const sk_debug* dbg, void* stream, const MxScales* mx = nullptr) {
@@ -570,19 +588,8 @@ static sk_status gemm_common(const sk_problem* p, const void* A, const void* B, 
   sk_status st = plan_problems(p, 1, cfg, &P);
   if (st != SK_OK) return st;
   if (mx) {
-    // kernels built for K-contiguous operands, whole 128-element iterations
-    // and 16-byte loads; scales read as 4-byte words, 4 per iteration
-    if (p->layout_a != SK_ROW_MAJOR || p->layout_b != SK_COL_MAJOR || p->K % 128 != 0)
-      return SK_ERR_UNSUPPORTED;
-    if (!aligned16(A) || !aligned16(B) || p->lda % 16 != 0 || p->ldb % 16 != 0)
-      return SK_ERR_UNSUPPORTED;
-    if (p->M > 0 && p->N > 0 && p->K > 0 &&
-        (mx->sA == nullptr || mx->sB == nullptr || ((uintptr_t)mx->sA & 3) != 0 ||
-         ((uintptr_t)mx->sB & 3) != 0 || mx->ldsa % 4 != 0 || mx->ldsb % 4 != 0 ||
-         mx->ldsa < p->K / 32 || mx->ldsb < p->K / 32))
-      return SK_ERR_INVALID_ARG;
-    if ((p->M - 1) * mx->ldsa + p->K / 32 > kMaxIndex || (p->N - 1) * mx->ldsb + p->K / 32 > kMaxIndex)
-      return SK_ERR_UNSUPPORTED;
+    st = check_mx(*p, A, B, *mx);
+    if (st != SK_OK) return st;
   }
   if (p->M == 0 || p->N == 0) return SK_OK;
   if (Cout == nullptr) return SK_ERR_INVALID_ARG;
@@ -834,16 +841,24 @@ sk_status sk_grouped_desc_size(int32_t nprobs, size_t* bytes) {
   return SK_OK;
 }
 
-sk_status sk_grouped_prepare(const sk_problem* probs, const void* const* A,
-                             const void* const* B, const void* const* C_in, void* const* C_out,
-                             int32_t nprobs, const sk_config* cfg, void* dev_desc,
-                             size_t desc_bytes, sk_grouped_plan* plan, void* stream) {
+// sk_grouped_prepare and, with the block scales of every problem,
+// sk_grouped_prepare_mx.
+static sk_status grouped_prepare(const sk_problem* probs, const void* const* A,
+                                 const void* const* B, const void* const* sA,
+                                 const int64_t* ldsa, const void* const* sB,
+                                 const int64_t* ldsb, const void* const* C_in,
+                                 void* const* C_out, int32_t nprobs, const sk_config* cfg,
+                                 void* dev_desc, size_t desc_bytes, sk_grouped_plan* plan,
+                                 void* stream) {
   if (plan == nullptr || A == nullptr || B == nullptr || C_out == nullptr || dev_desc == nullptr)
     return SK_ERR_INVALID_ARG;
   Plan P;
   sk_status st = plan_problems(probs, nprobs, cfg, &P);
   if (st != SK_OK) return st;
-  if (probs[0].dtype_ab == SK_MXF8E4M3) return SK_ERR_UNSUPPORTED;   // single problems only
+  // MXFP8 problems need their block scales (sk_grouped_prepare_mx); others take none
+  const bool mx = probs[0].dtype_ab == SK_MXF8E4M3;
+  if (mx != (sA != nullptr && ldsa != nullptr && sB != nullptr && ldsb != nullptr))
+    return SK_ERR_INVALID_ARG;
   if (desc_bytes < (size_t)nprobs * sizeof(ProbDesc)) return SK_ERR_WORKSPACE;
   const int eb = elem_bytes(probs[0].dtype_ab);
   int32_t all_aligned = 1;
@@ -858,6 +873,13 @@ sk_status sk_grouped_prepare(const sk_problem* probs, const void* const* A,
       if (d.Cout == nullptr) return SK_ERR_INVALID_ARG;
       if (p.K > 0 && (d.A == nullptr || d.B == nullptr)) return SK_ERR_INVALID_ARG;
       if (p.beta != 0.f && d.Cin == nullptr) return SK_ERR_INVALID_ARG;
+    }
+    if (mx) {
+      const MxScales m{sA[j], ldsa[j], sB[j], ldsb[j]};
+      st = check_mx(p, d.A, d.B, m);
+      if (st != SK_OK) return st;
+      d.sA = m.sA; d.sB = m.sB;
+      d.ldsa = m.ldsa; d.ldsb = m.ldsb;
     }
     d.aligned = aligned16(d.A) && aligned16(d.B) && (p.lda * eb) % 16 == 0 &&
                 (p.ldb * eb) % 16 == 0;
@@ -886,6 +908,27 @@ sk_status sk_grouped_prepare(const sk_problem* probs, const void* const* A,
   plan->all_aligned = all_aligned;
   plan->max_iters = P.max_iters;
   return SK_OK;
+}
+
+sk_status sk_grouped_prepare(const sk_problem* probs, const void* const* A,
+                             const void* const* B, const void* const* C_in, void* const* C_out,
+                             int32_t nprobs, const sk_config* cfg, void* dev_desc,
+                             size_t desc_bytes, sk_grouped_plan* plan, void* stream) {
+  return grouped_prepare(probs, A, B, nullptr, nullptr, nullptr, nullptr, C_in, C_out, nprobs,
+                         cfg, dev_desc, desc_bytes, plan, stream);
+}
+
+sk_status sk_grouped_prepare_mx(const sk_problem* probs, const void* const* A,
+                                const void* const* B, const void* const* scale_a,
+                                const int64_t* ld_scale_a, const void* const* scale_b,
+                                const int64_t* ld_scale_b, const void* const* C_in,
+                                void* const* C_out, int32_t nprobs, const sk_config* cfg,
+                                void* dev_desc, size_t desc_bytes, sk_grouped_plan* plan,
+                                void* stream) {
+  if (scale_a == nullptr || ld_scale_a == nullptr || scale_b == nullptr || ld_scale_b == nullptr)
+    return SK_ERR_INVALID_ARG;
+  return grouped_prepare(probs, A, B, scale_a, ld_scale_a, scale_b, ld_scale_b, C_in, C_out,
+                         nprobs, cfg, dev_desc, desc_bytes, plan, stream);
 }
 
 static sk_status grouped_common(const sk_grouped_plan* plan, const void* dev_desc,

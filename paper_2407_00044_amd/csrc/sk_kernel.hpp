@@ -855,12 +855,12 @@ struct FragReader {
   static constexpr int PITCH = R * C::EB;    // bytes per k-row (TR stage)
   int off[NB];
   int l32, half;
-  int sb;                                    // MXFP8: this lane's scale byte in block 0, step 0
+  int sb;                                    // MXFP8: the 4 scale bytes of this lane's row (block 0)
 
   __device__ __forceinline__ void init(int rowbase, int lane) {
     l32 = lane & 31;
     half = lane >> 5;
-    if constexpr (C::MX) sb = SREL + 4 * (rowbase + l32) + half;
+    if constexpr (C::MX) sb = SREL + 4 * (rowbase + l32);
     if constexpr (TR && C::EB == 2) {
       static_assert(C::STEPS == 4, "16 k-values per step");
       const int p = lane & 15, g = lane >> 4, j = p >> 2, q = p & 3;
@@ -914,7 +914,13 @@ struct FragReader {
         lo[1] = 0;
       }
       f = read_frag<C::DT>(op + off[i], lo);
-      if constexpr (C::MX) f.s = (int32_t)*(const uint8_t*)(op + sb + 128 * i + 2 * s);
+      // MXFP8: the scale of step s is byte 2s + half of the row's 4 bytes;
+      // the matrix core reads byte 0 of the operand.  Step 0 reads the 4
+      // bytes once, shifted to this lane's half; step 1 takes them from step
+      // 0.s fragment (in step_fenced), so each iteration reads the scales
+      // of a fragment with one LDS instruction instead of two.
+      if constexpr (C::MX)
+        f.s = (s & 1) ? 0 : (int32_t)(*(const uint32_t*)(op + sb + 128 * i) >> (8 * half));
     }
     return f;
   }
@@ -1093,8 +1099,18 @@ __device__ __forceinline__ void step_fenced(
   for (int t = 0; t < NM; ++t) {
     mma<C::DT>(acc.a[t / C::FN][t % C::FN], fa[t / C::FN], fb[t % C::FN]);
 #pragma unroll
-    for (int n = t * NRF / NM; n < (t + 1) * NRF / NM; ++n)
+    for (int n = t * NRF / NM; n < (t + 1) * NRF / NM; ++n) {
       read_frag_n<C>(ra, rb, rda, rdb, opA, opB, rs, n);
+      // MXFP8, step 1 read during step 0 of the same iteration: its scale
+      // is byte 2 of step 0's (bytes 2s + half of the row's 4)
+      if constexpr (C::MX) {
+        if (rs & 1) {
+          if (n < 1) ra[0].s = fa[0].s >> 16;
+          else if (n <= C::FN) rb[n - 1].s = fb[n - 1].s >> 16;
+          else ra[n - C::FN].s = fa[n - C::FN].s >> 16;
+        }
+      }
+    }
 #pragma unroll
     for (int c = CB + t * NCP / NM; c < CB + (t + 1) * NCP / NM; ++c) {
       if (c < NA) sa.issue_one(dst, kba, tid, on, c);

@@ -260,3 +260,48 @@ def test_mx_entry_point_host_checks():
                           ctypes.byref(cfg8), None) == _abi.SK_ERR_INVALID_ARG
     # the tile menu: 256x128 and 128x128
     assert sk.supported_tiles(_abi.SK_MXF8E4M3) == [(128, 128, 128), (256, 128, 128)]
+
+
+def test_grouped_mx_host_checks():
+    # host-side rejections of sk_grouped_prepare(_mx) for MXFP8 problems; each
+    # is raised before the descriptors would be copied (no GPU touched)
+    lib = _abi.load()
+    cfg = sk.Config(tile=(128, 128), num_cu=8).c_struct(_abi.SK_MXF8E4M3)
+    n = 2
+    probs = (_abi.SkProblem * n)()
+    for i, (M, N, K) in enumerate([(256, 256, 256), (100, 300, 512)]):
+        probs[i] = _abi.SkProblem(M, N, K, _abi.SK_ROW_MAJOR, _abi.SK_COL_MAJOR, K, K, N,
+                                  _abi.SK_MXF8E4M3, _abi.SK_F32, 1.0, 0.0, 1.0, 1.0)
+    fake = 1 << 20
+    ptr = lambda v: (ctypes.c_void_p * n)(*([v] * n))          # noqa: E731
+    lds = lambda v: (ctypes.c_int64 * n)(*([v] * n))           # noqa: E731
+    plan = _abi.SkGroupedPlan()
+    desc = ctypes.c_void_p(fake)
+    dbytes = 1 << 16
+    # plain prepare: MXFP8 problems need their scales
+    assert lib.sk_grouped_prepare(probs, ptr(fake), ptr(fake), None, ptr(fake), n,
+                                  ctypes.byref(cfg), desc, dbytes, ctypes.byref(plan),
+                                  None) == _abi.SK_ERR_INVALID_ARG
+
+    def call(sa=fake, sb=fake, la=16, lb=16):
+        return lib.sk_grouped_prepare_mx(probs, ptr(fake), ptr(fake), ptr(sa), lds(la), ptr(sb),
+                                         lds(lb), None, ptr(fake), n, ctypes.byref(cfg), desc,
+                                         dbytes, ctypes.byref(plan), None)
+    assert call(sa=fake + 2) == _abi.SK_ERR_INVALID_ARG          # scale rows 4-byte aligned
+    assert call(lb=6) == _abi.SK_ERR_INVALID_ARG                 # pitch a multiple of 4
+    assert call(la=8) == _abi.SK_ERR_INVALID_ARG                 # >= K/32 = 16 bytes
+    assert lib.sk_grouped_prepare_mx(probs, ptr(fake), ptr(fake), None, lds(16), ptr(fake),
+                                     lds(16), None, ptr(fake), n, ctypes.byref(cfg), desc,
+                                     dbytes, ctypes.byref(plan), None) == _abi.SK_ERR_INVALID_ARG
+    # K not a multiple of 128 in one problem: not built
+    probs[1].K = 320
+    probs[1].lda = probs[1].ldb = 320
+    assert call() == _abi.SK_ERR_UNSUPPORTED
+    # the MXFP8 prepare refuses other input types
+    cfg8 = sk.Config(tile=(128, 128), num_cu=8).c_struct(_abi.SK_F8E4M3)
+    for i in range(n):
+        probs[i].dtype_ab = _abi.SK_F8E4M3
+        probs[i].K = probs[i].lda = probs[i].ldb = 256
+    assert lib.sk_grouped_prepare_mx(probs, ptr(fake), ptr(fake), ptr(fake), lds(16), ptr(fake),
+                                     lds(16), None, ptr(fake), n, ctypes.byref(cfg8), desc,
+                                     dbytes, ctypes.byref(plan), None) == _abi.SK_ERR_INVALID_ARG

@@ -89,3 +89,55 @@ def test_mx_headline_shape_full_matrix_alpha_beta():
     assert sk.check_device_error() == 0
     expect = ref(2.0, 0.5, cin.cpu().numpy().astype(np.float64))
     assert rel_err(as64(out), expect) <= 1e-4
+
+
+GROUP = [(300, 260, 512), (64, 1000, 1024), (1000, 129, 256), (1, 64, 128), (513, 700, 384)]
+
+
+def grouped_mx_inputs(shapes, seed, dist="normal"):
+    probs, scales, refs = [], [], []
+    for i, (M, N, K) in enumerate(shapes):
+        A, B, SA, SB, ref = mx_inputs(M, N, K, seed + 10 * i, dist)
+        out = torch.full((M, N), float("nan"), device=dev())
+        probs.append((A, B, out))
+        scales.append((SA, SB))
+        refs.append(ref)
+    return probs, scales, refs
+
+
+@pytest.mark.parametrize("tile", [(128, 128), (256, 128)])
+@pytest.mark.parametrize("mode", ["sk", "hybrid", "dp", "auto"])
+def test_mx_grouped_parity(tile, mode):
+    print(f"case mx grouped {tile} {mode}", flush=True)
+    probs, scales, refs = grouped_mx_inputs(GROUP, 91)
+    cfg = sk.Config(tile=tile, mode=mode, num_cu=23, min_iters=1 if mode == "sk" else 0)
+    gg = sk.GroupedGemm(probs, config=cfg, mx_scales=scales)
+    if mode in ("sk", "hybrid"):
+        assert gg.info()["S"] > 0
+    gg.run()
+    torch.cuda.synchronize()
+    assert sk.check_device_error(workspace=gg.workspace) == 0
+    for (A, B, out), ref in zip(probs, refs):
+        assert rel_err(as64(out), ref()) <= 1e-4, tuple(out.shape)
+
+
+def test_mx_grouped_integers_bit_exact_and_graph_replays():
+    print("case mx grouped integers + graph", flush=True)
+    probs, scales, refs = grouped_mx_inputs(GROUP, 92, dist="int")
+    cfg = sk.Config(tile=(256, 128), mode="hybrid", num_cu=37, min_iters=1)
+    gg = sk.GroupedGemm(probs, config=cfg, mx_scales=scales)
+    gg.run()
+    torch.cuda.synchronize()
+    first = []
+    for (A, B, out), ref in zip(probs, refs):
+        assert np.array_equal(as64(out), ref())
+        first.append(out.clone())
+    g = gg.capture()
+    for r in range(3):
+        for _, _, out in probs:
+            out.fill_(float("nan"))              # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (_, _, out), f in zip(probs, first):
+            assert torch.equal(out, f), f"replay {r} differs"
