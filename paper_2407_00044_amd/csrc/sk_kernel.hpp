@@ -746,7 +746,11 @@ struct Cfg {
   // read instructions per step and need the two-step look-ahead of
   // mac_loop_dma (three or more stages) or mac_loop_fast (two).
   static constexpr bool RING = DMA && ((!TRA && !TRB) || (SK_RING_TR && STEPS == 4));
-  static constexpr int RING_LA = (TRA || TRB) ? 2 : 1;
+  // fragments read two matrix-core steps ahead for 16-bit tiles below
+  // 256x256 (+3% at 256x128 and 128x128); the 256x256 tile, at the register
+  // limit, reads one step ahead (two cost it 13-23%), and FP8 iterations
+  // have two steps only
+  static constexpr int RING_LA = (TRA || TRB || (STEPS == 4 && BM * BN < 256 * 256)) ? 2 : 1;
   // LDS-direct copies issued per wave for one iteration
   static constexpr int NLOADS = (BM + BN) / (NT / 8) + (MX ? 1 : 0);
   static_assert(!MX || (LA == L_ROW && LB == L_COL && (BM + BN) * 4 <= NW * 256),
