@@ -746,11 +746,11 @@ struct Cfg {
   // read instructions per step and need the two-step look-ahead of
   // mac_loop_dma (three or more stages) or mac_loop_fast (two).
   static constexpr bool RING = DMA && ((!TRA && !TRB) || (SK_RING_TR && STEPS == 4));
-  // fragments read two matrix-core steps ahead for 16-bit tiles below
-  // 256x256 (+3% at 256x128 and 128x128); the 256x256 tile, at the register
-  // limit, reads one step ahead (two cost it 13-23%), and FP8 iterations
-  // have two steps only
-  static constexpr int RING_LA = (TRA || TRB || (STEPS == 4 && BM * BN < 256 * 256)) ? 2 : 1;
+  // fragments read three matrix-core steps ahead for K-contiguous 16-bit
+  // tiles below 256x256 (against one step: +4-5% at 256x128, +3% at
+  // 128x128); the 256x256 tile, at the register limit, reads one step ahead
+  // (two cost it 13-23%), and FP8 iterations have two steps only
+  static constexpr int RING_LA = (TRA || TRB) ? 2 : (STEPS == 4 && BM * BN < 256 * 256) ? 3 : 1;
   // LDS-direct copies issued per wave for one iteration
   static constexpr int NLOADS = (BM + BN) / (NT / 8) + (MX ? 1 : 0);
   static_assert(!MX || (LA == L_ROW && LB == L_COL && (BM + BN) * 4 <= NW * 256),
@@ -1211,8 +1211,9 @@ __device__ __forceinline__ void mac_loop_dma(Acc<C>& acc, const OpTile& oa, cons
 //
 // Fragments are read LA matrix-core steps ahead of the MFMAs that use them
 // (LA = 1: two fragment buffers; LA = 2, for transposing reads, which take
-// twice the LDS instructions: four), the reads of a step spread evenly over
-// the MFMAs of the step that issues them.  Once the reads of the
+// twice the LDS instructions, and LA = 3, for 16-bit tiles below 256x256:
+// four), the reads of a step spread evenly over the MFMAs of the step that
+// issues them.  Once the reads of the
 // iteration's last step are issued (before step ST-LA), nothing of stage k
 // is read again: each wave waits for its own LDS reads, then for its copies
 // of iteration k+1, and the workgroup barrier makes both facts hold for
@@ -1292,7 +1293,22 @@ __device__ __forceinline__ void mac_loop_ring(Acc<C>& acc, const OpTile& oa, con
         step_fenced<C, 0, 0>(acc, fa[s % NBUF], fb[s % NBUF], fa[(s + LA) % NBUF],
                              fb[(s + LA) % NBUF], rda, rdb, src, src + C::BOFF, rs, sa, sb, ss, cur,
                              kn0, refill, tid);
-      else if (LA == 1 || s == ST - 2)
+      else if (LA == 3) {
+        // the refill's copies spread over the three steps after the barrier
+        if (s == ST - 3)
+          step_fenced<C, 0, NCP / 3>(acc, fa[s % NBUF], fb[s % NBUF], fa[(s + LA) % NBUF],
+                                     fb[(s + LA) % NBUF], rda, rdb, src, src + C::BOFF, rs, sa,
+                                     sb, ss, cur, kn0, refill, tid);
+        else if (s == ST - 2)
+          step_fenced<C, NCP / 3, 2 * NCP / 3>(acc, fa[s % NBUF], fb[s % NBUF],
+                                               fa[(s + LA) % NBUF], fb[(s + LA) % NBUF], rda,
+                                               rdb, src, src + C::BOFF, rs, sa, sb, ss, cur, kn0,
+                                               refill, tid);
+        else
+          step_fenced<C, 2 * NCP / 3, NCP>(acc, fa[s % NBUF], fb[s % NBUF], fa[(s + LA) % NBUF],
+                                           fb[(s + LA) % NBUF], rda, rdb, src, src + C::BOFF, rs,
+                                           sa, sb, ss, cur, kn0, refill, tid);
+      } else if (LA == 1 || s == ST - 2)
         step_fenced<C, 0, (LA == 1 ? NCP : NCP / 2)>(
             acc, fa[s % NBUF], fb[s % NBUF], fa[(s + LA) % NBUF], fb[(s + LA) % NBUF], rda, rdb,
             src, src + C::BOFF, rs, sa, sb, ss, cur, kn0, refill, tid);
