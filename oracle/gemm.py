@@ -121,6 +121,25 @@ def decode_e8m0(bits) -> np.ndarray:
     return np.where(e == 255, np.nan, v)
 
 
+def decode_e2m1(bits) -> np.ndarray:
+    """4-bit OCP FP4 (E2M1) codes 0..15 -> exact float64 values: sign bit,
+    2 exponent bits with bias 1, 1 mantissa bit; exponent 0 is subnormal
+    (0.5 * m); no infinities or NaN, so the magnitudes are 0, 0.5, 1, 1.5,
+    2, 3, 4 and 6."""
+    _, _, _, v = _decode_fields(np.asarray(bits).astype(np.int64) & 15, 2, 1, 1)
+    return v
+
+
+def unpack_fp4(packed, count) -> np.ndarray:
+    """Packed FP4 bytes -> `count` codes: element 2j in the low nibble of byte
+    j, element 2j+1 in the high nibble."""
+    b = np.asarray(packed).astype(np.int64).reshape(-1)
+    codes = np.empty(2 * b.size, dtype=np.int64)
+    codes[0::2] = b & 15
+    codes[1::2] = b >> 4
+    return codes[:count]
+
+
 DECODERS = {"f32": decode_f32, "f16": decode_f16, "bf16": decode_bf16,
             "e4m3": decode_e4m3fn}
 
@@ -175,12 +194,17 @@ def gemm(M, N, K, a, lda, a_col_major, b, ldb, b_col_major, alpha=1.0,
     return out
 
 
-def mx_operand(codes, ld, scales, ld_s, rows, K, block=32):
+def mx_operand(codes, ld, scales, ld_s, rows, K, block=32, elem="e4m3"):
     """An MX operand stored K-contiguous (OCP MX block scaling): element
-    (r, k) is decode_e4m3fn(codes[r*ld + k]) * decode_e8m0(scales[r*ld_s +
-    k // block]).  Returns the rows x K float64 values; each is a decoded
-    e4m3 value times a power of two, so the result is exact."""
-    x = decode_e4m3fn(np.asarray(codes).reshape(-1))
+    (r, k) is decode(codes[r*ld + k]) * decode_e8m0(scales[r*ld_s +
+    k // block]), the elements e4m3 codes, or with elem="e2m1" FP4 codes
+    unpacked from bytes (ld then counts elements: row r starts at element
+    r*ld).  Returns the rows x K float64 values; each is a decoded element
+    times a power of two, so the result is exact."""
+    if elem == "e2m1":
+        x = decode_e2m1(unpack_fp4(codes, 2 * np.asarray(codes).size))
+    else:
+        x = decode_e4m3fn(np.asarray(codes).reshape(-1))
     s = decode_e8m0(np.asarray(scales).reshape(-1))
     out = np.empty((rows, K), dtype=np.float64)
     for r in range(rows):
@@ -190,15 +214,16 @@ def mx_operand(codes, ld, scales, ld_s, rows, K, block=32):
 
 
 def gemm_mx(M, N, K, a_codes, lda, sa, ldsa, b_codes, ldb, sb, ldsb, alpha=1.0, beta=0.0,
-            cin=None, rows=None):
-    """MXFP8 product C = alpha * sum_k A^(i,k) B^(k,j) + beta * Cin, with A
+            cin=None, rows=None, elem="e4m3"):
+    """MX product C = alpha * sum_k A^(i,k) B^(k,j) + beta * Cin, with A
     row-major (row i at a_codes[i*lda]) and B column-major (column j at
-    b_codes[j*ldb]) e4m3 codes and E8M0 scales of every 32 K-values of each
-    row of A (sa[i*ldsa + k//32]) and column of B (sb[j*ldsb + k//32]):
-    A^ and B^ are the block-scaled values (mx_operand, exact), multiplied by
-    the plain FP64 product above."""
-    ahat = mx_operand(a_codes, lda, sa, ldsa, M, K)
-    bhat_t = mx_operand(b_codes, ldb, sb, ldsb, N, K)      # row j = column j of B
+    b_codes[j*ldb]) element codes (e4m3 bytes, or with elem="e2m1" FP4
+    codes packed two per byte, lda/ldb counted in elements) and E8M0 scales
+    of every 32 K-values of each row of A (sa[i*ldsa + k//32]) and column of
+    B (sb[j*ldsb + k//32]): A^ and B^ are the block-scaled values
+    (mx_operand, exact), multiplied by the plain FP64 product above."""
+    ahat = mx_operand(a_codes, lda, sa, ldsa, M, K, elem=elem)
+    bhat_t = mx_operand(b_codes, ldb, sb, ldsb, N, K, elem=elem)   # row j = column j of B
     return gemm(M, N, K, ahat, K, False, bhat_t, K, True, alpha, beta, cin,
                 N if cin is not None else None, rows)
 

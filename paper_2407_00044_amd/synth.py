@@ -80,6 +80,55 @@ def mx_quantize(x64, block=32):
     return codes_t, e.astype(np.uint8)
 
 
+FP4_MAX = 6.0
+# E2M1 magnitudes of codes 0..7 and the midpoints between neighbours
+_FP4_GRID = np.array([0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0])
+_FP4_MID = (_FP4_GRID[:-1] + _FP4_GRID[1:]) / 2
+
+
+def fp4_rne(x):
+    """Round to the nearest E2M1 (FP4) value, ties to the code with an even
+    mantissa, saturating at +-6: returns 4-bit codes (int64)."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.minimum(np.abs(x), FP4_MAX)
+    idx = np.zeros(a.shape, dtype=np.int64)
+    for i, m in enumerate(_FP4_MID):
+        # a tie between codes i and i+1 goes to the even one
+        idx += (a > m) if i % 2 == 0 else (a >= m)
+    return idx | (np.signbit(x).astype(np.int64) << 3)
+
+
+def pack_fp4(codes4):
+    """4-bit codes R x K (K even) -> bytes R x K/2, element 2j in the low
+    nibble of byte j."""
+    c = np.asarray(codes4, dtype=np.int64)
+    return (c[:, 0::2] | (c[:, 1::2] << 4)).astype(np.uint8)
+
+
+def mx4_quantize(x64, block=32):
+    """MXFP4 quantisation of rows along K: for each block of `block`
+    consecutive K-values of a row, the shared exponent X = the smallest power
+    of two with amax / 2^X <= 6 (amax 0 gives X = 0) is stored as the E8M0
+    code X + 127, and the elements become the nearest E2M1 value of x / 2^X.
+    Returns (packed FP4 bytes R x K/2, uint8 scale array R x ceil(K/block))."""
+    x = np.asarray(x64, dtype=np.float64)
+    R, K = x.shape
+    nb = -(-K // block)
+    e = np.zeros((R, nb), dtype=np.int64)
+    c = np.empty(x.shape, dtype=np.int64)
+    for b in range(nb):
+        blk = x[:, b * block:(b + 1) * block]
+        amax = np.max(np.abs(blk), axis=1)
+        safe = np.where(amax > 0, amax, FP4_MAX)
+        X = np.ceil(np.log2(safe / FP4_MAX))
+        X = np.where(safe / np.ldexp(1.0, X.astype(np.int64)) > FP4_MAX, X + 1, X)
+        X = np.where(safe / np.ldexp(1.0, (X - 1).astype(np.int64)) <= FP4_MAX, X - 1, X)
+        X = np.clip(np.where(amax > 0, X, 0), -127, 127).astype(np.int64)
+        e[:, b] = X + 127
+        c[:, b * block:(b + 1) * block] = fp4_rne(blk / np.ldexp(1.0, X)[:, None])
+    return pack_fp4(c), e.astype(np.uint8)
+
+
 def codes(t):
     """Raw bit patterns of a CPU tensor (uint32/uint16/uint8 numpy array)."""
     dt = {v: k for k, v in TORCH_DTYPES.items()}[t.dtype]

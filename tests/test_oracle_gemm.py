@@ -309,3 +309,83 @@ def test_epilogue_bias_before_activation():
     # other order would give 2)
     r = og.epilogue(np.full((2, 3), -1.0), np.full(3, 2.0), "relu")
     assert np.array_equal(r, np.ones((2, 3)))
+
+
+# ---------------------------------------------------------------------------
+# MXFP4: OCP FP4 (E2M1) elements, two per byte, with E8M0 block scales.
+
+def test_decode_e2m1_all_codes():
+    # the OCP MX format's E2M1 table: magnitudes 0, 0.5, 1, 1.5, 2, 3, 4, 6 for
+    # codes 0..7, the same negated for 8..15 (sign bit 3)
+    table = [0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0]
+    got = og.decode_e2m1(np.arange(16))
+    assert np.array_equal(got[:8], table)
+    assert np.array_equal(got[8:], [-v for v in table])
+    assert np.signbit(got[8])                     # code 8 is -0
+    # only the low nibble of a wider integer is a code
+    assert np.array_equal(og.decode_e2m1(np.arange(16) + 0x30), got)
+
+
+def test_unpack_fp4_low_nibble_first():
+    codes = og.unpack_fp4(np.array([0x21, 0xF7, 0x0A], dtype=np.uint8), 5)
+    assert list(codes) == [0x1, 0x2, 0x7, 0xF, 0xA]
+
+
+def test_mx_fp4_product_brute_force_exact_rationals(oracle_built):
+    # an independent evaluation: exact rational arithmetic over the decoded
+    # table, the scales applied per block of 32 K-values
+    from fractions import Fraction
+    rng = np.random.default_rng(11)
+    M, N, K = 3, 2, 64
+    a = rng.integers(0, 256, size=(M, K // 2)).astype(np.uint8)
+    b = rng.integers(0, 256, size=(N, K // 2)).astype(np.uint8)
+    sa = rng.integers(120, 135, size=(M, K // 32)).astype(np.uint8)
+    sb = rng.integers(120, 135, size=(N, K // 32)).astype(np.uint8)
+    table = [Fraction(v) for v in (0, 0.5, 1, 1.5, 2, 3, 4, 6)]
+
+    def val(byte_row, k):
+        code = (int(byte_row[k // 2]) >> (4 * (k % 2))) & 15
+        v = table[code & 7]
+        return -v if code & 8 else v
+
+    def scale(e):
+        return Fraction(2) ** (int(e) - 127)
+    got = og.gemm_mx(M, N, K, a, K, sa, K // 32, b, K, sb, K // 32, elem="e2m1")
+    for i in range(M):
+        for j in range(N):
+            exact = sum(val(a[i], k) * scale(sa[i, k // 32]) * val(b[j], k) * scale(sb[j, k // 32])
+                        for k in range(K))
+            assert got[i, j] == float(exact)
+
+
+def test_mx_fp4_unit_scales_equal_the_plain_product(oracle_built):
+    rng = np.random.default_rng(12)
+    M, N, K = 5, 4, 96
+    a = rng.integers(0, 256, size=(M, K // 2)).astype(np.uint8)
+    b = rng.integers(0, 256, size=(N, K // 2)).astype(np.uint8)
+    ones_a = np.full((M, K // 32), 127, np.uint8)
+    ones_b = np.full((N, K // 32), 127, np.uint8)
+    A = og.decode_e2m1(og.unpack_fp4(a, M * K)).reshape(M, K)
+    B = og.decode_e2m1(og.unpack_fp4(b, N * K)).reshape(N, K).T
+    got = og.gemm_mx(M, N, K, a, K, ones_a, K // 32, b, K, ones_b, K // 32, elem="e2m1")
+    assert np.array_equal(got, A @ B)            # small integers and halves: exact
+
+
+def test_mx4_quantize_round_trip_within_e2m1_precision():
+    # every element within half the E2M1 spacing at its magnitude (0.5 below
+    # 2, 1 below 4, 2 up to 6, times the block's power of two); values on
+    # the grid come back exactly; the block maximum never saturates
+    from paper_2407_00044_amd import synth
+    x = np.random.default_rng(5).standard_normal((5, 256)) * np.logspace(-3, 3, 256)[None, :]
+    p, s = synth.mx4_quantize(x)
+    assert p.dtype == np.uint8 and p.shape == (5, 128) and s.shape == (5, 8)
+    back = og.mx_operand(p, 256, s, 8, 5, 256, elem="e2m1")
+    scale = np.repeat(og.decode_e8m0(s), 32, axis=1)
+    y = np.abs(x) / scale                              # in [0, 6] by the choice of X
+    assert np.all(y <= 6.0)
+    half_spacing = np.where(y < 2, 0.25, np.where(y < 4, 0.5, 1.0)) * scale
+    assert np.all(np.abs(back - x) <= half_spacing)
+    grid = np.array([[0.5, -1.5, 3.0, 6.0] * 8])          # one block on the grid, scale 2^0
+    pg, sg = synth.mx4_quantize(grid)
+    assert sg[0, 0] == 127
+    assert np.array_equal(og.mx_operand(pg, 32, sg, 1, 1, 32, elem="e2m1"), grid)
