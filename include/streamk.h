@@ -77,9 +77,15 @@ typedef enum {
  * (finite, max 448) that gfx950 matrix cores consume.  SK_MXF8E4M3 is OCP
  * MXFP8: e4m3 elements, and for every 32 consecutive K-values of each row of
  * A and each column of B an E8M0 scale byte e (value 2^(e-127), e = 255 NaN)
- * that multiplies them (sk_gemm_mx only).  Accumulation is FP32 for every
- * input type. */
-typedef enum { SK_F32 = 0, SK_F16 = 1, SK_BF16 = 2, SK_F8E4M3 = 3, SK_MXF8E4M3 = 4 } sk_dtype;
+ * that multiplies them (sk_gemm_mx only).  SK_MXF4E2M1 is OCP MXFP4: E2M1
+ * elements (sign, 2 exponent bits with bias 1, 1 mantissa bit: magnitudes
+ * 0, 0.5, 1, 1.5, 2, 3, 4, 6) packed two per byte, element 2j of a row in
+ * the low nibble of byte j, with the same E8M0 block scales; sizes and
+ * leading dimensions count elements.  Accumulation is FP32 for every input
+ * type. */
+typedef enum {
+  SK_F32 = 0, SK_F16 = 1, SK_BF16 = 2, SK_F8E4M3 = 3, SK_MXF8E4M3 = 4, SK_MXF4E2M1 = 5
+} sk_dtype;
 typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
 
 /* How output tiles are distributed (Background section):
@@ -318,10 +324,10 @@ sk_status sk_gemm(const sk_problem* p, const void* A, const void* B,
                   const void* C_in, void* C_out, void* workspace,
                   size_t ws_bytes, const sk_config* cfg, void* hip_stream);
 
-/* One MXFP8 GEMM (dtype_ab = SK_MXF8E4M3): as sk_gemm, with
+/* One MX GEMM (dtype_ab = SK_MXF8E4M3 or SK_MXF4E2M1): as sk_gemm, with
  *   C_out[i][j] = alpha*scale_a*scale_b * sum_k A[i][k] * 2^(sa[i][k/32]-127)
  *                                   * B[k][j] * 2^(sb[j][k/32]-127) + beta*C_in
- * where A, B hold e4m3 codes, sa[i][b] = ((const uint8_t*)scale_a)[i*ld_scale_a
+ * where A, B hold e4m3 codes (MXFP4: packed E2M1 codes), sa[i][b] = ((const uint8_t*)scale_a)[i*ld_scale_a
  * + b] and sb[j][b] = ((const uint8_t*)scale_b)[j*ld_scale_b + b] (device
  * memory; one E8M0 byte per 32 K-values of row i of A / column j of B).
  * The block scales are applied by the matrix cores (gfx950 scaled MFMA),
@@ -329,10 +335,11 @@ sk_status sk_gemm(const sk_problem* p, const void* A, const void* B,
  * whose CK kernel is one configuration per precision (Background); the
  * scaled MX formats are the gfx950 matrix cores' own.
  * Requirements (else SK_ERR_UNSUPPORTED): A row-major and B column-major,
- * K a multiple of 128, A and B 16-byte aligned with lda, ldb multiples of
- * 16.  scale_a/scale_b 4-byte aligned, ld_scale_a/ld_scale_b multiples of 4
- * and >= K/32 (else SK_ERR_INVALID_ARG).  Grouped launches:
- * sk_grouped_prepare_mx; sk_gemm with SK_MXF8E4M3 returns
+ * K a multiple of 128 (MXFP4: 256), A and B 16-byte aligned with rows of a
+ * multiple of 16 bytes (lda, ldb multiples of 16; MXFP4: 32).
+ * scale_a/scale_b 4-byte aligned, ld_scale_a/ld_scale_b multiples of 4 and
+ * >= K/32 (else SK_ERR_INVALID_ARG).  Grouped launches:
+ * sk_grouped_prepare_mx; sk_gemm with an MX type returns
  * SK_ERR_INVALID_ARG. */
 sk_status sk_gemm_mx(const sk_problem* p, const void* A, const void* B,
                      const void* scale_a, int64_t ld_scale_a, const void* scale_b,
@@ -435,14 +442,15 @@ sk_status sk_grouped_prepare(const sk_problem* probs, const void* const* A,
                              size_t desc_bytes, sk_grouped_plan* plan,
                              void* hip_stream);
 
-/* sk_grouped_prepare for MXFP8 problems (dtype_ab = SK_MXF8E4M3 in every
- * problem; beyond the report: OCP MX block scaling, as sk_gemm_mx):
+/* sk_grouped_prepare for MX problems (dtype_ab = SK_MXF8E4M3 or
+ * SK_MXF4E2M1 in every problem; beyond the report: OCP MX block scaling, as
+ * sk_gemm_mx):
  * scale_a[i] / scale_b[i] are problem i's E8M0 scales (rows of A, columns
  * of B, one byte per 32 K-values, ld_scale_a[i] / ld_scale_b[i] bytes
  * apart), with sk_gemm_mx's requirements per problem (K-contiguous
- * operands, K a multiple of 128, 16-byte aligned operands and leading
- * dimensions, 4-byte aligned scale rows of at least K/32 bytes).
- * sk_grouped_prepare with SK_MXF8E4M3 problems returns SK_ERR_INVALID_ARG.
+ * operands, whole iterations, 16-byte aligned operands and rows, 4-byte
+ * aligned scale rows of at least K/32 bytes).  sk_grouped_prepare with MX
+ * problems returns SK_ERR_INVALID_ARG.
  * The plan launches with sk_gemm_grouped. */
 sk_status sk_grouped_prepare_mx(const sk_problem* probs, const void* const* A,
                                 const void* const* B, const void* const* scale_a,

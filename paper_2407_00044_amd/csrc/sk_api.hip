@@ -108,7 +108,7 @@ static sk_status resident_per_cu(const KernelEntry* ke, int* per_cu) {
 static sk_status check_problem(const sk_problem& p) {
   if (p.M < 0 || p.N < 0 || p.K < 0) return SK_ERR_INVALID_ARG;
   if (p.M > kMaxIndex || p.N > kMaxIndex || p.K > kMaxIndex) return SK_ERR_UNSUPPORTED;
-  if (p.dtype_ab < 0 || p.dtype_ab > 4) return SK_ERR_UNSUPPORTED;
+  if (p.dtype_ab < 0 || p.dtype_ab > 5) return SK_ERR_UNSUPPORTED;
   if (p.dtype_c < 0 || p.dtype_c > 2) return SK_ERR_UNSUPPORTED;
   if ((p.layout_a != SK_ROW_MAJOR && p.layout_a != SK_COL_MAJOR) ||
       (p.layout_b != SK_ROW_MAJOR && p.layout_b != SK_COL_MAJOR))
@@ -149,14 +149,15 @@ static sk_status resolve_config(const sk_config* cfg, int32_t dtype_ab, int64_t*
 // from the tile's first element (buffer instructions); every offset a tile
 // can form must stay below 2^31.
 static bool offsets_fit(const sk_problem& p, int64_t bm, int64_t bn) {
-  const int64_t eb = elem_bytes(p.dtype_ab), ec = p.dtype_c == SK_F32 ? 4 : 2;
+  const int64_t ec = p.dtype_c == SK_F32 ? 4 : 2;
   const int64_t rm = std::min<int64_t>(std::max<int64_t>(p.M, 1), bm);
   const int64_t rn = std::min<int64_t>(std::max<int64_t>(p.N, 1), bn);
   const int64_t k = std::max<int64_t>(p.K, 1);
-  const int64_t span_a = p.layout_a == SK_ROW_MAJOR ? ((rm - 1) * p.lda + k) * eb
-                                                    : ((k - 1) * p.lda + bm) * eb;
-  const int64_t span_b = p.layout_b == SK_COL_MAJOR ? ((rn - 1) * p.ldb + k) * eb
-                                                    : ((k - 1) * p.ldb + bn) * eb;
+  auto bytes = [&](int64_t n) { return elems_to_bytes(p.dtype_ab, n + (p.dtype_ab == 5 ? 1 : 0)); };
+  const int64_t span_a = p.layout_a == SK_ROW_MAJOR ? bytes((rm - 1) * p.lda + k)
+                                                    : bytes((k - 1) * p.lda + bm);
+  const int64_t span_b = p.layout_b == SK_COL_MAJOR ? bytes((rn - 1) * p.ldb + k)
+                                                    : bytes((k - 1) * p.ldb + bn);
   const int64_t span_c = ((rm - 1) * p.ldc + bn) * ec;
   return span_a <= kMaxIndex && span_b <= kMaxIndex && span_c <= kMaxIndex;
 }
@@ -294,6 +295,12 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
     d.tile_start = T;
     T += (int64_t)d.tm * d.tn;
     P.max_iters = std::max<int64_t>(P.max_iters, d.I);
+    if (p.dtype_ab == SK_MXF4E2M1) {
+      // the kernels see MXFP4 operands as bytes of two elements
+      d.K = elems_to_bytes(p.dtype_ab, d.K);
+      d.lda = elems_to_bytes(p.dtype_ab, d.lda);
+      d.ldb = elems_to_bytes(p.dtype_ab, d.ldb);
+    }
   }
   if (T > kMaxIndex) return SK_ERR_UNSUPPORTED;
   P.T = T;
@@ -564,10 +571,13 @@ struct MxScales {
 // for K-contiguous operands, whole 128-element iterations and 16-byte loads,
 // and read the scales as 4-byte words, 4 per iteration.
 static sk_status check_mx(const sk_problem& p, const void* A, const void* B, const MxScales& mx) {
-  if (p.layout_a != SK_ROW_MAJOR || p.layout_b != SK_COL_MAJOR || p.K % 128 != 0)
+  if (p.layout_a != SK_ROW_MAJOR || p.layout_b != SK_COL_MAJOR ||
+      p.K % k_per_iter(p.dtype_ab) != 0)
     return SK_ERR_UNSUPPORTED;
   if (p.M == 0 || p.N == 0 || p.K == 0) return SK_OK;
-  if (!aligned16(A) || !aligned16(B) || p.lda % 16 != 0 || p.ldb % 16 != 0)
+  // rows of a multiple of 16 bytes (MXFP4: 32 elements)
+  const int64_t row_align = p.dtype_ab == SK_MXF4E2M1 ? 32 : 16;
+  if (!aligned16(A) || !aligned16(B) || p.lda % row_align != 0 || p.ldb % row_align != 0)
     return SK_ERR_UNSUPPORTED;
   if (mx.sA == nullptr || mx.sB == nullptr || ((uintptr_t)mx.sA & 3) != 0 ||
       ((uintptr_t)mx.sB & 3) != 0 || mx.ldsa % 4 != 0 || mx.ldsb % 4 != 0 ||
@@ -582,8 +592,9 @@ static sk_status gemm_common(const sk_problem* p, const void* A, const void* B, 
                              void* Cout, void* ws, size_t ws_bytes_, const sk_config* cfg,
                              const sk_debug* dbg, void* stream, const MxScales* mx = nullptr) {
   if (p == nullptr) return SK_ERR_INVALID_ARG;
-  // MXFP8 inputs need their block scales (sk_gemm_mx); others take none
-  if ((p->dtype_ab == SK_MXF8E4M3) != (mx != nullptr)) return SK_ERR_INVALID_ARG;
+  // MX inputs need their block scales (sk_gemm_mx); others take none
+  const bool is_mx = p->dtype_ab == SK_MXF8E4M3 || p->dtype_ab == SK_MXF4E2M1;
+  if (is_mx != (mx != nullptr)) return SK_ERR_INVALID_ARG;
   Plan P;
   sk_status st = plan_problems(p, 1, cfg, &P);
   if (st != SK_OK) return st;
@@ -601,8 +612,8 @@ static sk_status gemm_common(const sk_problem* p, const void* A, const void* B, 
     d.sA = mx->sA; d.sB = mx->sB;
     d.ldsa = mx->ldsa; d.ldsb = mx->ldsb;
   }
-  const int eb = elem_bytes(p->dtype_ab);
-  d.aligned = aligned16(A) && aligned16(B) && (p->lda * eb) % 16 == 0 && (p->ldb * eb) % 16 == 0;
+  d.aligned = aligned16(A) && aligned16(B) && elems_to_bytes(p->dtype_ab, p->lda) % 16 == 0 &&
+              elems_to_bytes(p->dtype_ab, p->ldb) % 16 == 0;
   return launch(P, cfg, p->dtype_ab, p->layout_a, p->layout_b, p->dtype_c, &d, nullptr, 1, ws,
                 ws_bytes_, dbg, (hipStream_t)stream);
 }
@@ -855,12 +866,12 @@ static sk_status grouped_prepare(const sk_problem* probs, const void* const* A,
   Plan P;
   sk_status st = plan_problems(probs, nprobs, cfg, &P);
   if (st != SK_OK) return st;
-  // MXFP8 problems need their block scales (sk_grouped_prepare_mx); others take none
-  const bool mx = probs[0].dtype_ab == SK_MXF8E4M3;
+  // MX problems need their block scales (sk_grouped_prepare_mx); others take none
+  const bool mx = probs[0].dtype_ab == SK_MXF8E4M3 || probs[0].dtype_ab == SK_MXF4E2M1;
   if (mx != (sA != nullptr && ldsa != nullptr && sB != nullptr && ldsb != nullptr))
     return SK_ERR_INVALID_ARG;
   if (desc_bytes < (size_t)nprobs * sizeof(ProbDesc)) return SK_ERR_WORKSPACE;
-  const int eb = elem_bytes(probs[0].dtype_ab);
+  const int32_t dt = probs[0].dtype_ab;
   int32_t all_aligned = 1;
   for (int32_t i = 0; i < nprobs; ++i) {
     const int32_t j = P.order[i];
@@ -881,8 +892,8 @@ static sk_status grouped_prepare(const sk_problem* probs, const void* const* A,
       d.sA = m.sA; d.sB = m.sB;
       d.ldsa = m.ldsa; d.ldsb = m.ldsb;
     }
-    d.aligned = aligned16(d.A) && aligned16(d.B) && (p.lda * eb) % 16 == 0 &&
-                (p.ldb * eb) % 16 == 0;
+    d.aligned = aligned16(d.A) && aligned16(d.B) && elems_to_bytes(dt, p.lda) % 16 == 0 &&
+                elems_to_bytes(dt, p.ldb) % 16 == 0;
     all_aligned &= d.aligned;
   }
   if (hipMemcpyAsync(dev_desc, P.descs.data(), (size_t)nprobs * sizeof(ProbDesc),

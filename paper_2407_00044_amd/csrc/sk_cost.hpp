@@ -20,8 +20,8 @@
 // tiles takes ceil(T / CUs) waves of one tile each.
 //
 // The constants are measured on MI355X per input type and tile by
-// paper_2407_00044_amd/calibrate.py (f16 uses the bf16 rows and MXFP8 the
-// e4m3 rows: same kernels, same rate).  They are policy: no result depends on them, only which
+// paper_2407_00044_amd/calibrate.py (f16 uses the bf16 rows, MXFP8 the e4m3
+// rows and MXFP4 the bf16 rows: the same data path per iteration).  They are policy: no result depends on them, only which
 // launch the auto mode picks.
 #pragma once
 
@@ -61,7 +61,8 @@ inline double auto_margin(int32_t dt) { return dt == 0 ? kAutoMarginF32 : kAutoM
 // Row of (input type, tile); f16 takes bf16's.  A tile without a row takes
 // the row of the same type whose tile area is closest.
 inline const CostRow* cost_row(int32_t dt, int32_t bm, int32_t bn) {
-  const int32_t d = dt == 1 ? 2 : dt == 4 ? 3 : dt;   // f16 as bf16, MXFP8 as e4m3
+  // f16 and MXFP4 (four 16-byte steps per iteration) as bf16, MXFP8 as e4m3
+  const int32_t d = (dt == 1 || dt == 5) ? 2 : dt == 4 ? 3 : dt;
   const CostRow* best = nullptr;
   int64_t best_gap = 0;
   for (const CostRow& r : kCostTable) {

@@ -48,11 +48,15 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef int v2i __attribute__((ext_vector_type(2)));
 
-enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3, DT_MX8 = 4 };
+enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3, DT_MX8 = 4, DT_MX4 = 5 };
 // 8-bit e4m3 elements: plain (per-tensor scales, applied in the epilogue) or
 // MXFP8 (an E8M0 scale per 32 K-values of each row of A and column of B,
 // applied by the matrix core)
 constexpr bool is_f8(int dt) { return dt == DT_F8 || dt == DT_MX8; }
+// MXFP4: E2M1 elements packed two per byte, with MXFP8's block scales.  The
+// kernels see its operands as bytes (K, lda, ldb in bytes, 256 elements per
+// 128-byte iteration).
+constexpr bool is_mx(int dt) { return dt == DT_MX8 || dt == DT_MX4; }
 enum { L_ROW = 0, L_COL = 1 };
 enum { R_FULL = 0, R_FINISH = 1, R_PARTIAL = 2, R_DP = 3 };
 
@@ -662,6 +666,9 @@ struct Frag { u32x4 c[is_f8(DT) ? 2 : 1]; };
 // MXFP8: the lane's 32 K-values and the E8M0 scale of their block
 template <>
 struct Frag<DT_MX8> { u32x4 c[2]; int32_t s; };
+// MXFP4: the lane's 32 K-values (16 bytes) and the scale of their block
+template <>
+struct Frag<DT_MX4> { u32x4 c[1]; int32_t s; };
 
 // Per-lane LDS byte offset, inside a 32-row block, of the 16-byte piece
 // `chunk` of the lane's row (lane mod 32).  The swizzle repeats every 32
@@ -702,13 +709,19 @@ __device__ __forceinline__ void mma(v16f& acc, const Frag<DT>& a, const Frag<DT>
     v8i bv = __builtin_bit_cast(v8i, b.c);
     // operand format 0 (e4m3) for A and B; E8M0 scale 127 = 2^0
     acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, 127, 0, 127);
-  } else {
+  } else if constexpr (DT == DT_MX8) {
     // MXFP8: each lane's 32 K-values (one block of its row of A / column of
     // B) carry that block's E8M0 scale; the matrix core multiplies every
     // product by 2^(sa-127) * 2^(sb-127)
     v8i av = __builtin_bit_cast(v8i, a.c);
     v8i bv = __builtin_bit_cast(v8i, b.c);
     acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, a.s, 0, b.s);
+  } else {
+    // MXFP4 (operand format 4, e2m1): 16 bytes per lane, the lane's block
+    // of 32 K-values with its scale
+    const v8i av = {(int)a.c[0][0], (int)a.c[0][1], (int)a.c[0][2], (int)a.c[0][3], 0, 0, 0, 0};
+    const v8i bv = {(int)b.c[0][0], (int)b.c[0][1], (int)b.c[0][2], (int)b.c[0][3], 0, 0, 0, 0};
+    acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 4, 4, 0, a.s, 0, b.s);
   }
 }
 
@@ -717,19 +730,22 @@ template <int DT_, int LA_, int LB_, int BM_, int BN_, int WGM_, int NW_>
 struct Cfg {
   static constexpr int DT = DT_, LA = LA_, LB = LB_, BM = BM_, BN = BN_, WGM = WGM_;
   static constexpr int NW = NW_, NT = 64 * NW_;     // waves, threads per workgroup
-  static constexpr int EB = DT == DT_F32 ? 4 : is_f8(DT) ? 1 : 2;
-  static constexpr bool MX = DT == DT_MX8;           // E8M0 block scales in the stage
+  static constexpr int EB = DT == DT_F32 ? 4 : (is_f8(DT) || DT == DT_MX4) ? 1 : 2;
+  static constexpr bool MX = is_mx(DT);              // E8M0 block scales in the stage
+  static constexpr int SB = DT == DT_MX4 ? 8 : 4;    // MX: scale bytes per row and iteration
   static constexpr int KE = 128 / EB;                // K elements per iteration
   static constexpr int WGN = NW / WGM;
   static constexpr int WM = BM / WGM, WN = BN / WGN; // per-wave tile
   static constexpr int FM = WM / 32, FN = WN / 32;   // 32x32 blocks per wave
   static constexpr int STEPS = is_f8(DT) ? 2 : 4;   // matrix-core steps per iteration
   static constexpr int BOFF = BM * 128;              // B tile offset in a stage
-  // MXFP8: after the tiles, 4 scale bytes (the iteration's 4 blocks) per
-  // row of A then per column of B, one 256-byte block per wave
+  // MX: after the tiles, SB scale bytes (the iteration's SB blocks of 32
+  // K-values) per row of A then per column of B, copied in 256-byte blocks,
+  // SNI per wave
   static constexpr int SCL_A = (BM + BN) * 128;
-  static constexpr int SCL_B = SCL_A + 4 * BM;
-  static constexpr int STAGE = (BM + BN) * 128 + (MX ? NW * 256 : 0);   // LDS bytes per stage
+  static constexpr int SCL_B = SCL_A + SB * BM;
+  static constexpr int SNI = MX ? ((BM + BN) * SB + NW * 256 - 1) / (NW * 256) : 0;
+  static constexpr int STAGE = (BM + BN) * 128 + SNI * NW * 256;   // LDS bytes per stage
   // M/N-contiguous 16-bit operands are read with transposing LDS reads
   // (e4m3: tiles of at least 128 rows)
   static constexpr bool TR16 = (DT == DT_F16 || DT == DT_BF16) && SK_MN_TR && SK_KMAJOR_DMA;
@@ -752,9 +768,9 @@ struct Cfg {
   // (two cost it 13-23%), and FP8 iterations have two steps only
   static constexpr int RING_LA = (TRA || TRB) ? 2 : (STEPS == 4 && BM * BN < 256 * 256) ? 3 : 1;
   // LDS-direct copies issued per wave for one iteration
-  static constexpr int NLOADS = (BM + BN) / (NT / 8) + (MX ? 1 : 0);
-  static_assert(!MX || (LA == L_ROW && LB == L_COL && (BM + BN) * 4 <= NW * 256),
-                "MXFP8: K-contiguous operands, scale rows fit one block per wave");
+  static constexpr int NLOADS = (BM + BN) / (NT / 8) + SNI;
+  static_assert(!MX || (LA == L_ROW && LB == L_COL && (BM * SB) % 256 == 0),
+                "MX: K-contiguous operands, A's scale rows end on a 256-byte block");
   // LDS read instructions per matrix-core step
   static constexpr int RD_K = is_f8(DT) ? 2 : 1;    // K-contiguous fragment
   static constexpr int RD_T = is_f8(DT) ? 4 : 2;    // transposed fragment
@@ -768,44 +784,60 @@ struct Cfg {
 template <typename C>
 struct Acc { v16f a[C::FM][C::FN]; };
 
-// MXFP8 block scales of one tile into the stage: the 4 scale bytes of an
-// iteration (its 4 blocks of 32 K-values) for each row of A, then for each
-// column of B, one 4-byte LDS-direct copy per lane.  Wave w copies rows
-// 64w .. 64w+63 of [rows of A | columns of B] into its own 256-byte block of
-// the stage; a wave past them copies zeros (out-of-range offsets) into its
-// block, so every wave issues the same number of copies per stage.  Rows
-// past M or N read as zero scales (their elements are zero too).
+// MX block scales of one tile into the stage: the SB scale bytes of an
+// iteration (its SB blocks of 32 K-values: 4 for MXFP8, 8 for MXFP4) for
+// each row of A, then for each column of B, in 4-byte LDS-direct copies.
+// The stage holds them as [rows of A | columns of B] x SB bytes; copy j of
+// wave w fills bytes 256 (w + NW j) .. +255 of that (lane l: 4 bytes at
+// 256 (w + NW j) + 4l), so A's and B's rows never share a copy (BM * SB is
+// a multiple of 256).  A copy past the last row reads nothing (out-of-range
+// offset) and zeroes its bytes, so every wave issues the same number of
+// copies per stage.  Rows past M or N read as zero scales (their elements
+// are zero too).
 template <typename C>
 struct ScaleStage {
-  static constexpr int NI = C::MX ? 1 : 0;
-  uint32_t voff;
-  __amdgpu_buffer_rsrc_t prs;
+  static constexpr int NI = C::SNI;
+  uint32_t voff[NI > 0 ? NI : 1];
+  __amdgpu_buffer_rsrc_t prs[NI > 0 ? NI : 1];
 
   __device__ __forceinline__ void prep(const ProbDesc& pd, int64_t m0, int64_t n0, int tid) {
     if constexpr (C::MX) {
       const int wave = uniform32(tid >> 6);
-      const int r = 64 * wave + (tid & 63);
-      if (64 * wave < C::BM) {
-        prs = make_rsrc((const char*)pd.sA + m0 * pd.ldsa, (pd.M - m0) * pd.ldsa);
-        voff = (uint32_t)r * (uint32_t)pd.ldsa;
-      } else if (64 * wave < C::BM + C::BN) {
-        prs = make_rsrc((const char*)pd.sB + n0 * pd.ldsb, (pd.N - n0) * pd.ldsb);
-        voff = (uint32_t)(r - C::BM) * (uint32_t)pd.ldsb;
-      } else {
-        prs = make_rsrc((const char*)pd.sA, 0);
-        voff = kOOB;
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        const int blk = wave + C::NW * j;              // 256-byte block of the stage
+        const int f = 256 * blk + 4 * (tid & 63);      // this lane's byte
+        const int r = f / C::SB, part = (f % C::SB) / 4;
+        if (256 * blk < C::SB * C::BM) {
+          prs[j] = make_rsrc((const char*)pd.sA + m0 * pd.ldsa, (pd.M - m0) * pd.ldsa);
+          voff[j] = (uint32_t)r * (uint32_t)pd.ldsa + 4 * part;
+        } else if (256 * blk < C::SB * (C::BM + C::BN)) {
+          prs[j] = make_rsrc((const char*)pd.sB + n0 * pd.ldsb, (pd.N - n0) * pd.ldsb);
+          voff[j] = (uint32_t)(r - C::BM) * (uint32_t)pd.ldsb + 4 * part;
+        } else {
+          prs[j] = make_rsrc((const char*)pd.sA, 0);
+          voff[j] = kOOB;
+        }
       }
     }
   }
 
-  // Iteration k's scale bytes into the stage at L (on == false: zeros).
-  __device__ __forceinline__ void issue(char* L, int64_t k, int tid, bool on) const {
+  // Copy j of iteration k's scale bytes into the stage at L (on == false:
+  // zeros).
+  __device__ __forceinline__ void issue_one(char* L, int64_t k, int tid, bool on, int j) const {
     if constexpr (C::MX) {
       const int wave = uniform32(tid >> 6);
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          prs, (__attribute__((address_space(3))) void*)(L + C::SCL_A + 256 * wave), 4,
-          (int)(on ? voff : kOOB), uniform32((int32_t)(4 * k)), 0, 0);
+          prs[j],
+          (__attribute__((address_space(3))) void*)(L + C::SCL_A + 256 * (wave + C::NW * j)), 4,
+          (int)(on ? voff[j] : kOOB), uniform32((int32_t)(C::SB * k)), 0, 0);
     }
+  }
+
+  // All of iteration k's scale bytes.
+  __device__ __forceinline__ void issue(char* L, int64_t k, int tid, bool on) const {
+#pragma unroll
+    for (int j = 0; j < NI; ++j) issue_one(L, k, tid, on, j);
   }
 };
 
@@ -859,12 +891,12 @@ struct FragReader {
   static constexpr int PITCH = R * C::EB;    // bytes per k-row (TR stage)
   int off[NB];
   int l32, half;
-  int sb;                                    // MXFP8: the 4 scale bytes of this lane's row (block 0)
+  int sb;                                    // MX: the SB scale bytes of this lane's row (block 0)
 
   __device__ __forceinline__ void init(int rowbase, int lane) {
     l32 = lane & 31;
     half = lane >> 5;
-    if constexpr (C::MX) sb = SREL + 4 * (rowbase + l32);
+    if constexpr (C::MX) sb = SREL + C::SB * (rowbase + l32);
     if constexpr (TR && C::EB == 2) {
       static_assert(C::STEPS == 4, "16 k-values per step");
       const int p = lane & 15, g = lane >> 4, j = p >> 2, q = p & 3;
@@ -907,7 +939,7 @@ struct FragReader {
       f.c[0] = u32x4{lo[0], lo[1], hi[0], hi[1]};
     } else {
       int lo[2];
-      if constexpr (C::MX) {
+      if constexpr (C::DT == DT_MX8) {
         lo[0] = frag_lane_off(l32, 4 * s + half);
         lo[1] = frag_lane_off(l32, 4 * s + 2 + half);
       } else if constexpr (is_f8(C::DT)) {
@@ -923,8 +955,16 @@ struct FragReader {
       // bytes once, shifted to this lane's half; step 1 takes them from step
       // 0.s fragment (in step_fenced), so each iteration reads the scales
       // of a fragment with one LDS instruction instead of two.
-      if constexpr (C::MX)
+      if constexpr (C::DT == DT_MX8)
         f.s = (s & 1) ? 0 : (int32_t)(*(const uint32_t*)(op + sb + 128 * i) >> (8 * half));
+      // MXFP4: step s covers K bytes 32s .. 32s+31 of the row, lane half h
+      // the 16-byte block 2s + h of them (the scaled matrix core takes a
+      // lane half's 32 values as one block, with that half's scale: checked
+      // on the device with an all-ones operand and one lane's scale doubled),
+      // whose scale is byte 2s + h of the row's 8
+      if constexpr (C::DT == DT_MX4)
+        f.s = (int32_t)(*(const uint32_t*)(op + sb + 256 * i + 4 * (s >> 1)) >>
+                        (8 * (2 * (s & 1) + half)));
     }
     return f;
   }
@@ -1107,7 +1147,7 @@ __device__ __forceinline__ void step_fenced(
       read_frag_n<C>(ra, rb, rda, rdb, opA, opB, rs, n);
       // MXFP8, step 1 read during step 0 of the same iteration: its scale
       // is byte 2 of step 0's (bytes 2s + half of the row's 4)
-      if constexpr (C::MX) {
+      if constexpr (C::DT == DT_MX8) {
         if (rs & 1) {
           if (n < 1) ra[0].s = fa[0].s >> 16;
           else if (n <= C::FN) rb[n - 1].s = fb[n - 1].s >> 16;
@@ -1119,7 +1159,7 @@ __device__ __forceinline__ void step_fenced(
     for (int c = CB + t * NCP / NM; c < CB + (t + 1) * NCP / NM; ++c) {
       if (c < NA) sa.issue_one(dst, kba, tid, on, c);
       else if (c < NA + C::StageB::NI) sb.issue_one(dst + C::BOFF, kbb, tid, on, c - NA);
-      else ss.issue(dst, k0 / C::KE, tid, on);
+      else ss.issue_one(dst, k0 / C::KE, tid, on, c - NA - C::StageB::NI);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -1364,8 +1404,9 @@ __device__ __forceinline__ void mac_loop(Acc<C>& acc, const ProbDesc& pd, int64_
   if constexpr (C::RING)
     if (kf > kb && !C::StageA::whole(oa, (int64_t)(kf - 1) * C::KE)) --kf;
   if constexpr (C::MX) {
-    // MXFP8 launches are K-contiguous, 16-byte aligned and K a multiple of
-    // 128 (checked on the host): every iteration is whole and fast
+    // MX launches are K-contiguous, 16-byte aligned and whole iterations
+    // (K a multiple of 128 MXFP8 / 256 MXFP4 elements; checked on the
+    // host): every iteration is whole and fast
     ScaleStage<C> ss;
     ss.prep(pd, m0, n0, tid);
     if (ke > kb) mac_loop_ring<C>(acc, oa, ob, ss, kb, ke, lds, tid, cover_row);

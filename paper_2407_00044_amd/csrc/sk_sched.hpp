@@ -92,13 +92,21 @@ SK_HD int64_t logical_id(int64_t b, int64_t g, int32_t xcd_remap, int32_t revers
   return b;
 }
 
-// Elements of K per MAC iteration: 128 bytes of K for every input type.
+// Elements of K per MAC iteration: 128 bytes of K for every input type
+// (MXFP4: 256 elements of half a byte).
 SK_HD int32_t k_per_iter(int32_t dtype_ab) {
-  return dtype_ab == 0 ? 32 : dtype_ab >= 3 ? 128 : 64;
+  return dtype_ab == 0 ? 32 : dtype_ab == 5 ? 256 : dtype_ab >= 3 ? 128 : 64;
 }
 
+// Bytes per element of the kernels' view of an operand (MXFP4 operands are
+// seen as bytes of two elements).
 SK_HD int32_t elem_bytes(int32_t dtype) {
   return dtype == 0 ? 4 : dtype >= 3 ? 1 : 2;
+}
+
+// Bytes of n elements (n even for MXFP4).
+SK_HD int64_t elems_to_bytes(int32_t dtype, int64_t n) {
+  return dtype == 5 ? n / 2 : n * elem_bytes(dtype);
 }
 
 }  // namespace sk

@@ -254,6 +254,33 @@ def mxfp8(dev, reps=5, shape=(3840, 4096, 4096), tile=(256, 128)):
     return res
 
 
+def mxfp4(dev, reps=5, shape=(3840, 4096, 4096), tile=(256, 128)):
+    """MXFP4 (E2M1 elements two per byte, an E8M0 scale per 32 K-values,
+    applied by the matrix cores) at the headline shape on the same tile as
+    the MXFP8 leg: Stream-K (two-tile hybrid), the auto policy and the
+    data-parallel grid; % of the dense FP4 MFMA peak (10.1 PFLOP/s)."""
+    M, N, K = shape
+    ws = api.Workspace(dev)
+    ws.get(96 << 20, torch.cuda.current_stream().cuda_stream)
+    pa, sa = synth.mx4_quantize(synth.normal((M, K), 63))
+    pb, sb = synth.mx4_quantize(synth.normal((N, K), 64))
+    A, B = torch.from_numpy(pa).to(dev), torch.from_numpy(pb).to(dev).t()
+    SA, SB = torch.from_numpy(sa).to(dev), torch.from_numpy(sb).to(dev)
+    out = torch.empty((M, N), device=dev)
+    fl = 2.0 * M * N * K
+    cfgs = {"stream_k": api.Config(tile=tile, mode="hybrid"),
+            "auto": api.Config(tile=tile, mode="auto"),
+            "dp": api.Config(tile=tile, mode="dp")}
+    fns = [(lambda c: (lambda: api.gemm_mx4(A, B, SA, SB, out=out, config=c, workspace=ws)))(c)
+           for c in cfgs.values()]
+    ts = _time_all(fns, reps)
+    res = {"workload": f"{M}x{N}x{K}, A row-major, B column-major, FP32 output, tile "
+                       f"{tile[0]}x{tile[1]}"}
+    for n, t in zip(cfgs, ts):
+        res[n] = {"tflops": _tf(fl, t), "pct_peak": round(100 * fl / t / 1e9 / 10066.3, 2)}
+    return res
+
+
 def epilogue(dev, reps=5, shape=(3840, 4096, 4096), tile=(256, 256)):
     """Cost of the fused epilogue (bias per column, then ReLU / GELU / SiLU)
     on BF16 at the headline shape, auto policy: the plain GEMM, each fused
@@ -380,7 +407,8 @@ def run_all(dev, extra=False, only=None, c5_tile=None):
     c5_tile runs c5 in auto mode on that tile instead of the tuner's pick."""
     out = {}
     todo = [("c1", c1), ("c3", c3), ("c4", c4), ("c5", lambda d: c5(d, tile=c5_tile)),
-            ("per_dtype", per_dtype), ("mxfp8", mxfp8), ("epilogue", epilogue)]
+            ("per_dtype", per_dtype), ("mxfp8", mxfp8), ("mxfp4", mxfp4),
+            ("epilogue", epilogue)]
     if extra or only:
         todo += [("padding", padding), ("compute_units", compute_units),
                  ("hybrid_variants", hybrid_variants)]

@@ -305,3 +305,29 @@ def test_grouped_mx_host_checks():
     assert lib.sk_grouped_prepare_mx(probs, ptr(fake), ptr(fake), ptr(fake), lds(16), ptr(fake),
                                      lds(16), None, ptr(fake), n, ctypes.byref(cfg8), desc,
                                      dbytes, ctypes.byref(plan), None) == _abi.SK_ERR_INVALID_ARG
+
+
+def test_mx4_entry_point_host_checks():
+    # MXFP4 through sk_gemm_mx: whole 256-element iterations and rows of a
+    # multiple of 16 bytes (32 elements), else unsupported (nothing launched)
+    lib = _abi.load()
+    cfg = sk.Config(tile=(128, 128), num_cu=8).c_struct(_abi.SK_MXF4E2M1)
+    assert cfg.block_k == 256
+    fake = ctypes.c_void_p(1 << 20)
+
+    def call(M, N, K, lda=None, ldb=None, lds=16):
+        p = _abi.SkProblem(M, N, K, _abi.SK_ROW_MAJOR, _abi.SK_COL_MAJOR, lda or K, ldb or K, N,
+                           _abi.SK_MXF4E2M1, _abi.SK_F32, 1.0, 0.0, 1.0, 1.0)
+        return lib.sk_gemm_mx(ctypes.byref(p), fake, fake, fake, lds, fake, lds, None, fake,
+                              None, 0, ctypes.byref(cfg), None)
+    assert call(256, 256, 384) == _abi.SK_ERR_UNSUPPORTED          # K % 256
+    assert call(256, 256, 512, lda=528) == _abi.SK_ERR_UNSUPPORTED   # 264-byte rows
+    assert call(256, 256, 512, ldb=520) == _abi.SK_ERR_UNSUPPORTED
+    assert call(256, 256, 512, lds=8) == _abi.SK_ERR_INVALID_ARG     # < K/32 scale bytes
+    assert sk.supported_tiles(_abi.SK_MXF4E2M1) == [(128, 128, 256), (256, 128, 256)]
+    # the planner counts K in elements: 512 / 256 = 2 iterations per tile
+    p = _abi.SkProblem(256, 256, 512, _abi.SK_ROW_MAJOR, _abi.SK_COL_MAJOR, 512, 512, 256,
+                       _abi.SK_MXF4E2M1, _abi.SK_F32, 1.0, 0.0, 1.0, 1.0)
+    info = _abi.SkPlanInfo()
+    assert lib.sk_plan(ctypes.byref(p), 1, ctypes.byref(cfg), ctypes.byref(info)) == 0
+    assert info.T == 4 and info.max_iters == 2
