@@ -268,6 +268,23 @@ def _fp4_bytes(t):
     return t
 
 
+def _mx4_problem(A, B, out, alpha, beta):
+    """sk_problem of an MXFP4 product: A (M x K/2 bytes, row-major), B (K/2 x
+    N bytes, column-major), out row-major M x N; sizes in elements."""
+    A, B = _fp4_bytes(A), _fp4_bytes(B)
+    if (A.numel() and A.stride(1) != 1) or (B.numel() and B.stride(0) != 1):
+        raise ValueError("MXFP4: A row-major and B column-major")
+    M, K, N = A.shape[0], 2 * A.shape[1], B.shape[1]
+    if B.shape[0] * 2 != K or tuple(out.shape) != (M, N):
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)} (bytes), "
+                         f"out {tuple(out.shape)}")
+    if out.dtype not in OUT_CODES or (out.stride(1) != 1 and N > 1):
+        raise ValueError("out must be a row-major float32/float16/bfloat16 tensor")
+    return SkProblem(M, N, K, SK_ROW_MAJOR, SK_COL_MAJOR, max(2 * A.stride(0), K, 1),
+                     max(2 * B.stride(1), K, 1), max(out.stride(0), N, 1), _abi.SK_MXF4E2M1,
+                     OUT_CODES[out.dtype], alpha, beta, 1.0, 1.0)
+
+
 def gemm_mx4(A, B, scale_a, scale_b, C=None, *, alpha=1.0, beta=0.0, out=None,
              out_dtype=torch.float32, bias=None, activation="none", config=None,
              workspace=None, stream=None):
@@ -292,14 +309,9 @@ def gemm_mx4(A, B, scale_a, scale_b, C=None, *, alpha=1.0, beta=0.0, out=None,
             (M, N), dtype=out_dtype, device=A.device)
     if beta != 0.0 and C is None:
         raise ValueError("beta != 0 needs C")
-    if tuple(out.shape) != (M, N) or out.dtype not in OUT_CODES or (out.stride(1) != 1 and N > 1):
-        raise ValueError("out must be a row-major M x N float32/float16/bfloat16 tensor")
     if scale_a.shape[0] != M or scale_b.shape[0] != N:
         raise ValueError("one scale row per row of A and per column of B")
-    p = SkProblem(M, N, K, SK_ROW_MAJOR, SK_COL_MAJOR, max(2 * A.stride(0), K, 1),
-                  max(2 * B.stride(1), K, 1), max(out.stride(0), N, 1), _abi.SK_MXF4E2M1,
-                  OUT_CODES[out.dtype], alpha, beta, 1.0, 1.0)
-    _set_epilogue(p, bias, activation, A.device)
+    p = _set_epilogue(_mx4_problem(A, B, out, alpha, beta), bias, activation, A.device)
     if config is None:
         # the bf16 rule (the same four 16-byte steps per iteration) on the
         # MXFP4 menu: 256x128 and 128x128
@@ -529,9 +541,10 @@ class GroupedGemm:
     workspace are set up once here (not capturable); run() only launches and
     can be captured into a HIP graph (torch.cuda.CUDAGraph).  biases: per
     problem a float32 vector of N values or None, added before the activation
-    (one for every problem) in the fused epilogue.  mx_scales: MXFP8
-    problems (A, B torch.float8_e4m3fn codes, A row-major, B column-major),
-    per problem (scale_a, scale_b) as for gemm_mx."""
+    (one for every problem) in the fused epilogue.  mx_scales: MX problems
+    (A, B torch.float8_e4m3fn codes for MXFP8, or packed FP4 bytes as for
+    gemm_mx4 for MXFP4; A row-major, B column-major), per problem
+    (scale_a, scale_b) as for gemm_mx."""
 
     def __init__(self, problems, config=None, alpha=1.0, scales=None, stream=None,
                  biases=None, activation="none", mx_scales=None):
@@ -553,10 +566,12 @@ class GroupedGemm:
             Cin = pr[3] if len(pr) > 3 else None
             beta = pr[4] if len(pr) > 4 else 0.0
             sa, sb = scales[i] if scales is not None else (1.0, 1.0)
-            probs[i] = _set_epilogue(_problem(A, B, out, alpha, beta, sa, sb, prefer),
-                                     biases[i] if biases is not None else None, activation,
+            fp4 = mx_scales is not None and A.dtype in (torch.uint8, torch.float4_e2m1fn_x2)
+            base = (_mx4_problem(A, B, out, alpha, beta) if fp4 else
+                    _problem(A, B, out, alpha, beta, sa, sb, prefer))
+            probs[i] = _set_epilogue(base, biases[i] if biases is not None else None, activation,
                                      A.device)
-            if mx_scales is not None:
+            if mx_scales is not None and not fp4:
                 probs[i].dtype_ab = _abi.SK_MXF8E4M3
             ptrs["A"][i] = A.data_ptr()
             ptrs["B"][i] = B.data_ptr()
@@ -565,9 +580,10 @@ class GroupedGemm:
         dev = problems[0][0].device
         M0, N0, K0 = probs[0].M, probs[0].N, probs[0].K
         if config is None:
-            tile = default_tile(M0, N0, K0, problems[0][0].dtype)
+            dt0 = torch.bfloat16 if probs[0].dtype_ab == _abi.SK_MXF4E2M1 else problems[0][0].dtype
+            tile = default_tile(M0, N0, K0, dt0)
             if mx_scales is not None and tile not in ((256, 128), (128, 128)):
-                tile = (128, 128)         # the MXFP8 tile menu
+                tile = (256, 128) if tile[0] == 256 else (128, 128)   # the MX tile menu
             config = Config(tile=tile)
         self.config = config
         c = self.config.c_struct(probs[0].dtype_ab)

@@ -101,3 +101,38 @@ def test_mx4_fused_epilogue():
     torch.cuda.synchronize()
     expect = og.epilogue(ref(), bias.cpu().numpy().astype(np.float64), "gelu")
     assert rel_err(as64(out), expect) <= 1e-4
+
+
+GROUP = [(300, 260, 512), (64, 1000, 1024), (1000, 129, 256), (1, 64, 256), (513, 700, 768)]
+
+
+@pytest.mark.parametrize("tile", [(128, 128), (256, 128)])
+@pytest.mark.parametrize("mode", ["sk", "hybrid", "auto"])
+def test_mx4_grouped_parity_and_replays(tile, mode):
+    print(f"case mx4 grouped {tile} {mode}", flush=True)
+    probs, scales, refs = [], [], []
+    for i, (M, N, K) in enumerate(GROUP):
+        A, B, SA, SB, ref = mx4_inputs(M, N, K, 190 + 10 * i)
+        probs.append((A, B, torch.full((M, N), float("nan"), device=dev())))
+        scales.append((SA, SB))
+        refs.append(ref)
+    cfg = sk.Config(tile=tile, mode=mode, num_cu=23, min_iters=1 if mode == "sk" else 0)
+    gg = sk.GroupedGemm(probs, config=cfg, mx_scales=scales)
+    if mode != "auto":
+        assert gg.info()["S"] > 0
+    gg.run()
+    torch.cuda.synchronize()
+    assert sk.check_device_error(workspace=gg.workspace) == 0
+    first = []
+    for (A, B, out), ref in zip(probs, refs):
+        assert rel_err(as64(out), ref()) <= 1e-4, tuple(out.shape)
+        first.append(out.clone())
+    g = gg.capture()
+    for r in range(2):
+        for _, _, out in probs:
+            out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (_, _, out), f in zip(probs, first):
+            assert torch.equal(out, f), f"replay {r} differs"
