@@ -19,7 +19,9 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     cc = os.environ.get("CC", "gcc")
-    tmp = LIB + ".tmp"
+    # a per-process name: concurrent builds (parallel test workers) each
+    # write their own file and the last rename wins
+    tmp = "%s.%d.tmp" % (LIB, os.getpid())
     cmd = [cc, "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
            "-fPIC", "-shared", "-std=c11", SRC, "-o", tmp]
     if verbose:
