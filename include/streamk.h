@@ -101,7 +101,7 @@ typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
  *   SK_MODE_AUTO    SK_MODE_HYBRID, except that S = 0 (no tile is split)
  *                   unless the launch-time model (sk_cost_model) predicts
  *                   the launch without splits to be more than `margin`
- *                   times slower (1.08; FP32 inputs, whose kernels the
+ *                   times slower (1.07; FP32 inputs, whose kernels the
  *                   model fits more closely, 1.03); with nothing split on one problem
  *                   the launch is the data-parallel grid itself.  The
  *                   model's constants are measured on MI355X; not in the
