@@ -767,6 +767,11 @@ struct Cfg {
   // 128x128); the 256x256 tile, at the register limit, reads one step ahead
   // (two cost it 13-23%), and FP8 iterations have two steps only
   static constexpr int RING_LA = (TRA || TRB) ? 2 : (STEPS == 4 && BM * BN < 256 * 256) ? 3 : 1;
+  // e4m3 fragments read with transposing LDS reads on the 256x256 tile:
+  // two steps of fragments (96 registers) beside the 128 accumulator
+  // registers exceed the 256 a wave of two per SIMD has, so the two-stage
+  // loop reads each step's fragments just before its MFMAs
+  static constexpr bool FRAG_LOOKAHEAD = !(is_f8(DT) && (TRA || TRB) && FM * FN >= 8);
   // LDS-direct copies issued per wave for one iteration
   static constexpr int NLOADS = (BM + BN) / (NT / 8) + SNI;
   static_assert(!MX || (LA == L_ROW && LB == L_COL && (BM * SB) % 256 == 0),
@@ -1000,6 +1005,20 @@ __device__ __forceinline__ void compute_stage(Acc<C>& acc, const char* stage, in
   rb.init((wave % C::WGN) * C::WN, lane);
   const char* opA = stage;
   const char* opB = stage + C::BOFF;
+  if constexpr (!C::FRAG_LOOKAHEAD) {
+    // one set of fragment registers: each step's reads, then its MFMAs
+#pragma unroll
+    for (int s = 0; s < C::STEPS; ++s) {
+      Frag<C::DT> ga[C::FM], gb[C::FN];
+      read_step<C>(ga, gb, ra, rb, opA, opB, s);
+#pragma unroll
+      for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < C::FN; ++j) mma<C::DT>(acc.a[i][j], ga[i], gb[j]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    return;
+  }
   Frag<C::DT> fa[3][C::FM], fb[3][C::FN];
   read_step<C>(fa[0], fb[0], ra, rb, opA, opB, 0);
   if (C::STEPS > 1) read_step<C>(fa[1], fb[1], ra, rb, opA, opB, 1);
