@@ -474,6 +474,24 @@ sk_status sk_gemm_grouped_debug(const sk_grouped_plan* plan, const void* dev_des
                                 void* workspace, size_t ws_bytes, const sk_debug* dbg,
                                 void* hip_stream);
 
+/* ---- Operand packing -----------------------------------------------------
+ * Library mechanism (the report's GEMMs take their operands as laid out).
+ * Out-of-place transpose: `in` is a rows x cols row-major matrix (element
+ * (i, j) at in[i*ld_in + j], ld_in >= max(1, cols)), `out` receives the
+ * cols x rows row-major matrix out[j*ld_out + i] = in[i*ld_in + j] (ld_out
+ * >= max(1, rows)); elements of elem_bytes = 1, 2 or 4 bytes are copied bit
+ * for bit.  A column-major operand viewed as its row-major transpose gives,
+ * through this, the K-contiguous copy that the GEMM kernels read with plain
+ * 16-byte LDS reads (M- or N-major operands are read with transposing LDS
+ * reads, which take two instructions per 16-bit fragment and four per
+ * e4m3 fragment).  Device pointers, not overlapping; asynchronous on
+ * hip_stream and capturable.  Errors: SK_ERR_INVALID_ARG for another
+ * elem_bytes, negative sizes, a leading dimension below its minimum, NULL
+ * pointers with rows * cols > 0, or overlapping matrices; SK_ERR_HIP if the
+ * launch fails.  rows or cols 0: nothing is enqueued. */
+sk_status sk_transpose(const void* in, int64_t rows, int64_t cols, int64_t ld_in,
+                       void* out, int64_t ld_out, int32_t elem_bytes, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

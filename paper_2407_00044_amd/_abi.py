@@ -117,6 +117,7 @@ PROTOTYPES = {
     "sk_gemm_grouped": (c_i32, [P(SkGroupedPlan), c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "sk_gemm_grouped_debug": (c_i32, [P(SkGroupedPlan), c_vp, c_vp, ctypes.c_size_t,
                                       P(SkDebug), c_vp]),
+    "sk_transpose": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_vp, c_i64, c_i32, c_vp]),
 }
 
 _lib = None

@@ -671,16 +671,61 @@ class GroupedGemm:
 # ---------------------------------------------------------------------------
 # Differentiable linear layer.
 
+def transpose(t, stream=None):
+    """Row-major transposed copy of a row-major 2-D GPU tensor through
+    sk_transpose: u[j, i] = t[i, j], bit for bit (1-, 2- and 4-byte
+    elements)."""
+    if t.dim() != 2 or not t.is_cuda:
+        raise ValueError("transpose: a 2-D GPU tensor")
+    rows, cols = t.shape
+    if t.numel() and t.stride(1) != 1 and cols > 1:
+        raise ValueError("transpose: rows must be contiguous (unit column stride)")
+    eb = t.element_size()
+    u = torch.empty((cols, rows), dtype=t.dtype, device=t.device)
+    check("sk_transpose", load().sk_transpose(
+        ctypes.c_void_p(t.data_ptr()), rows, cols, max(1, t.stride(0), cols),
+        ctypes.c_void_p(u.data_ptr()), max(1, rows), eb, ctypes.c_void_p(_stream_ptr(stream))))
+    return u
+
+
+def k_contiguous(op, role):
+    """`op` itself if its K dimension is contiguous, else a K-contiguous copy
+    (sk_transpose): role "a" for an M x K operand (K-contiguous = row-major),
+    "b" for a K x N operand (K-contiguous = column-major)."""
+    if role == "a":
+        if op.stride(1) == 1 or op.shape[1] <= 1:
+            return op
+        return transpose(op.t())            # op.t() is K x M row-major
+    if op.stride(0) == 1 or op.shape[0] <= 1:
+        return op
+    return transpose(op).t()                # N x K row-major, viewed K x N
+
+
+def pack_pays(M, N, K, dtype):
+    """Whether a product with M- or N-major operands should be computed from
+    K-contiguous copies.  Transposing LDS reads cost the 16-bit and e4m3
+    kernels 30-45% on large products (BF16 8192x4096x11008 with B N-major:
+    880 vs 601 us on K-contiguous copies, 11008x4096x8192 with both operands
+    transposed: 907 vs 652 us), while a transpose moves each operand byte
+    twice at HBM speed (~40 us for 90 MB); below ~2048 on every dimension
+    the copies' launch and traffic take what they save."""
+    code = DTYPE_CODES[dtype] if isinstance(dtype, torch.dtype) else dtype
+    return code in (_abi.SK_F16, _abi.SK_BF16, _abi.SK_F8E4M3) and min(M, N, K) >= 2048
+
+
 class StreamKLinearFn(torch.autograd.Function):
     """Y = X @ W^T with a hand-written backward through the same kernels:
-    dX = dY @ W and dW = dY^T @ X, expressed purely with layout flags (W read
-    as a column-major K x N operand in the forward; dY read column-major for
-    dW), so no transposed copies are made."""
+    dX = dY @ W and dW = dY^T @ X.  The forward reads W as a column-major
+    K x N operand (K-contiguous, no copy).  The backward products take W, dY
+    and X as laid out (B N-major for dX; A M-major and B N-major for dW), or,
+    with `pack` (True, or "auto": when pack_pays), K-contiguous copies made by
+    sk_transpose."""
 
     @staticmethod
-    def forward(ctx, X, W, config_fwd=None, config_dx=None, config_dw=None):
+    def forward(ctx, X, W, config_fwd=None, config_dx=None, config_dw=None, pack="auto"):
         ctx.save_for_backward(X, W)
         ctx.cfgs = (config_dx, config_dw)
+        ctx.pack = pack
         Y = torch.empty((X.shape[0], W.shape[0]), dtype=X.dtype, device=X.device)
         return gemm(X, W.t(), out=Y, config=config_fwd)
 
@@ -690,18 +735,32 @@ class StreamKLinearFn(torch.autograd.Function):
         cfg_dx, cfg_dw = ctx.cfgs
         if dY.stride(1) != 1 and dY.stride(0) != 1:
             dY = dY.contiguous()
+
+        def packed(M, N, K):
+            return ctx.pack is True or (ctx.pack == "auto" and pack_pays(M, N, K, X.dtype))
+
         dX = dW = None
         if ctx.needs_input_grad[0]:
             dX = torch.empty_like(X, memory_format=torch.contiguous_format)
-            gemm(dY, W, out=dX, config=cfg_dx)
+            B = W
+            if packed(dY.shape[0], W.shape[1], W.shape[0]):
+                B = k_contiguous(W, "b")
+            gemm(dY, B, out=dX, config=cfg_dx)
         if ctx.needs_input_grad[1]:
             dW = torch.empty_like(W, memory_format=torch.contiguous_format)
-            gemm(dY.t(), X, out=dW, config=cfg_dw)
-        return dX, dW, None, None, None
+            A, B = dY.t(), X
+            if packed(W.shape[0], W.shape[1], X.shape[0]):
+                A, B = k_contiguous(A, "a"), k_contiguous(B, "b")
+            gemm(A, B, out=dW, config=cfg_dw)
+        return dX, dW, None, None, None, None
 
 
-def linear(X, W, config_fwd=None, config_dx=None, config_dw=None):
-    return StreamKLinearFn.apply(X, W, config_fwd, config_dx, config_dw)
+def linear(X, W, config_fwd=None, config_dx=None, config_dw=None, pack="auto"):
+    """Y = X @ W^T (StreamKLinearFn); `pack`: True, False or "auto", whether
+    the backward products read K-contiguous copies of their operands."""
+    if pack not in (True, False, "auto"):
+        raise ValueError('pack must be True, False or "auto"')
+    return StreamKLinearFn.apply(X, W, config_fwd, config_dx, config_dw, pack)
 
 
 def with_tile(config, tile):

@@ -1,7 +1,8 @@
 """Build libstreamk.so (the HIP kernels and the C ABI) for gfx950.
 
 Every (input type, A layout, B layout) triple is one compilation of
-csrc/sk_inst.hip; the host library csrc/sk_api.hip is another.  The units
+csrc/sk_inst.hip; the host library csrc/sk_api.hip is another, and the
+operand-packing transpose csrc/sk_transpose.hip a third.  The units
 are compiled in parallel with hipcc and linked into a shared library next to
 this file, where the Python binding loads it.
 
@@ -35,7 +36,8 @@ def _hipcc():
 
 
 def _units():
-    units = [("sk_api", os.path.join(CSRC, "sk_api.hip"), [])]
+    units = [("sk_api", os.path.join(CSRC, "sk_api.hip"), []),
+             ("sk_transpose", os.path.join(CSRC, "sk_transpose.hip"), [])]
     for dt, dn in DTYPES.items():
         for la, an in LAYOUTS.items():
             for lb, bn in LAYOUTS.items():

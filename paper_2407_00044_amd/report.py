@@ -65,7 +65,8 @@ def c4(dev, reps=5):
     """BF16 linear layer Y = X W^T, X [8192, 4096], W [11008, 4096], dY
     [8192, 11008]: forward (A row, B col), dX = dY W (A row, B row) and
     dW = dY^T X (A col, B row), each Stream-K (auto) vs data-parallel at the
-    default tile."""
+    default tile on the operands as laid out, and the two backward products
+    on K-contiguous copies as the linear layer makes them (copies timed)."""
     X = _normal((8192, 4096), 4, dev).to(torch.bfloat16)
     W = _normal((11008, 4096), 5, dev).to(torch.bfloat16)
     dY = _normal((8192, 11008), 40, dev).to(torch.bfloat16)
@@ -85,6 +86,16 @@ def c4(dev, reps=5):
         p = api.plan([(M, N, K)], torch.bfloat16, cfgs[0])
         res[name] = {"M": M, "N": N, "K": K, "tile": list(tile), "stream_k_tiles": p["S"],
                      "tiles": p["T"], "sk_tflops": _tf(fl, t_sk), "dp_tflops": _tf(fl, t_dp)}
+        if name != "forward":
+            # the backward as StreamKLinearFn runs it at this size: K-contiguous
+            # copies (sk_transpose) of the M- or N-major operands, then the
+            # same auto GEMM; the copies' time is included
+            def packed(c=cfgs[0]):
+                api.gemm(api.k_contiguous(A, "a"), api.k_contiguous(B, "b"), out=out, config=c,
+                         workspace=ws)
+            (t_pk,) = _time_all([packed], reps)
+            res[name]["packed_tflops"] = _tf(fl, t_pk)
+            res[name]["packed_by_linear"] = api.pack_pays(M, N, K, torch.bfloat16)
         del out
     return res
 

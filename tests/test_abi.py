@@ -331,3 +331,35 @@ def test_mx4_entry_point_host_checks():
     info = _abi.SkPlanInfo()
     assert lib.sk_plan(ctypes.byref(p), 1, ctypes.byref(cfg), ctypes.byref(info)) == 0
     assert info.T == 4 and info.max_iters == 2
+
+
+def test_transpose_rejects_bad_arguments_on_the_host():
+    # every check runs before anything is enqueued (no GPU needed)
+    lib = sk.load()
+    c = ctypes.c_void_p
+    buf_a, buf_b = c(0x100000), c(0x900000)
+    bad = [
+        (buf_a, 4, 5, 5, buf_b, 4, 3),        # 3-byte elements
+        (buf_a, -1, 5, 5, buf_b, 4, 2),       # negative rows
+        (buf_a, 4, 5, 4, buf_b, 4, 2),        # ld_in < cols
+        (buf_a, 4, 5, 5, buf_b, 3, 2),        # ld_out < rows
+        (c(None), 4, 5, 5, buf_b, 4, 2),      # null input
+        (buf_a, 4, 5, 5, c(None), 4, 2),      # null output
+        (buf_a, 4, 5, 5, c(0x100000 + 8), 4, 2),   # overlapping matrices
+    ]
+    for args in bad:
+        assert lib.sk_transpose(*args, c(None)) == _abi.SK_ERR_INVALID_ARG, args
+    # empty matrices: nothing to do, no pointers needed
+    assert lib.sk_transpose(c(None), 0, 5, 5, c(None), 1, 2, c(None)) == _abi.SK_OK
+    assert lib.sk_transpose(c(None), 7, 0, 1, c(None), 7, 4, c(None)) == _abi.SK_OK
+
+
+def test_pack_rule():
+    # the BF16 linear layer's backward products pack; small ones, FP32 and
+    # any product with a dimension below 2048 do not
+    assert sk.pack_pays(8192, 4096, 11008, torch.bfloat16)
+    assert sk.pack_pays(11008, 4096, 8192, torch.bfloat16)
+    assert sk.pack_pays(4096, 4096, 4096, torch.float8_e4m3fn)
+    assert not sk.pack_pays(8192, 4096, 11008, torch.float32)
+    assert not sk.pack_pays(1024, 4096, 11008, torch.bfloat16)
+    assert not sk.pack_pays(320, 384, 448, torch.float16)
