@@ -487,7 +487,8 @@ sk_status sk_gemm_grouped_debug(const sk_grouped_plan* plan, const void* dev_des
  * e4m3 fragment).  Device pointers, not overlapping; asynchronous on
  * hip_stream and capturable.  Errors: SK_ERR_INVALID_ARG for another
  * elem_bytes, negative sizes, a leading dimension below its minimum, NULL
- * pointers with rows * cols > 0, or overlapping matrices; SK_ERR_HIP if the
+ * pointers with rows * cols > 0, a matrix of 2^58 elements or more
+ * (rows * ld_in or cols * ld_out), or overlapping matrices; SK_ERR_HIP if the
  * launch fails.  rows or cols 0: nothing is enqueued. */
 sk_status sk_transpose(const void* in, int64_t rows, int64_t cols, int64_t ld_in,
                        void* out, int64_t ld_out, int32_t elem_bytes, void* hip_stream);

@@ -105,6 +105,9 @@ extern "C" sk_status sk_transpose(const void* in, int64_t rows, int64_t cols, in
     return SK_ERR_INVALID_ARG;
   if (rows == 0 || cols == 0) return SK_OK;
   if (in == nullptr || out == nullptr) return SK_ERR_INVALID_ARG;
+  // byte extents below 2^60 (no overflow in the address arithmetic)
+  constexpr int64_t kMaxElems = (int64_t)1 << 58;
+  if (rows > kMaxElems / ld_in || cols > kMaxElems / ld_out) return SK_ERR_INVALID_ARG;
   // the two matrices' byte ranges must not overlap
   const uintptr_t a0 = (uintptr_t)in, a1 = a0 + (uintptr_t)(((rows - 1) * ld_in + cols) * elem_bytes);
   const uintptr_t b0 = (uintptr_t)out, b1 = b0 + (uintptr_t)(((cols - 1) * ld_out + rows) * elem_bytes);

@@ -165,6 +165,20 @@ int main() {
   size_t dsz = 0;
   EXPECT(sk_grouped_desc_size(0, &dsz) == SK_ERR_INVALID_ARG);
   EXPECT(sk_grouped_desc_size(48, &dsz) == SK_OK && dsz > 0);
+  // sk_transpose: argument checks (before any launch), extreme sizes in the
+  // overlap test's address arithmetic
+  void* pa = (void*)(uintptr_t)0x100000;
+  void* pb = (void*)(uintptr_t)0x900000;
+  EXPECT(sk_transpose(pa, 4, 5, 5, pb, 4, 3, nullptr) == SK_ERR_INVALID_ARG);
+  EXPECT(sk_transpose(pa, 4, 5, 4, pb, 4, 2, nullptr) == SK_ERR_INVALID_ARG);
+  EXPECT(sk_transpose(pa, 4, 5, 5, pb, 3, 2, nullptr) == SK_ERR_INVALID_ARG);
+  EXPECT(sk_transpose(nullptr, 4, 5, 5, pb, 4, 2, nullptr) == SK_ERR_INVALID_ARG);
+  EXPECT(sk_transpose(pa, 4, 5, 5, (char*)pa + 8, 4, 2, nullptr) == SK_ERR_INVALID_ARG);
+  EXPECT(sk_transpose(pa, (int64_t)1 << 20, (int64_t)1 << 20, (int64_t)1 << 20, pa, (int64_t)1 << 20,
+                      4, nullptr) == SK_ERR_INVALID_ARG);
+  EXPECT(sk_transpose(pa, (int64_t)1 << 40, 3, (int64_t)1 << 40, pb, (int64_t)1 << 40, 1,
+                      nullptr) == SK_ERR_INVALID_ARG);
+  EXPECT(sk_transpose(nullptr, 0, 9, 9, nullptr, 1, 1, nullptr) == SK_OK);
 
   if (failures) {
     fprintf(stderr, "%d expectation(s) failed\n", failures);

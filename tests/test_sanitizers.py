@@ -32,7 +32,8 @@ def test_host_library_code_under_asan_ubsan():
           "-Wno-unused-command-line-argument", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops", "-I" + os.path.join(ROOT, "include")] + san +
          [os.path.join(HERE, "host_abi_driver.cpp"),
-          os.path.join(ROOT, "paper_2407_00044_amd", "csrc", "sk_api.hip"), "-o", exe])
+          os.path.join(ROOT, "paper_2407_00044_amd", "csrc", "sk_api.hip"),
+          os.path.join(ROOT, "paper_2407_00044_amd", "csrc", "sk_transpose.hip"), "-o", exe])
     r = _run([exe], env=ENV, timeout=300)
     assert "host ABI driver: ok" in r.stdout
     assert "runtime error" not in r.stderr
