@@ -176,17 +176,24 @@ def _stream_ptr(stream=None):
 
 def gemm(A, B, C=None, *, alpha=1.0, beta=0.0, out=None, out_dtype=torch.float32,
          scale_a=1.0, scale_b=1.0, bias=None, activation="none", config=None,
-         workspace=None, stream=None):
+         workspace=None, stream=None, pack=False):
     """out = act(alpha * scale_a * scale_b * (A @ B) + beta * C + bias) on the
     GPU (bias and act optional: the fused epilogue; see ACTIVATIONS).
 
     A (M x K) and B (K x N) may each be row- or column-major (unit stride in
     one dimension); out and C are row-major.  With C given and out None the
-    update is in place (out = C)."""
+    update is in place (out = C).  pack (False, True or "auto": where
+    pack_pays) first copies M- or N-major operands K-contiguous
+    (sk_transpose, on the same stream); the result is the same bit for bit."""
     lib = load()
     if not (A.is_cuda and B.is_cuda):
         raise ValueError("operands must be on the GPU")
+    if pack not in (True, False, "auto"):
+        raise ValueError('pack must be True, False or "auto"')
     M, N = A.shape[0], B.shape[1]
+    if pack is True or (pack == "auto" and A.dtype in DTYPE_CODES and
+                        pack_pays(M, N, A.shape[1], A.dtype)):
+        A, B = k_contiguous(A, "a", stream), k_contiguous(B, "b", stream)
     if out is None:
         out = C if (C is not None and beta != 0.0) else torch.empty(
             (M, N), dtype=out_dtype, device=A.device)
@@ -688,17 +695,17 @@ def transpose(t, stream=None):
     return u
 
 
-def k_contiguous(op, role):
+def k_contiguous(op, role, stream=None):
     """`op` itself if its K dimension is contiguous, else a K-contiguous copy
     (sk_transpose): role "a" for an M x K operand (K-contiguous = row-major),
     "b" for a K x N operand (K-contiguous = column-major)."""
     if role == "a":
         if op.stride(1) == 1 or op.shape[1] <= 1:
             return op
-        return transpose(op.t())            # op.t() is K x M row-major
+        return transpose(op.t(), stream)    # op.t() is K x M row-major
     if op.stride(0) == 1 or op.shape[0] <= 1:
         return op
-    return transpose(op).t()                # N x K row-major, viewed K x N
+    return transpose(op, stream).t()        # N x K row-major, viewed K x N
 
 
 def pack_pays(M, N, K, dtype):

@@ -85,6 +85,7 @@ def test_k_contiguous_copies_give_the_same_gemm(dtype):
         packed = sk.gemm(Ak, Bk, config=cfg)
         torch.cuda.synchronize()
         assert torch.equal(got, packed), tile
+        assert torch.equal(sk.gemm(A, B, config=cfg, pack=True), packed), tile
     ref = og.gemm_dense(a.float().double().numpy(), b.float().double().numpy())
     assert og.rel_frobenius(as64(packed), ref) <= 1e-4
 
