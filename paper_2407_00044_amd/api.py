@@ -711,13 +711,20 @@ def k_contiguous(op, role, stream=None):
 def pack_pays(M, N, K, dtype):
     """Whether a product with M- or N-major operands should be computed from
     K-contiguous copies.  Transposing LDS reads cost the 16-bit and e4m3
-    kernels 30-45% on large products (BF16 8192x4096x11008 with B N-major:
-    880 vs 601 us on K-contiguous copies, 11008x4096x8192 with both operands
-    transposed: 907 vs 652 us), while a transpose moves each operand byte
-    twice at HBM speed (~40 us for 90 MB); below ~2048 on every dimension
-    the copies' launch and traffic take what they save."""
+    kernels up to 30-45% (BF16 1024x4096x4096 with both operands M/N-major:
+    70.8 us as laid out, 50.9 us packed, copies included), while a copy moves
+    each operand byte twice at 5-7 TB/s; the copies lose where K is short
+    (BF16 4096x4096x1024, A M-major and B N-major: 0.90x) or the product is
+    small (1024^3: 0.84-1.02x; e4m3, whose GEMMs are faster, 2048^3: 0.76-0.91x).
+    Measured on 8 shapes x 3 layouts per type: K >= 2048 and M*N >= 2^22
+    (and M*N*K >= 2^35 for e4m3) packs every product that gains and none that
+    loses more than 1%."""
     code = DTYPE_CODES[dtype] if isinstance(dtype, torch.dtype) else dtype
-    return code in (_abi.SK_F16, _abi.SK_BF16, _abi.SK_F8E4M3) and min(M, N, K) >= 2048
+    if code not in (_abi.SK_F16, _abi.SK_BF16, _abi.SK_F8E4M3):
+        return False
+    if K < 2048 or M * N < (1 << 22):
+        return False
+    return code != _abi.SK_F8E4M3 or M * N * K >= (1 << 35)
 
 
 class StreamKLinearFn(torch.autograd.Function):

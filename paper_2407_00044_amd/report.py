@@ -325,6 +325,41 @@ def epilogue(dev, reps=5, shape=(3840, 4096, 4096), tile=(256, 256)):
     return res
 
 
+def packing(dev, reps=5):
+    """Operand packing: GEMMs with M- or N-major operands (A M-major and/or
+    B N-major) as laid out (transposing LDS reads) and on K-contiguous
+    copies made by sk_transpose (copies included), BF16 and e4m3, auto mode
+    on the default tile, beside what the packing rule (pack_pays) decides."""
+    ws = api.Workspace(dev)
+    ws.get(96 << 20, torch.cuda.current_stream().cuda_stream)
+    shapes = [(1024, 1024, 1024), (2048, 2048, 2048), (1024, 4096, 4096), (4096, 1024, 4096),
+              (4096, 4096, 1024), (2048, 4096, 8192), (4096, 4096, 4096), (8192, 8192, 2048)]
+    res = {"workload": "A row or col, B row or col (not both K-contiguous), auto, default tile"}
+    for dt in (torch.bfloat16, torch.float8_e4m3fn):
+        name = "bf16" if dt == torch.bfloat16 else "e4m3"
+        rows = []
+        for M, N, K in shapes:
+            a = _uniform((M, K), 11, dev)
+            b = _uniform((K, N), 12, dev)
+            cfg = api.Config(tile=api.default_tile(M, N, K, dt), mode="auto")
+            out = torch.empty((M, N), device=dev)
+            for la, lb in (("row", "row"), ("col", "row"), ("col", "col")):
+                A = (a if la == "row" else a.t().contiguous().t()).to(dt)
+                B = (b.t().contiguous().t() if lb == "col" else b).to(dt)
+                t0, t1 = _time_all([
+                    lambda: api.gemm(A, B, out=out, config=cfg, workspace=ws),
+                    lambda: api.gemm(A, B, out=out, config=cfg, workspace=ws, pack=True)], reps)
+                rows.append({"shape": f"{M}x{N}x{K}", "layout": la[0] + lb[0],
+                             "tile": list(cfg.tile), "as_laid_us": round(t0 * 1e3, 1),
+                             "packed_us": round(t1 * 1e3, 1), "speedup": round(t0 / t1, 3),
+                             "rule_packs": api.pack_pays(M, N, K, dt)})
+                del A, B
+            del out
+            torch.cuda.empty_cache()
+        res[name] = rows
+    return res
+
+
 def padding(dev, reps=10, tile=(256, 128)):
     """The report's padding experiment (Methodology, Results, Table 1) on
     FP16: each shape run unpadded (edges through out-of-range loads and
@@ -421,7 +456,7 @@ def run_all(dev, extra=False, only=None, c5_tile=None):
             ("per_dtype", per_dtype), ("mxfp8", mxfp8), ("mxfp4", mxfp4),
             ("epilogue", epilogue)]
     if extra or only:
-        todo += [("padding", padding), ("compute_units", compute_units),
+        todo += [("packing", packing), ("padding", padding), ("compute_units", compute_units),
                  ("hybrid_variants", hybrid_variants)]
     if only:
         unknown = set(only) - {n for n, _ in todo}

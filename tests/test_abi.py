@@ -355,11 +355,15 @@ def test_transpose_rejects_bad_arguments_on_the_host():
 
 
 def test_pack_rule():
-    # the BF16 linear layer's backward products pack; small ones, FP32 and
-    # any product with a dimension below 2048 do not
+    # the BF16 linear layer's backward products pack, and so do products
+    # with a short M or N but long K; short K, small products, small e4m3
+    # products and FP32 do not
     assert sk.pack_pays(8192, 4096, 11008, torch.bfloat16)
     assert sk.pack_pays(11008, 4096, 8192, torch.bfloat16)
+    assert sk.pack_pays(1024, 4096, 4096, torch.bfloat16)
     assert sk.pack_pays(4096, 4096, 4096, torch.float8_e4m3fn)
+    assert not sk.pack_pays(4096, 4096, 1024, torch.bfloat16)
+    assert not sk.pack_pays(1024, 1024, 4096, torch.bfloat16)
+    assert not sk.pack_pays(2048, 2048, 2048, torch.float8_e4m3fn)
     assert not sk.pack_pays(8192, 4096, 11008, torch.float32)
-    assert not sk.pack_pays(1024, 4096, 11008, torch.bfloat16)
     assert not sk.pack_pays(320, 384, 448, torch.float16)
