@@ -80,11 +80,17 @@ typedef enum {
  * that multiplies them (sk_gemm_mx only).  SK_MXF4E2M1 is OCP MXFP4: E2M1
  * elements (sign, 2 exponent bits with bias 1, 1 mantissa bit: magnitudes
  * 0, 0.5, 1, 1.5, 2, 3, 4, 6) packed two per byte, element 2j of a row in
- * the low nibble of byte j, with the same E8M0 block scales; sizes and
- * leading dimensions count elements.  Accumulation is FP32 for every input
- * type. */
+ * the low nibble of byte j, with the same E8M0 block scales.  SK_MXF6E2M3
+ * and SK_MXF6E3M2 are OCP MXFP6: six-bit elements (sign, then 2 exponent
+ * bits with bias 1 and 3 mantissa bits, max 7.5; or 3 exponent bits with
+ * bias 3 and 2 mantissa bits, max 28; no infinities or NaNs) packed
+ * little-endian, element k of a row at bits 6k .. 6k+5 of the row's bytes
+ * (a block of 32 elements is 24 bytes), with the same E8M0 block scales.
+ * Sizes and leading dimensions count elements.  Accumulation is FP32 for
+ * every input type. */
 typedef enum {
-  SK_F32 = 0, SK_F16 = 1, SK_BF16 = 2, SK_F8E4M3 = 3, SK_MXF8E4M3 = 4, SK_MXF4E2M1 = 5
+  SK_F32 = 0, SK_F16 = 1, SK_BF16 = 2, SK_F8E4M3 = 3, SK_MXF8E4M3 = 4, SK_MXF4E2M1 = 5,
+  SK_MXF6E2M3 = 6, SK_MXF6E3M2 = 7
 } sk_dtype;
 typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
 
@@ -324,10 +330,11 @@ sk_status sk_gemm(const sk_problem* p, const void* A, const void* B,
                   const void* C_in, void* C_out, void* workspace,
                   size_t ws_bytes, const sk_config* cfg, void* hip_stream);
 
-/* One MX GEMM (dtype_ab = SK_MXF8E4M3 or SK_MXF4E2M1): as sk_gemm, with
+/* One MX GEMM (dtype_ab = SK_MXF8E4M3, SK_MXF4E2M1, SK_MXF6E2M3 or
+ * SK_MXF6E3M2): as sk_gemm, with
  *   C_out[i][j] = alpha*scale_a*scale_b * sum_k A[i][k] * 2^(sa[i][k/32]-127)
  *                                   * B[k][j] * 2^(sb[j][k/32]-127) + beta*C_in
- * where A, B hold e4m3 codes (MXFP4: packed E2M1 codes), sa[i][b] = ((const uint8_t*)scale_a)[i*ld_scale_a
+ * where A, B hold e4m3 codes (MXFP4, MXFP6: packed codes), sa[i][b] = ((const uint8_t*)scale_a)[i*ld_scale_a
  * + b] and sb[j][b] = ((const uint8_t*)scale_b)[j*ld_scale_b + b] (device
  * memory; one E8M0 byte per 32 K-values of row i of A / column j of B).
  * The block scales are applied by the matrix cores (gfx950 scaled MFMA),
@@ -336,7 +343,7 @@ sk_status sk_gemm(const sk_problem* p, const void* A, const void* B,
  * scaled MX formats are the gfx950 matrix cores' own.
  * Requirements (else SK_ERR_UNSUPPORTED): A row-major and B column-major,
  * K a multiple of 128 (MXFP4: 256), A and B 16-byte aligned with rows of a
- * multiple of 16 bytes (lda, ldb multiples of 16; MXFP4: 32).
+ * multiple of 16 bytes (lda, ldb multiples of 16; MXFP4: 32; MXFP6: 64).
  * scale_a/scale_b 4-byte aligned, ld_scale_a/ld_scale_b multiples of 4 and
  * >= K/32 (else SK_ERR_INVALID_ARG).  Grouped launches:
  * sk_grouped_prepare_mx; sk_gemm with an MX type returns

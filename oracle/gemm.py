@@ -140,6 +140,33 @@ def unpack_fp4(packed, count) -> np.ndarray:
     return codes[:count]
 
 
+def decode_e2m3(bits) -> np.ndarray:
+    """6-bit OCP FP6 E2M3 codes 0..63 -> exact float64 values: sign bit, 2
+    exponent bits with bias 1, 3 mantissa bits; exponent 0 is subnormal
+    (m / 8); no infinities or NaN, so the largest magnitude is 7.5."""
+    _, _, _, v = _decode_fields(np.asarray(bits).astype(np.int64) & 63, 2, 3, 1)
+    return v
+
+
+def decode_e3m2(bits) -> np.ndarray:
+    """6-bit OCP FP6 E3M2 codes 0..63 -> exact float64 values: sign bit, 3
+    exponent bits with bias 3, 2 mantissa bits; exponent 0 is subnormal
+    (m / 16); no infinities or NaN, so the largest magnitude is 28."""
+    _, _, _, v = _decode_fields(np.asarray(bits).astype(np.int64) & 63, 3, 2, 3)
+    return v
+
+
+def unpack_fp6(packed, count) -> np.ndarray:
+    """Packed FP6 bytes -> `count` codes: element k at bits 6k .. 6k+5 of
+    the bytes read as one little-endian bit string (four elements in three
+    bytes: byte 3j holds element 4j and the low 2 bits of element 4j+1, ...)."""
+    b = np.asarray(packed).astype(np.int64).reshape(-1)
+    bits = ((b[:, None] >> np.arange(8)) & 1).reshape(-1)      # bit 8i+t of the string
+    n = min(count, bits.size // 6)
+    w = bits[:6 * n].reshape(n, 6)
+    return (w << np.arange(6)).sum(axis=1)
+
+
 DECODERS = {"f32": decode_f32, "f16": decode_f16, "bf16": decode_bf16,
             "e4m3": decode_e4m3fn}
 
@@ -197,12 +224,15 @@ def gemm(M, N, K, a, lda, a_col_major, b, ldb, b_col_major, alpha=1.0,
 def mx_operand(codes, ld, scales, ld_s, rows, K, block=32, elem="e4m3"):
     """An MX operand stored K-contiguous (OCP MX block scaling): element
     (r, k) is decode(codes[r*ld + k]) * decode_e8m0(scales[r*ld_s +
-    k // block]), the elements e4m3 codes, or with elem="e2m1" FP4 codes
-    unpacked from bytes (ld then counts elements: row r starts at element
-    r*ld).  Returns the rows x K float64 values; each is a decoded element
+    k // block]), the elements e4m3 codes, or with elem="e2m1" FP4 codes or
+    elem="e2m3" / "e3m2" FP6 codes unpacked from bytes (ld then counts
+    elements: row r starts at element r*ld).  Returns the rows x K float64 values; each is a decoded element
     times a power of two, so the result is exact."""
     if elem == "e2m1":
         x = decode_e2m1(unpack_fp4(codes, 2 * np.asarray(codes).size))
+    elif elem in ("e2m3", "e3m2"):
+        c = unpack_fp6(codes, 8 * np.asarray(codes).size // 6)
+        x = decode_e2m3(c) if elem == "e2m3" else decode_e3m2(c)
     else:
         x = decode_e4m3fn(np.asarray(codes).reshape(-1))
     s = decode_e8m0(np.asarray(scales).reshape(-1))

@@ -13,6 +13,6 @@ from ._abi import LIB_PATH, StreamKError, load  # noqa: F401
 from . import tune  # noqa: F401
 from .api import (ACTIVATIONS, Config, GroupedGemm, StreamKLinearFn, Workspace,  # noqa: F401
                   check_device_error, check_noalloc_error, cost_model, default_tile, device_query,
-                  gemm, gemm_debug, gemm_mx, gemm_mx4, gemm_noalloc, k_contiguous,
+                  gemm, gemm_debug, gemm_mx, gemm_mx4, gemm_mx6, gemm_noalloc, k_contiguous,
                   launch_params, linear, pack_pays, plan, plan_order, schedule,
                   supported_tiles, transpose)

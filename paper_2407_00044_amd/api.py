@@ -19,7 +19,8 @@ DTYPE_CODES = {torch.float32: _abi.SK_F32, torch.float16: _abi.SK_F16,
 OUT_CODES = {torch.float32: _abi.SK_F32, torch.float16: _abi.SK_F16,
              torch.bfloat16: _abi.SK_BF16}
 K_PER_ITER = {_abi.SK_F32: 32, _abi.SK_F16: 64, _abi.SK_BF16: 64, _abi.SK_F8E4M3: 128,
-              _abi.SK_MXF8E4M3: 128, _abi.SK_MXF4E2M1: 256}
+              _abi.SK_MXF8E4M3: 128, _abi.SK_MXF4E2M1: 256, _abi.SK_MXF6E2M3: 128,
+              _abi.SK_MXF6E3M2: 128}
 
 SEGMENT_FIELDS = ("wg", "problem", "tile", "tile_m", "tile_n", "k_begin", "k_end",
                   "role", "npeers")
@@ -325,6 +326,68 @@ def gemm_mx4(A, B, scale_a, scale_b, C=None, *, alpha=1.0, beta=0.0, out=None,
         tile = default_tile(M, N, K, torch.bfloat16)
         config = Config(tile=(256, 128) if tile[0] == 256 else (128, 128))
     c = config.c_struct(_abi.SK_MXF4E2M1)
+    sp = _stream_ptr(stream)
+    nbytes = ctypes.c_size_t()
+    check("sk_workspace_size", lib.sk_workspace_size(ctypes.byref(p), 1, ctypes.byref(c),
+                                                      ctypes.byref(nbytes)))
+    ws = workspace or workspace_for(A.device, sp)
+    wptr, wlen = ws.get(nbytes.value, sp)
+    cin = C.data_ptr() if (C is not None and beta != 0.0) else None
+    check("sk_gemm_mx", lib.sk_gemm_mx(
+        ctypes.byref(p), ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+        ctypes.c_void_p(scale_a.data_ptr()), max(1, scale_a.stride(0)),
+        ctypes.c_void_p(scale_b.data_ptr()), max(1, scale_b.stride(0)), ctypes.c_void_p(cin),
+        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(wptr), wlen, ctypes.byref(c),
+        ctypes.c_void_p(sp)))
+    return out
+
+
+MX6_FORMATS = {"e2m3": _abi.SK_MXF6E2M3, "e3m2": _abi.SK_MXF6E3M2}
+
+
+def gemm_mx6(A, B, scale_a, scale_b, C=None, *, fmt="e2m3", alpha=1.0, beta=0.0, out=None,
+             out_dtype=torch.float32, bias=None, activation="none", config=None,
+             workspace=None, stream=None):
+    """MXFP6 GEMM through sk_gemm_mx: A (M x 3K/4 bytes, row-major) and B
+    (3K/4 x N bytes, column-major: the transpose of an N x 3K/4 row-major
+    array) hold six-bit codes of `fmt` ("e2m3" or "e3m2"), element k of a
+    row at bits 6k .. 6k+5 of its bytes read as one little-endian bit
+    string; scale_a (M x >= K/32) and scale_b (N x >= K/32) hold one E8M0
+    byte per 32 K-values, rows contiguous.
+    out = act(alpha * sum_k (A * 2^(sa-127)) (B * 2^(sb-127)) + beta * C + bias)."""
+    lib = load()
+    if fmt not in MX6_FORMATS:
+        raise ValueError(f"fmt must be one of {list(MX6_FORMATS)}")
+    if A.dtype != torch.uint8 or B.dtype != torch.uint8:
+        raise TypeError("MXFP6 operands: packed bytes (uint8)")
+    for s_ in (scale_a, scale_b):
+        if s_.dtype != torch.uint8 or s_.dim() != 2 or s_.stride(1) != 1 or not s_.is_cuda:
+            raise TypeError("block scales: 2-D uint8 GPU tensors with contiguous rows")
+    if not (A.is_cuda and B.is_cuda) or A.stride(1) != 1 or B.stride(0) != 1:
+        raise ValueError("A row-major and B column-major on the GPU")
+    if A.shape[1] % 3 or B.shape[0] != A.shape[1]:
+        raise ValueError("A and B must hold 3K/4 bytes of K per row / column")
+    M, K, N = A.shape[0], 4 * A.shape[1] // 3, B.shape[1]
+    if A.stride(0) % 3 or B.stride(1) % 3:
+        raise ValueError("row pitches must hold whole groups of four elements")
+    if out is None:
+        out = C if (C is not None and beta != 0.0) else torch.empty(
+            (M, N), dtype=out_dtype, device=A.device)
+    if beta != 0.0 and C is None:
+        raise ValueError("beta != 0 needs C")
+    if scale_a.shape[0] != M or scale_b.shape[0] != N:
+        raise ValueError("one scale row per row of A and per column of B")
+    if tuple(out.shape) != (M, N) or out.dtype not in OUT_CODES or (out.stride(1) != 1 and N > 1):
+        raise ValueError("out must be a row-major M x N float32/float16/bfloat16 tensor")
+    p = SkProblem(M, N, K, SK_ROW_MAJOR, SK_COL_MAJOR, max(4 * A.stride(0) // 3, K, 1),
+                  max(4 * B.stride(1) // 3, K, 1), max(out.stride(0), N, 1), MX6_FORMATS[fmt],
+                  OUT_CODES[out.dtype], alpha, beta, 1.0, 1.0)
+    p = _set_epilogue(p, bias, activation, A.device)
+    if config is None:
+        # the e4m3 rule (two steps per iteration) on the MX menu
+        tile = default_tile(M, N, K, torch.float8_e4m3fn)
+        config = Config(tile=(256, 128) if tile[0] == 256 else (128, 128))
+    c = config.c_struct(MX6_FORMATS[fmt])
     sp = _stream_ptr(stream)
     nbytes = ctypes.c_size_t()
     check("sk_workspace_size", lib.sk_workspace_size(ctypes.byref(p), 1, ctypes.byref(c),

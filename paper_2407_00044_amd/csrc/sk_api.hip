@@ -108,7 +108,7 @@ static sk_status resident_per_cu(const KernelEntry* ke, int* per_cu) {
 static sk_status check_problem(const sk_problem& p) {
   if (p.M < 0 || p.N < 0 || p.K < 0) return SK_ERR_INVALID_ARG;
   if (p.M > kMaxIndex || p.N > kMaxIndex || p.K > kMaxIndex) return SK_ERR_UNSUPPORTED;
-  if (p.dtype_ab < 0 || p.dtype_ab > 5) return SK_ERR_UNSUPPORTED;
+  if (p.dtype_ab < 0 || p.dtype_ab > 7) return SK_ERR_UNSUPPORTED;
   if (p.dtype_c < 0 || p.dtype_c > 2) return SK_ERR_UNSUPPORTED;
   if ((p.layout_a != SK_ROW_MAJOR && p.layout_a != SK_COL_MAJOR) ||
       (p.layout_b != SK_ROW_MAJOR && p.layout_b != SK_COL_MAJOR))
@@ -153,7 +153,7 @@ static bool offsets_fit(const sk_problem& p, int64_t bm, int64_t bn) {
   const int64_t rm = std::min<int64_t>(std::max<int64_t>(p.M, 1), bm);
   const int64_t rn = std::min<int64_t>(std::max<int64_t>(p.N, 1), bn);
   const int64_t k = std::max<int64_t>(p.K, 1);
-  auto bytes = [&](int64_t n) { return elems_to_bytes(p.dtype_ab, n + (p.dtype_ab == 5 ? 1 : 0)); };
+  auto bytes = [&](int64_t n) { return elems_to_bytes(p.dtype_ab, n); };
   const int64_t span_a = p.layout_a == SK_ROW_MAJOR ? bytes((rm - 1) * p.lda + k)
                                                     : bytes((k - 1) * p.lda + bm);
   const int64_t span_b = p.layout_b == SK_COL_MAJOR ? bytes((rn - 1) * p.ldb + k)
@@ -295,8 +295,8 @@ static sk_status plan_problems(const sk_problem* probs, int32_t n, const sk_conf
     d.tile_start = T;
     T += (int64_t)d.tm * d.tn;
     P.max_iters = std::max<int64_t>(P.max_iters, d.I);
-    if (p.dtype_ab == SK_MXF4E2M1) {
-      // the kernels see MXFP4 operands as bytes of two elements
+    if (p.dtype_ab == SK_MXF4E2M1 || p.dtype_ab == SK_MXF6E2M3 || p.dtype_ab == SK_MXF6E3M2) {
+      // the kernels see MXFP4 and MXFP6 operands as bytes
       d.K = elems_to_bytes(p.dtype_ab, d.K);
       d.lda = elems_to_bytes(p.dtype_ab, d.lda);
       d.ldb = elems_to_bytes(p.dtype_ab, d.ldb);
@@ -576,7 +576,8 @@ static sk_status check_mx(const sk_problem& p, const void* A, const void* B, con
     return SK_ERR_UNSUPPORTED;
   if (p.M == 0 || p.N == 0 || p.K == 0) return SK_OK;
   // rows of a multiple of 16 bytes (MXFP4: 32 elements)
-  const int64_t row_align = p.dtype_ab == SK_MXF4E2M1 ? 32 : 16;
+  const int64_t row_align = p.dtype_ab == SK_MXF4E2M1 ? 32
+                            : (p.dtype_ab == SK_MXF6E2M3 || p.dtype_ab == SK_MXF6E3M2) ? 64 : 16;
   if (!aligned16(A) || !aligned16(B) || p.lda % row_align != 0 || p.ldb % row_align != 0)
     return SK_ERR_UNSUPPORTED;
   if (mx.sA == nullptr || mx.sB == nullptr || ((uintptr_t)mx.sA & 3) != 0 ||
@@ -593,7 +594,7 @@ static sk_status gemm_common(const sk_problem* p, const void* A, const void* B, 
                              const sk_debug* dbg, void* stream, const MxScales* mx = nullptr) {
   if (p == nullptr) return SK_ERR_INVALID_ARG;
   // MX inputs need their block scales (sk_gemm_mx); others take none
-  const bool is_mx = p->dtype_ab == SK_MXF8E4M3 || p->dtype_ab == SK_MXF4E2M1;
+  const bool is_mx = p->dtype_ab >= SK_MXF8E4M3;
   if (is_mx != (mx != nullptr)) return SK_ERR_INVALID_ARG;
   Plan P;
   sk_status st = plan_problems(p, 1, cfg, &P);
@@ -867,7 +868,7 @@ static sk_status grouped_prepare(const sk_problem* probs, const void* const* A,
   sk_status st = plan_problems(probs, nprobs, cfg, &P);
   if (st != SK_OK) return st;
   // MX problems need their block scales (sk_grouped_prepare_mx); others take none
-  const bool mx = probs[0].dtype_ab == SK_MXF8E4M3 || probs[0].dtype_ab == SK_MXF4E2M1;
+  const bool mx = probs[0].dtype_ab >= SK_MXF8E4M3;
   if (mx != (sA != nullptr && ldsa != nullptr && sB != nullptr && ldsb != nullptr))
     return SK_ERR_INVALID_ARG;
   if (desc_bytes < (size_t)nprobs * sizeof(ProbDesc)) return SK_ERR_WORKSPACE;

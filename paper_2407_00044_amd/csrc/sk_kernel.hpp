@@ -48,7 +48,8 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef int v2i __attribute__((ext_vector_type(2)));
 
-enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3, DT_MX8 = 4, DT_MX4 = 5 };
+enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3, DT_MX8 = 4, DT_MX4 = 5, DT_MX6 = 6,
+       DT_MX6E3 = 7 };
 // 8-bit e4m3 elements: plain (per-tensor scales, applied in the epilogue) or
 // MXFP8 (an E8M0 scale per 32 K-values of each row of A and column of B,
 // applied by the matrix core)
@@ -56,7 +57,8 @@ constexpr bool is_f8(int dt) { return dt == DT_F8 || dt == DT_MX8; }
 // MXFP4: E2M1 elements packed two per byte, with MXFP8's block scales.  The
 // kernels see its operands as bytes (K, lda, ldb in bytes, 256 elements per
 // 128-byte iteration).
-constexpr bool is_mx(int dt) { return dt == DT_MX8 || dt == DT_MX4; }
+constexpr bool is_mx6(int dt) { return dt == DT_MX6 || dt == DT_MX6E3; }
+constexpr bool is_mx(int dt) { return dt == DT_MX8 || dt == DT_MX4 || is_mx6(dt); }
 enum { L_ROW = 0, L_COL = 1 };
 enum { R_FULL = 0, R_FINISH = 1, R_PARTIAL = 2, R_DP = 3 };
 
@@ -143,10 +145,15 @@ __device__ __forceinline__ u32x4 pack_chunk(const uint32_t (&e)[16 / EB]) {
 // one wave instruction fills 1 KiB of LDS, i.e. 8 consecutive tile rows, and
 // lane i writes the 16 bytes at position i%8 of row i/8, so it fetches the
 // logical chunk that the swizzle puts there.  No registers hold the stage.
-template <int R, int EB, int NT>
+template <int R, int EB, int NT, int KB = 128>
 struct KMajorStage {
   static constexpr int EPC = 16 / EB;        // elements per chunk
-  static constexpr int KE = 128 / EB;        // K elements per iteration
+  static constexpr int KE = KB / EB;         // K elements per iteration
+  // chunks of a 128-byte LDS row that hold data: all 8, or (MXFP6, 96
+  // bytes of K per iteration) the first 6; the others read nothing and
+  // hold zeros
+  static constexpr int KC = KB / 16;
+  static_assert(KB % 16 == 0 && KB <= 128, "bytes of K per iteration");
   static constexpr int NI = R / (NT / 8);    // 1 KiB copies per wave
   static_assert(R % (NT / 8) == 0, "tile rows");
 
@@ -176,7 +183,8 @@ struct KMajorStage {
       for (int j = 0; j < NI; ++j) {
         const int jj = wave * NI + j;
         const int c = (lane & 7) ^ lr ^ (jj & 3);
-        const uint32_t off = lane_row + (uint32_t)(c * 16) + ((uint32_t)(jj * 8) * ld32 + kb32);
+        const uint32_t off = (KC < 8 && c >= KC) ? kOOB
+            : lane_row + (uint32_t)(c * 16) + ((uint32_t)(jj * 8) * ld32 + kb32);
         __builtin_amdgcn_raw_ptr_buffer_load_lds(
             rs, (__attribute__((address_space(3))) void*)(L + jj * 1024), 16, (int)off, 0, 0, 0);
       }
@@ -216,7 +224,7 @@ struct KMajorStage {
     for (int j = 0; j < NI; ++j) {
       const int jj = wave * NI + j;
       const int c = (lane & 7) ^ lr ^ (jj & 3);
-      const bool ok = jj * 8 + lr < rl;
+      const bool ok = jj * 8 + lr < rl && (KC == 8 || c < KC);
       pre[j] = ok ? (uint32_t)(jj * 8 + lr) * ld32 + (uint32_t)(c * 16) : kOOB;
     }
   }
@@ -313,8 +321,9 @@ struct KMajorStage {
 
 // Register-staged variant of the K-contiguous path (16-byte buffer loads
 // into registers, then 16-byte LDS writes); selected at build time.
-template <int R, int EB, int NT>
+template <int R, int EB, int NT, int KB = 128>
 struct KMajorStageReg {
+  static_assert(KB == 128, "register staging: 128 bytes of K per iteration");
   static constexpr int EPC = 16 / EB;
   static constexpr int KE = 128 / EB;
   static constexpr int NCH = R * 8 / NT;     // chunks per thread
@@ -642,20 +651,20 @@ struct MNMajorDMAStage {
 
 // Stage of an operand: K-contiguous, M/N-contiguous through transposing LDS
 // reads (TR), or M/N-contiguous transposed in registers.
-template <bool KMAJOR, bool TR, int R, int EB, int NT>
+template <bool KMAJOR, bool TR, int R, int EB, int NT, int KB>
 struct StageSel;
-template <bool TR, int R, int EB, int NT>
-struct StageSel<true, TR, R, EB, NT> {
+template <bool TR, int R, int EB, int NT, int KB>
+struct StageSel<true, TR, R, EB, NT, KB> {
 #if SK_KMAJOR_DMA
-  using type = KMajorStage<R, EB, NT>;
+  using type = KMajorStage<R, EB, NT, KB>;
 #else
-  using type = KMajorStageReg<R, EB, NT>;
+  using type = KMajorStageReg<R, EB, NT, KB>;
 #endif
 };
-template <int R, int EB, int NT>
-struct StageSel<false, true, R, EB, NT> { using type = MNMajorDMAStage<R, EB, NT>; };
-template <int R, int EB, int NT>
-struct StageSel<false, false, R, EB, NT> { using type = MNMajorStage<R, EB, NT>; };
+template <int R, int EB, int NT, int KB>
+struct StageSel<false, true, R, EB, NT, KB> { using type = MNMajorDMAStage<R, EB, NT>; };
+template <int R, int EB, int NT, int KB>
+struct StageSel<false, false, R, EB, NT, KB> { using type = MNMajorStage<R, EB, NT>; };
 
 // ---------------------------------------------------------------------------
 // Matrix-core step: one 32-byte (f32/f16/bf16) or 64-byte (e4m3) slice of K
@@ -669,6 +678,12 @@ struct Frag<DT_MX8> { u32x4 c[2]; int32_t s; };
 // MXFP4: the lane's 32 K-values (16 bytes) and the scale of their block
 template <>
 struct Frag<DT_MX4> { u32x4 c[1]; int32_t s; };
+// MXFP6 (e2m3 / e3m2): the lane's 32 six-bit K-values (24 bytes, element j
+// at bits 6j .. 6j+5) and the scale of their block
+template <>
+struct Frag<DT_MX6> { u32x2 c[3]; int32_t s; };
+template <>
+struct Frag<DT_MX6E3> { u32x2 c[3]; int32_t s; };
 
 // Per-lane LDS byte offset, inside a 32-row block, of the 16-byte piece
 // `chunk` of the lane's row (lane mod 32).  The swizzle repeats every 32
@@ -716,6 +731,17 @@ __device__ __forceinline__ void mma(v16f& acc, const Frag<DT>& a, const Frag<DT>
     v8i av = __builtin_bit_cast(v8i, a.c);
     v8i bv = __builtin_bit_cast(v8i, b.c);
     acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, a.s, 0, b.s);
+  } else if constexpr (is_mx6(DT)) {
+    // MXFP6 (operand format 2, e2m3, or 3, e3m2): 24 bytes per lane, the
+    // lane's block of 32 K-values with its scale (the lane half's 32 values
+    // form one block: checked on the device against random operands with
+    // per-half scales)
+    constexpr int F = DT == DT_MX6 ? 2 : 3;
+    const v8i av = {(int)a.c[0][0], (int)a.c[0][1], (int)a.c[1][0], (int)a.c[1][1],
+                    (int)a.c[2][0], (int)a.c[2][1], 0, 0};
+    const v8i bv = {(int)b.c[0][0], (int)b.c[0][1], (int)b.c[1][0], (int)b.c[1][1],
+                    (int)b.c[2][0], (int)b.c[2][1], 0, 0};
+    acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, F, F, 0, a.s, 0, b.s);
   } else {
     // MXFP4 (operand format 4, e2m1): 16 bytes per lane, the lane's block
     // of 32 K-values with its scale
@@ -730,14 +756,16 @@ template <int DT_, int LA_, int LB_, int BM_, int BN_, int WGM_, int NW_>
 struct Cfg {
   static constexpr int DT = DT_, LA = LA_, LB = LB_, BM = BM_, BN = BN_, WGM = WGM_;
   static constexpr int NW = NW_, NT = 64 * NW_;     // waves, threads per workgroup
-  static constexpr int EB = DT == DT_F32 ? 4 : (is_f8(DT) || DT == DT_MX4) ? 1 : 2;
+  static constexpr int EB = DT == DT_F32 ? 4 : (is_f8(DT) || DT == DT_MX4 || is_mx6(DT)) ? 1 : 2;
   static constexpr bool MX = is_mx(DT);              // E8M0 block scales in the stage
   static constexpr int SB = DT == DT_MX4 ? 8 : 4;    // MX: scale bytes per row and iteration
-  static constexpr int KE = 128 / EB;                // K elements per iteration
+  // K elements per iteration (MX formats: bytes of K); an LDS stage row is
+  // 128 bytes, of which MXFP6 (128 six-bit values) fills 96
+  static constexpr int KE = is_mx6(DT) ? 96 : 128 / EB;
   static constexpr int WGN = NW / WGM;
   static constexpr int WM = BM / WGM, WN = BN / WGN; // per-wave tile
   static constexpr int FM = WM / 32, FN = WN / 32;   // 32x32 blocks per wave
-  static constexpr int STEPS = is_f8(DT) ? 2 : 4;   // matrix-core steps per iteration
+  static constexpr int STEPS = (is_f8(DT) || is_mx6(DT)) ? 2 : 4;   // matrix-core steps per iteration
   static constexpr int BOFF = BM * 128;              // B tile offset in a stage
   // MX: after the tiles, SB scale bytes (the iteration's SB blocks of 32
   // K-values) per row of A then per column of B, copied in 256-byte blocks,
@@ -777,13 +805,13 @@ struct Cfg {
   static_assert(!MX || (LA == L_ROW && LB == L_COL && (BM * SB) % 256 == 0),
                 "MX: K-contiguous operands, A's scale rows end on a 256-byte block");
   // LDS read instructions per matrix-core step
-  static constexpr int RD_K = is_f8(DT) ? 2 : 1;    // K-contiguous fragment
+  static constexpr int RD_K = is_f8(DT) ? 2 : is_mx6(DT) ? 3 : 1;   // K-contiguous fragment
   static constexpr int RD_T = is_f8(DT) ? 4 : 2;    // transposed fragment
   static constexpr int NRD = FM * (TRA ? RD_T : RD_K) + FN * (TRB ? RD_T : RD_K);
   static_assert(WGM * WGN == NW && FM >= 1 && FN >= 1, "wave grid");
   static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile");
-  using StageA = typename StageSel<LA == L_ROW, TRA, BM, EB, NT>::type;
-  using StageB = typename StageSel<LB == L_COL, TRB, BN, EB, NT>::type;
+  using StageA = typename StageSel<LA == L_ROW, TRA, BM, EB, NT, KE * EB>::type;
+  using StageB = typename StageSel<LB == L_COL, TRB, BN, EB, NT, KE * EB>::type;
 };
 
 template <typename C>
@@ -942,6 +970,17 @@ struct FragReader {
           u32x2, __builtin_amdgcn_ds_read_tr16_b64_v4i16(
                      (__attribute__((address_space(3))) v4s*)(p + 4 * PITCH)));
       f.c[0] = u32x4{lo[0], lo[1], hi[0], hi[1]};
+    } else if constexpr (is_mx6(C::DT)) {
+      // MXFP6: step s covers K bytes 48s .. 48s+47 of the row, lane half h
+      // the 24 bytes 48s + 24h .. (its block of 32 values), read as three
+      // 8-byte pieces of the swizzled 16-byte chunks; scales as MXFP8
+      const char* p = op + off[i];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int u = 6 * s + 3 * half + t;   // 8-byte unit of the row
+        f.c[t] = *(const u32x2*)(p + frag_lane_off(l32, u >> 1) + 8 * (u & 1));
+      }
+      f.s = (s & 1) ? 0 : (int32_t)(*(const uint32_t*)(op + sb + 128 * i) >> (8 * half));
     } else {
       int lo[2];
       if constexpr (C::DT == DT_MX8) {
@@ -1166,7 +1205,7 @@ __device__ __forceinline__ void step_fenced(
       read_frag_n<C>(ra, rb, rda, rdb, opA, opB, rs, n);
       // MXFP8, step 1 read during step 0 of the same iteration: its scale
       // is byte 2 of step 0's (bytes 2s + half of the row's 4)
-      if constexpr (C::DT == DT_MX8) {
+      if constexpr (C::DT == DT_MX8 || is_mx6(C::DT)) {
         if (rs & 1) {
           if (n < 1) ra[0].s = fa[0].s >> 16;
           else if (n <= C::FN) rb[n - 1].s = fb[n - 1].s >> 16;

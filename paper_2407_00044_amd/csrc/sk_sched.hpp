@@ -93,20 +93,24 @@ SK_HD int64_t logical_id(int64_t b, int64_t g, int32_t xcd_remap, int32_t revers
 }
 
 // Elements of K per MAC iteration: 128 bytes of K for every input type
-// (MXFP4: 256 elements of half a byte).
+// (MXFP4: 256 elements of half a byte), except MXFP6: 128 elements, 96
+// bytes (four blocks of 32 six-bit values).
 SK_HD int32_t k_per_iter(int32_t dtype_ab) {
   return dtype_ab == 0 ? 32 : dtype_ab == 5 ? 256 : dtype_ab >= 3 ? 128 : 64;
 }
 
-// Bytes per element of the kernels' view of an operand (MXFP4 operands are
-// seen as bytes of two elements).
+// Bytes per element of the kernels' view of an operand (MXFP4 and MXFP6
+// operands are seen as bytes: two, or four per three, elements).
 SK_HD int32_t elem_bytes(int32_t dtype) {
   return dtype == 0 ? 4 : dtype >= 3 ? 1 : 2;
 }
 
-// Bytes of n elements (n even for MXFP4).
+// Bytes of n elements (n even for MXFP4, a multiple of 4 for MXFP6; a
+// count past those rounds up to the byte holding the last element's bits).
 SK_HD int64_t elems_to_bytes(int32_t dtype, int64_t n) {
-  return dtype == 5 ? n / 2 : n * elem_bytes(dtype);
+  if (dtype == 5) return (n + 1) / 2;
+  if (dtype == 6 || dtype == 7) return (3 * n + 3) / 4;
+  return n * elem_bytes(dtype);
 }
 
 }  // namespace sk

@@ -129,6 +129,73 @@ def mx4_quantize(x64, block=32):
     return pack_fp4(c), e.astype(np.uint8)
 
 
+FP6_MAX = {"e2m3": 7.5, "e3m2": 28.0}
+_FP6_FIELDS = {"e2m3": (2, 3, 1), "e3m2": (3, 2, 3)}   # exponent bits, mantissa bits, bias
+
+
+def _fp6_grid(fmt):
+    """Non-negative FP6 magnitudes in code order (codes 0..31)."""
+    eb, mb, bias = _FP6_FIELDS[fmt]
+    out = []
+    for c in range(32):
+        e, m = c >> mb, c & ((1 << mb) - 1)
+        out.append(math.ldexp(m, 1 - bias - mb) if e == 0 else
+                   math.ldexp((1 << mb) + m, e - bias - mb))
+    return np.array(out)
+
+
+def fp6_rne(x, fmt):
+    """Round to the nearest FP6 value of `fmt` ("e2m3" or "e3m2"), ties to
+    the code with an even mantissa, saturating at the largest magnitude:
+    returns 6-bit codes (int64)."""
+    grid = _fp6_grid(fmt)
+    mid = (grid[:-1] + grid[1:]) / 2
+    x = np.asarray(x, dtype=np.float64)
+    a = np.minimum(np.abs(x), grid[-1])
+    idx = np.zeros(a.shape, dtype=np.int64)
+    for i, m in enumerate(mid):
+        # a tie between codes i and i+1 goes to the even one
+        idx += (a > m) if i % 2 == 0 else (a >= m)
+    return idx | (np.signbit(x).astype(np.int64) << 5)
+
+
+def pack_fp6(codes6):
+    """6-bit codes R x K (K a multiple of 4) -> bytes R x 3K/4, element k at
+    bits 6k .. 6k+5 of the row's little-endian bit string."""
+    c = np.asarray(codes6, dtype=np.int64)
+    R, K = c.shape
+    g = c.reshape(R, K // 4, 4)
+    word = g[..., 0] | (g[..., 1] << 6) | (g[..., 2] << 12) | (g[..., 3] << 18)   # 24 bits
+    out = np.stack([word & 255, (word >> 8) & 255, (word >> 16) & 255], axis=-1)
+    return out.reshape(R, 3 * K // 4).astype(np.uint8)
+
+
+def mx6_quantize(x64, fmt, block=32):
+    """MXFP6 quantisation of rows along K: for each block of `block`
+    consecutive K-values of a row, the shared exponent X = the smallest
+    power of two with amax / 2^X <= the format's largest value (amax 0 gives
+    X = 0) is stored as the E8M0 code X + 127, and the elements become the
+    nearest FP6 value of x / 2^X.  Returns (packed bytes R x 3K/4, uint8
+    scale array R x ceil(K/block))."""
+    x = np.asarray(x64, dtype=np.float64)
+    top = FP6_MAX[fmt]
+    R, K = x.shape
+    nb = -(-K // block)
+    e = np.zeros((R, nb), dtype=np.int64)
+    c = np.empty(x.shape, dtype=np.int64)
+    for b in range(nb):
+        blk = x[:, b * block:(b + 1) * block]
+        amax = np.max(np.abs(blk), axis=1)
+        safe = np.where(amax > 0, amax, top)
+        X = np.ceil(np.log2(safe / top))
+        X = np.where(safe / np.ldexp(1.0, X.astype(np.int64)) > top, X + 1, X)
+        X = np.where(safe / np.ldexp(1.0, (X - 1).astype(np.int64)) <= top, X - 1, X)
+        X = np.clip(np.where(amax > 0, X, 0), -127, 127).astype(np.int64)
+        e[:, b] = X + 127
+        c[:, b * block:(b + 1) * block] = fp6_rne(blk / np.ldexp(1.0, X)[:, None], fmt)
+    return pack_fp6(c), e.astype(np.uint8)
+
+
 def codes(t):
     """Raw bit patterns of a CPU tensor (uint32/uint16/uint8 numpy array)."""
     dt = {v: k for k, v in TORCH_DTYPES.items()}[t.dtype]

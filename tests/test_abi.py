@@ -367,3 +367,27 @@ def test_pack_rule():
     assert not sk.pack_pays(2048, 2048, 2048, torch.float8_e4m3fn)
     assert not sk.pack_pays(8192, 4096, 11008, torch.float32)
     assert not sk.pack_pays(320, 384, 448, torch.float16)
+
+
+def test_mx6_entry_point_host_checks():
+    # MXFP6 through sk_gemm_mx: whole 128-element iterations and rows of a
+    # multiple of 64 elements (48 bytes, a multiple of 16); nothing launched
+    lib = _abi.load()
+    fake = ctypes.c_void_p(1 << 20)
+    for dt in (_abi.SK_MXF6E2M3, _abi.SK_MXF6E3M2):
+        cfg = sk.Config(tile=(128, 128), num_cu=8).c_struct(dt)
+        assert cfg.block_k == 128
+
+        def call(M, N, K, lda, ldb, lds=8):
+            p = _abi.SkProblem(M, N, K, _abi.SK_ROW_MAJOR, _abi.SK_COL_MAJOR, lda, ldb, N, dt,
+                               _abi.SK_F32, 1.0, 0.0, 1.0, 1.0)
+            return lib.sk_gemm_mx(ctypes.byref(p), fake, fake, fake, lds, fake, lds, None, fake,
+                                  None, 0, ctypes.byref(cfg), None)
+        assert call(256, 256, 192, 192, 192) == _abi.SK_ERR_UNSUPPORTED    # K % 128
+        assert call(256, 256, 256, 288, 256) == _abi.SK_ERR_UNSUPPORTED    # lda % 64
+        assert call(256, 256, 256, 256, 320, lds=4) == _abi.SK_ERR_INVALID_ARG   # scales < K/32
+        # plain sk_gemm refuses an MX type
+        p = _abi.SkProblem(256, 256, 256, _abi.SK_ROW_MAJOR, _abi.SK_COL_MAJOR, 256, 256, 256,
+                           dt, _abi.SK_F32, 1.0, 0.0, 1.0, 1.0)
+        assert lib.sk_gemm(ctypes.byref(p), fake, fake, None, fake, None, 0, ctypes.byref(cfg),
+                           None) == _abi.SK_ERR_INVALID_ARG

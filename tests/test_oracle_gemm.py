@@ -389,3 +389,60 @@ def test_mx4_quantize_round_trip_within_e2m1_precision():
     pg, sg = synth.mx4_quantize(grid)
     assert sg[0, 0] == 127
     assert np.array_equal(og.mx_operand(pg, 32, sg, 1, 1, 32, elem="e2m1"), grid)
+
+
+# ---------------------------------------------------------------------------
+# MXFP6 (OCP FP6 E2M3 and E3M2 elements)
+
+def test_fp6_decoders_against_the_format_tables():
+    # the OCP MX formats' published extremes: E2M3 max normal 7.5, min
+    # normal 1.0, max subnormal 0.875, min subnormal 0.125; E3M2 28.0, 0.25,
+    # 0.1875, 0.0625; 32 distinct increasing magnitudes, sign bit 5
+    for dec, ext in [(og.decode_e2m3, (7.5, 1.0, 0.875, 0.125)),
+                     (og.decode_e3m2, (28.0, 0.25, 0.1875, 0.0625))]:
+        v = dec(np.arange(64))
+        mag = v[:32]
+        assert np.all(np.diff(mag) > 0) and mag[0] == 0.0
+        assert np.array_equal(v[32:], -mag)
+        normals = mag[mag >= ext[1]]
+        subnormals = mag[(mag > 0) & (mag < ext[1])]
+        assert (normals.max(), normals.min(), subnormals.max(), subnormals.min()) == ext
+        # subnormals are evenly spaced by the smallest one
+        assert np.allclose(np.diff(np.concatenate([[0.0], subnormals])), ext[3])
+
+
+def test_fp6_unpack_bit_order_hand_worked():
+    # codes 1, 2, 3, 4 at bits 0-5, 6-11, 12-17, 18-23:
+    # 1 + 2*2^6 + 3*2^12 + 4*2^18 = 0x103081 -> bytes 0x81 0x30 0x10
+    assert list(og.unpack_fp6(np.array([0x81, 0x30, 0x10]), 4)) == [1, 2, 3, 4]
+    # the top code in every slot: all 24 bits set
+    assert list(og.unpack_fp6(np.array([0xFF, 0xFF, 0xFF]), 4)) == [63] * 4
+
+
+def test_fp6_pack_round_trip_and_quantizer():
+    from paper_2407_00044_amd import synth
+    rng = np.random.default_rng(7)
+    c = rng.integers(0, 64, size=(5, 96))
+    packed = synth.pack_fp6(c)
+    assert packed.shape == (5, 72)
+    for r in range(5):
+        assert np.array_equal(og.unpack_fp6(packed[r], 96), c[r])
+    for fmt, dec in (("e2m3", og.decode_e2m3), ("e3m2", og.decode_e3m2)):
+        grid = dec(np.arange(64))
+        # every representable value is its own rounding
+        assert np.array_equal(dec(synth.fp6_rne(grid, fmt)), grid)
+        # the midpoint of two neighbours goes to the even code; beyond the
+        # largest value saturates
+        mag = grid[:32]
+        mids = (mag[:-1] + mag[1:]) / 2
+        got = synth.fp6_rne(mids, fmt)
+        assert np.all(got % 2 == 0)
+        assert dec(synth.fp6_rne(np.array([1e9, -1e9]), fmt)).tolist() == [mag[-1], -mag[-1]]
+    # MX quantisation: the block's largest magnitude lands in the top binade
+    x = synth.normal((4, 128), 8)
+    packed, sc = synth.mx6_quantize(x, "e2m3")
+    vals = og.decode_e2m3(og.unpack_fp6(packed.reshape(-1), 4 * 128)).reshape(4, 128)
+    for b in range(4):
+        blk = np.abs(x[:, 32 * b:32 * b + 32]).max(axis=1) / np.ldexp(1.0, sc[:, b].astype(int) - 127)
+        assert np.all((blk <= 7.5) & (blk > 7.5 / 2))
+    assert np.max(np.abs(vals)) <= 7.5
