@@ -292,6 +292,35 @@ def mxfp4(dev, reps=5, shape=(3840, 4096, 4096), tile=(256, 128)):
     return res
 
 
+def mxfp6(dev, reps=5, shape=(3840, 4096, 4096), tile=(256, 128)):
+    """MXFP6 (E2M3 and E3M2 elements, 24 bytes per 32, an E8M0 scale per
+    32 K-values, applied by the matrix cores) at the headline shape on the
+    MX tile: Stream-K (two-tile hybrid), the auto policy and the
+    data-parallel grid; % of the dense FP6 MFMA peak (10.1 PFLOP/s)."""
+    M, N, K = shape
+    ws = api.Workspace(dev)
+    ws.get(96 << 20, torch.cuda.current_stream().cuda_stream)
+    out = torch.empty((M, N), device=dev)
+    fl = 2.0 * M * N * K
+    res = {"workload": f"{M}x{N}x{K}, A row-major, B column-major, FP32 output, tile "
+                       f"{tile[0]}x{tile[1]}"}
+    for fmt in ("e2m3", "e3m2"):
+        pa, sa = synth.mx6_quantize(synth.normal((M, K), 65), fmt)
+        pb, sb = synth.mx6_quantize(synth.normal((N, K), 66), fmt)
+        A, B = torch.from_numpy(pa).to(dev), torch.from_numpy(pb).to(dev).t()
+        SA, SB = torch.from_numpy(sa).to(dev), torch.from_numpy(sb).to(dev)
+        cfgs = {"stream_k": api.Config(tile=tile, mode="hybrid"),
+                "auto": api.Config(tile=tile, mode="auto"),
+                "dp": api.Config(tile=tile, mode="dp")}
+        fns = [(lambda c: (lambda: api.gemm_mx6(A, B, SA, SB, fmt=fmt, out=out, config=c,
+                                                workspace=ws)))(c) for c in cfgs.values()]
+        ts = _time_all(fns, reps)
+        res[fmt] = {n: {"tflops": _tf(fl, t), "pct_peak": round(100 * fl / t / 1e9 / 10066.3, 2)}
+                    for n, t in zip(cfgs, ts)}
+        del A, B
+    return res
+
+
 def epilogue(dev, reps=5, shape=(3840, 4096, 4096), tile=(256, 256)):
     """Cost of the fused epilogue (bias per column, then ReLU / GELU / SiLU)
     on BF16 at the headline shape, auto policy: the plain GEMM, each fused
@@ -453,7 +482,7 @@ def run_all(dev, extra=False, only=None, c5_tile=None):
     c5_tile runs c5 in auto mode on that tile instead of the tuner's pick."""
     out = {}
     todo = [("c1", c1), ("c3", c3), ("c4", c4), ("c5", lambda d: c5(d, tile=c5_tile)),
-            ("per_dtype", per_dtype), ("mxfp8", mxfp8), ("mxfp4", mxfp4),
+            ("per_dtype", per_dtype), ("mxfp8", mxfp8), ("mxfp4", mxfp4), ("mxfp6", mxfp6),
             ("epilogue", epilogue)]
     if extra or only:
         todo += [("packing", packing), ("padding", padding), ("compute_units", compute_units),
