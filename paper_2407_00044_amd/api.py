@@ -345,6 +345,27 @@ def gemm_mx4(A, B, scale_a, scale_b, C=None, *, alpha=1.0, beta=0.0, out=None,
 MX6_FORMATS = {"e2m3": _abi.SK_MXF6E2M3, "e3m2": _abi.SK_MXF6E3M2}
 
 
+def _mx6_problem(A, B, out, alpha, beta, fmt):
+    """sk_problem of an MXFP6 product: A (M x 3K/4 bytes, row-major), B (3K/4
+    x N bytes, column-major), out row-major M x N; sizes in elements."""
+    if fmt not in MX6_FORMATS:
+        raise ValueError(f"fmt must be one of {list(MX6_FORMATS)}")
+    if A.dtype != torch.uint8 or B.dtype != torch.uint8:
+        raise TypeError("MXFP6 operands: packed bytes (uint8)")
+    if (A.numel() and A.stride(1) != 1) or (B.numel() and B.stride(0) != 1):
+        raise ValueError("MXFP6: A row-major and B column-major")
+    if A.shape[1] % 3 or B.shape[0] != A.shape[1]:
+        raise ValueError("A and B must hold 3K/4 bytes of K per row / column")
+    if A.stride(0) % 3 or B.stride(1) % 3:
+        raise ValueError("row pitches must hold whole groups of four elements")
+    M, K, N = A.shape[0], 4 * A.shape[1] // 3, B.shape[1]
+    if tuple(out.shape) != (M, N) or out.dtype not in OUT_CODES or (out.stride(1) != 1 and N > 1):
+        raise ValueError("out must be a row-major M x N float32/float16/bfloat16 tensor")
+    return SkProblem(M, N, K, SK_ROW_MAJOR, SK_COL_MAJOR, max(4 * A.stride(0) // 3, K, 1),
+                     max(4 * B.stride(1) // 3, K, 1), max(out.stride(0), N, 1), MX6_FORMATS[fmt],
+                     OUT_CODES[out.dtype], alpha, beta, 1.0, 1.0)
+
+
 def gemm_mx6(A, B, scale_a, scale_b, C=None, *, fmt="e2m3", alpha=1.0, beta=0.0, out=None,
              out_dtype=torch.float32, bias=None, activation="none", config=None,
              workspace=None, stream=None):
@@ -368,8 +389,6 @@ def gemm_mx6(A, B, scale_a, scale_b, C=None, *, fmt="e2m3", alpha=1.0, beta=0.0,
     if A.shape[1] % 3 or B.shape[0] != A.shape[1]:
         raise ValueError("A and B must hold 3K/4 bytes of K per row / column")
     M, K, N = A.shape[0], 4 * A.shape[1] // 3, B.shape[1]
-    if A.stride(0) % 3 or B.stride(1) % 3:
-        raise ValueError("row pitches must hold whole groups of four elements")
     if out is None:
         out = C if (C is not None and beta != 0.0) else torch.empty(
             (M, N), dtype=out_dtype, device=A.device)
@@ -377,12 +396,7 @@ def gemm_mx6(A, B, scale_a, scale_b, C=None, *, fmt="e2m3", alpha=1.0, beta=0.0,
         raise ValueError("beta != 0 needs C")
     if scale_a.shape[0] != M or scale_b.shape[0] != N:
         raise ValueError("one scale row per row of A and per column of B")
-    if tuple(out.shape) != (M, N) or out.dtype not in OUT_CODES or (out.stride(1) != 1 and N > 1):
-        raise ValueError("out must be a row-major M x N float32/float16/bfloat16 tensor")
-    p = SkProblem(M, N, K, SK_ROW_MAJOR, SK_COL_MAJOR, max(4 * A.stride(0) // 3, K, 1),
-                  max(4 * B.stride(1) // 3, K, 1), max(out.stride(0), N, 1), MX6_FORMATS[fmt],
-                  OUT_CODES[out.dtype], alpha, beta, 1.0, 1.0)
-    p = _set_epilogue(p, bias, activation, A.device)
+    p = _set_epilogue(_mx6_problem(A, B, out, alpha, beta, fmt), bias, activation, A.device)
     if config is None:
         # the e4m3 rule (two steps per iteration) on the MX menu
         tile = default_tile(M, N, K, torch.float8_e4m3fn)
@@ -612,12 +626,13 @@ class GroupedGemm:
     can be captured into a HIP graph (torch.cuda.CUDAGraph).  biases: per
     problem a float32 vector of N values or None, added before the activation
     (one for every problem) in the fused epilogue.  mx_scales: MX problems
-    (A, B torch.float8_e4m3fn codes for MXFP8, or packed FP4 bytes as for
-    gemm_mx4 for MXFP4; A row-major, B column-major), per problem
-    (scale_a, scale_b) as for gemm_mx."""
+    (A, B torch.float8_e4m3fn codes for MXFP8, or packed bytes as for
+    gemm_mx4 / gemm_mx6; A row-major, B column-major), per problem
+    (scale_a, scale_b) as for gemm_mx; mx_format names the packed bytes'
+    elements: "e2m1" (MXFP4, the default), "e2m3" or "e3m2" (MXFP6)."""
 
     def __init__(self, problems, config=None, alpha=1.0, scales=None, stream=None,
-                 biases=None, activation="none", mx_scales=None):
+                 biases=None, activation="none", mx_scales=None, mx_format="e2m1"):
         lib = load()
         n = len(problems)
         if n == 0:
@@ -637,8 +652,14 @@ class GroupedGemm:
             beta = pr[4] if len(pr) > 4 else 0.0
             sa, sb = scales[i] if scales is not None else (1.0, 1.0)
             fp4 = mx_scales is not None and A.dtype in (torch.uint8, torch.float4_e2m1fn_x2)
-            base = (_mx4_problem(A, B, out, alpha, beta) if fp4 else
-                    _problem(A, B, out, alpha, beta, sa, sb, prefer))
+            if fp4 and mx_format in MX6_FORMATS:
+                base = _mx6_problem(A, B, out, alpha, beta, mx_format)
+            elif fp4:
+                if mx_format != "e2m1":
+                    raise ValueError('mx_format must be "e2m1", "e2m3" or "e3m2"')
+                base = _mx4_problem(A, B, out, alpha, beta)
+            else:
+                base = _problem(A, B, out, alpha, beta, sa, sb, prefer)
             probs[i] = _set_epilogue(base, biases[i] if biases is not None else None, activation,
                                      A.device)
             if mx_scales is not None and not fp4:
@@ -650,7 +671,9 @@ class GroupedGemm:
         dev = problems[0][0].device
         M0, N0, K0 = probs[0].M, probs[0].N, probs[0].K
         if config is None:
-            dt0 = torch.bfloat16 if probs[0].dtype_ab == _abi.SK_MXF4E2M1 else problems[0][0].dtype
+            dt0 = (torch.bfloat16 if probs[0].dtype_ab == _abi.SK_MXF4E2M1 else
+                   torch.float8_e4m3fn if probs[0].dtype_ab in MX6_FORMATS.values() else
+                   problems[0][0].dtype)
             tile = default_tile(M0, N0, K0, dt0)
             if mx_scales is not None and tile not in ((256, 128), (128, 128)):
                 tile = (256, 128) if tile[0] == 256 else (128, 128)   # the MX tile menu

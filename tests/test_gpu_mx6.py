@@ -12,7 +12,9 @@ FP64, then the plain product).
 * the headline shape on the full matrix, alpha and an in-place beta * C, and
   the fused epilogue;
 * scale-row padding (bytes past K/32) holds NaN codes, which must never be
-  read.
+  read;
+* a grouped launch of five uneven problems per format, against the oracle
+  and bitwise across graph replays.
 """
 import numpy as np
 import pytest
@@ -106,3 +108,37 @@ def test_mx6_fused_epilogue():
     torch.cuda.synchronize()
     expect = og.epilogue(ref(), bias.cpu().numpy().astype(np.float64), "silu")
     assert rel_err(as64(out), expect) <= 1e-4
+
+
+GROUP = [(300, 260, 512), (64, 1000, 1024), (1000, 129, 256), (1, 64, 256), (513, 700, 768)]
+
+
+@pytest.mark.parametrize("fmt", ["e2m3", "e3m2"])
+@pytest.mark.parametrize("mode", ["sk", "hybrid"])
+def test_mx6_grouped_parity_and_replays(fmt, mode):
+    print(f"case mx6 grouped {fmt} {mode}", flush=True)
+    probs, scales, refs = [], [], []
+    for i, (M, N, K) in enumerate(GROUP):
+        A, B, SA, SB, ref = mx6_inputs(M, N, K, fmt, 290 + 10 * i)
+        probs.append((A, B, torch.full((M, N), float("nan"), device=dev())))
+        scales.append((SA, SB))
+        refs.append(ref)
+    cfg = sk.Config(tile=(128, 128), mode=mode, num_cu=23, min_iters=1 if mode == "sk" else 0)
+    gg = sk.GroupedGemm(probs, config=cfg, mx_scales=scales, mx_format=fmt)
+    assert gg.info()["S"] > 0 and gg.info()["dtype_ab"] == sk.api.MX6_FORMATS[fmt]
+    gg.run()
+    torch.cuda.synchronize()
+    assert sk.check_device_error(workspace=gg.workspace) == 0
+    first = []
+    for (A, B, out), ref in zip(probs, refs):
+        assert rel_err(as64(out), ref()) <= 1e-4, tuple(out.shape)
+        first.append(out.clone())
+    g = gg.capture()
+    for r in range(2):
+        for _, _, out in probs:
+            out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (_, _, out), f in zip(probs, first):
+            assert torch.equal(out, f), f"replay {r} differs"
