@@ -86,11 +86,14 @@ typedef enum {
  * bias 3 and 2 mantissa bits, max 28; no infinities or NaNs) packed
  * little-endian, element k of a row at bits 6k .. 6k+5 of the row's bytes
  * (a block of 32 elements is 24 bytes), with the same E8M0 block scales.
+ * SK_MXF8E5M2 is OCP MXFP8 with e5m2 elements (sign, 5 exponent bits with
+ * bias 15, 2 mantissa bits; exponent 31 holds infinities and NaNs; max
+ * finite 57344), one byte each, with the same block scales.
  * Sizes and leading dimensions count elements.  Accumulation is FP32 for
  * every input type. */
 typedef enum {
   SK_F32 = 0, SK_F16 = 1, SK_BF16 = 2, SK_F8E4M3 = 3, SK_MXF8E4M3 = 4, SK_MXF4E2M1 = 5,
-  SK_MXF6E2M3 = 6, SK_MXF6E3M2 = 7
+  SK_MXF6E2M3 = 6, SK_MXF6E3M2 = 7, SK_MXF8E5M2 = 8
 } sk_dtype;
 typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
 
@@ -330,11 +333,11 @@ sk_status sk_gemm(const sk_problem* p, const void* A, const void* B,
                   const void* C_in, void* C_out, void* workspace,
                   size_t ws_bytes, const sk_config* cfg, void* hip_stream);
 
-/* One MX GEMM (dtype_ab = SK_MXF8E4M3, SK_MXF4E2M1, SK_MXF6E2M3 or
- * SK_MXF6E3M2): as sk_gemm, with
+/* One MX GEMM (dtype_ab = SK_MXF8E4M3, SK_MXF8E5M2, SK_MXF4E2M1,
+ * SK_MXF6E2M3 or SK_MXF6E3M2): as sk_gemm, with
  *   C_out[i][j] = alpha*scale_a*scale_b * sum_k A[i][k] * 2^(sa[i][k/32]-127)
  *                                   * B[k][j] * 2^(sb[j][k/32]-127) + beta*C_in
- * where A, B hold e4m3 codes (MXFP4, MXFP6: packed codes), sa[i][b] = ((const uint8_t*)scale_a)[i*ld_scale_a
+ * where A, B hold e4m3 / e5m2 codes (MXFP4, MXFP6: packed codes), sa[i][b] = ((const uint8_t*)scale_a)[i*ld_scale_a
  * + b] and sb[j][b] = ((const uint8_t*)scale_b)[j*ld_scale_b + b] (device
  * memory; one E8M0 byte per 32 K-values of row i of A / column j of B).
  * The block scales are applied by the matrix cores (gfx950 scaled MFMA),

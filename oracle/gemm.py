@@ -106,6 +106,17 @@ def decode_e4m3fn(bits) -> np.ndarray:
     return np.where((e == 15) & (f == 7), np.nan, v)
 
 
+def decode_e5m2(bits) -> np.ndarray:
+    """uint8 OCP e5m2 codes -> exact float64 values: sign bit, 5 exponent
+    bits with bias 15, 2 mantissa bits; exponent 31 encodes infinity
+    (mantissa 0) and NaN (otherwise), as in IEEE binary16, whose upper byte
+    it is."""
+    sign, e, f, v = _decode_fields(bits, 5, 2, 15)
+    special = e == 31
+    v = np.where(special & (f == 0), np.where(sign == 1, -np.inf, np.inf), v)
+    return np.where(special & (f != 0), np.nan, v)
+
+
 def decode_f32(bits) -> np.ndarray:
     """uint32 IEEE binary32 codes -> exact float64 values (the widening of
     binary32 to binary64 is exact)."""
@@ -224,7 +235,8 @@ def gemm(M, N, K, a, lda, a_col_major, b, ldb, b_col_major, alpha=1.0,
 def mx_operand(codes, ld, scales, ld_s, rows, K, block=32, elem="e4m3"):
     """An MX operand stored K-contiguous (OCP MX block scaling): element
     (r, k) is decode(codes[r*ld + k]) * decode_e8m0(scales[r*ld_s +
-    k // block]), the elements e4m3 codes, or with elem="e2m1" FP4 codes or
+    k // block]), the elements e4m3 codes (elem="e5m2": e5m2 codes), or
+    with elem="e2m1" FP4 codes or
     elem="e2m3" / "e3m2" FP6 codes unpacked from bytes (ld then counts
     elements: row r starts at element r*ld).  Returns the rows x K float64 values; each is a decoded element
     times a power of two, so the result is exact."""
@@ -233,6 +245,8 @@ def mx_operand(codes, ld, scales, ld_s, rows, K, block=32, elem="e4m3"):
     elif elem in ("e2m3", "e3m2"):
         c = unpack_fp6(codes, 8 * np.asarray(codes).size // 6)
         x = decode_e2m3(c) if elem == "e2m3" else decode_e3m2(c)
+    elif elem == "e5m2":
+        x = decode_e5m2(np.asarray(codes).reshape(-1))
     else:
         x = decode_e4m3fn(np.asarray(codes).reshape(-1))
     s = decode_e8m0(np.asarray(scales).reshape(-1))
@@ -247,7 +261,7 @@ def gemm_mx(M, N, K, a_codes, lda, sa, ldsa, b_codes, ldb, sb, ldsb, alpha=1.0, 
             cin=None, rows=None, elem="e4m3"):
     """MX product C = alpha * sum_k A^(i,k) B^(k,j) + beta * Cin, with A
     row-major (row i at a_codes[i*lda]) and B column-major (column j at
-    b_codes[j*ldb]) element codes (e4m3 bytes, or with elem="e2m1" FP4
+    b_codes[j*ldb]) element codes (e4m3 or e5m2 bytes, or with elem="e2m1" FP4
     codes packed two per byte, lda/ldb counted in elements) and E8M0 scales
     of every 32 K-values of each row of A (sa[i*ldsa + k//32]) and column of
     B (sb[j*ldsb + k//32]): A^ and B^ are the block-scaled values

@@ -20,7 +20,9 @@ OUT_CODES = {torch.float32: _abi.SK_F32, torch.float16: _abi.SK_F16,
              torch.bfloat16: _abi.SK_BF16}
 K_PER_ITER = {_abi.SK_F32: 32, _abi.SK_F16: 64, _abi.SK_BF16: 64, _abi.SK_F8E4M3: 128,
               _abi.SK_MXF8E4M3: 128, _abi.SK_MXF4E2M1: 256, _abi.SK_MXF6E2M3: 128,
-              _abi.SK_MXF6E3M2: 128}
+              _abi.SK_MXF6E3M2: 128, _abi.SK_MXF8E5M2: 128}
+# MXFP8 element formats: torch code dtype -> sk_dtype
+MX8_CODES = {torch.float8_e4m3fn: _abi.SK_MXF8E4M3, torch.float8_e5m2: _abi.SK_MXF8E5M2}
 
 SEGMENT_FIELDS = ("wg", "problem", "tile", "tile_m", "tile_n", "k_begin", "k_end",
                   "role", "npeers")
@@ -225,13 +227,16 @@ def gemm_mx(A, B, scale_a, scale_b, C=None, *, alpha=1.0, beta=0.0, out=None,
             out_dtype=torch.float32, bias=None, activation="none", config=None,
             workspace=None, stream=None):
     """MXFP8 GEMM through sk_gemm_mx: A (M x K, row-major) and B (K x N,
-    column-major) hold e4m3 codes (torch.float8_e4m3fn); scale_a (M x >= K/32)
+    column-major) hold e4m3 or e5m2 codes (torch.float8_e4m3fn or
+    torch.float8_e5m2, both operands alike); scale_a (M x >= K/32)
     and scale_b (N x >= K/32) hold one E8M0 byte (uint8, 2^(e-127)) per 32
     K-values of each row of A and column of B, rows contiguous.
     out = act(alpha * sum_k (A * 2^(sa-127)) (B * 2^(sb-127)) + beta * C + bias)."""
     lib = load()
-    if A.dtype != torch.float8_e4m3fn or B.dtype != torch.float8_e4m3fn:
-        raise TypeError("MXFP8 operands are torch.float8_e4m3fn codes")
+    if A.dtype not in MX8_CODES or B.dtype != A.dtype:
+        raise TypeError("MXFP8 operands: torch.float8_e4m3fn or torch.float8_e5m2 codes, "
+                        "both alike")
+    dt = MX8_CODES[A.dtype]
     for s_ in (scale_a, scale_b):
         if s_.dtype != torch.uint8 or s_.dim() != 2 or s_.stride(1) != 1 or not s_.is_cuda:
             raise TypeError("block scales: 2-D uint8 GPU tensors with contiguous rows")
@@ -241,15 +246,17 @@ def gemm_mx(A, B, scale_a, scale_b, C=None, *, alpha=1.0, beta=0.0, out=None,
             (M, N), dtype=out_dtype, device=A.device)
     if beta != 0.0 and C is None:
         raise ValueError("beta != 0 needs C")
-    p = _set_epilogue(_problem(A, B, out, alpha, beta, 1.0, 1.0), bias, activation, A.device)
-    p.dtype_ab = _abi.SK_MXF8E4M3
+    # the descriptor takes its layout from byte views of the codes
+    p = _set_epilogue(_problem(A.view(torch.float8_e4m3fn), B.view(torch.float8_e4m3fn), out,
+                               alpha, beta, 1.0, 1.0), bias, activation, A.device)
+    p.dtype_ab = dt
     if scale_a.shape[0] != M or scale_b.shape[0] != N:
         raise ValueError("one scale row per row of A and per column of B")
     if config is None:
         tile = default_tile(M, N, A.shape[1], torch.float8_e4m3fn)
         config = Config(tile=tile if tile in ((256, 128), (128, 128)) else (128, 128))
     cfg = config
-    c = cfg.c_struct(_abi.SK_MXF8E4M3)
+    c = cfg.c_struct(dt)
     sp = _stream_ptr(stream)
     nbytes = ctypes.c_size_t()
     check("sk_workspace_size", lib.sk_workspace_size(ctypes.byref(p), 1, ctypes.byref(c),
@@ -658,12 +665,17 @@ class GroupedGemm:
                 if mx_format != "e2m1":
                     raise ValueError('mx_format must be "e2m1", "e2m3" or "e3m2"')
                 base = _mx4_problem(A, B, out, alpha, beta)
+            elif mx_scales is not None and A.dtype == torch.float8_e5m2:
+                base = _problem(A.view(torch.float8_e4m3fn), B.view(torch.float8_e4m3fn), out,
+                                alpha, beta, sa, sb, prefer)
             else:
                 base = _problem(A, B, out, alpha, beta, sa, sb, prefer)
             probs[i] = _set_epilogue(base, biases[i] if biases is not None else None, activation,
                                      A.device)
             if mx_scales is not None and not fp4:
-                probs[i].dtype_ab = _abi.SK_MXF8E4M3
+                if A.dtype not in MX8_CODES or B.dtype != A.dtype:
+                    raise TypeError("MXFP8 operands: float8_e4m3fn or float8_e5m2 codes")
+                probs[i].dtype_ab = MX8_CODES[A.dtype]
             ptrs["A"][i] = A.data_ptr()
             ptrs["B"][i] = B.data_ptr()
             ptrs["Cin"][i] = Cin.data_ptr() if (Cin is not None and beta != 0.0) else None
@@ -672,7 +684,8 @@ class GroupedGemm:
         M0, N0, K0 = probs[0].M, probs[0].N, probs[0].K
         if config is None:
             dt0 = (torch.bfloat16 if probs[0].dtype_ab == _abi.SK_MXF4E2M1 else
-                   torch.float8_e4m3fn if probs[0].dtype_ab in MX6_FORMATS.values() else
+                   torch.float8_e4m3fn if probs[0].dtype_ab in MX6_FORMATS.values() or
+                   probs[0].dtype_ab == _abi.SK_MXF8E5M2 else
                    problems[0][0].dtype)
             tile = default_tile(M0, N0, K0, dt0)
             if mx_scales is not None and tile not in ((256, 128), (128, 128)):

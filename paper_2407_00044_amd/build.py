@@ -22,7 +22,8 @@ OUT = os.path.join(HERE, "libstreamk.so")
 BUILD = os.path.join(ROOT, "_build")
 
 ARCH = "gfx950"
-DTYPES = {0: "f32", 1: "f16", 2: "bf16", 3: "e4m3", 4: "mx8", 5: "mx4", 6: "mx6", 7: "mx6e3m2"}
+DTYPES = {0: "f32", 1: "f16", 2: "bf16", 3: "e4m3", 4: "mx8", 5: "mx4", 6: "mx6", 7: "mx6e3m2",
+          8: "mx8e5m2"}
 LAYOUTS = {0: "r", 1: "c"}
 
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",

@@ -108,7 +108,7 @@ static sk_status resident_per_cu(const KernelEntry* ke, int* per_cu) {
 static sk_status check_problem(const sk_problem& p) {
   if (p.M < 0 || p.N < 0 || p.K < 0) return SK_ERR_INVALID_ARG;
   if (p.M > kMaxIndex || p.N > kMaxIndex || p.K > kMaxIndex) return SK_ERR_UNSUPPORTED;
-  if (p.dtype_ab < 0 || p.dtype_ab > 7) return SK_ERR_UNSUPPORTED;
+  if (p.dtype_ab < 0 || p.dtype_ab > 8) return SK_ERR_UNSUPPORTED;
   if (p.dtype_c < 0 || p.dtype_c > 2) return SK_ERR_UNSUPPORTED;
   if ((p.layout_a != SK_ROW_MAJOR && p.layout_a != SK_COL_MAJOR) ||
       (p.layout_b != SK_ROW_MAJOR && p.layout_b != SK_COL_MAJOR))

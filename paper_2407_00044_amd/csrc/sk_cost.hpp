@@ -63,8 +63,8 @@ inline double auto_margin(int32_t dt) { return dt == 0 ? kAutoMarginF32 : kAutoM
 // Row of (input type, tile); f16 takes bf16's.  A tile without a row takes
 // the row of the same type whose tile area is closest.
 inline const CostRow* cost_row(int32_t dt, int32_t bm, int32_t bn) {
-  // f16 and MXFP4 (four 16-byte steps per iteration) as bf16, MXFP8 and
-  // MXFP6 (two steps) as e4m3
+  // f16 and MXFP4 (four 16-byte steps per iteration) as bf16, MXFP8 (both
+  // element formats) and MXFP6 (two steps) as e4m3
   const int32_t d = (dt == 1 || dt == 5) ? 2 : dt >= 4 ? 3 : dt;
   const CostRow* best = nullptr;
   int64_t best_gap = 0;

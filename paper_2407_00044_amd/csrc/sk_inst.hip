@@ -19,8 +19,8 @@
 // f32: 128x128x32 (the 512^3 Stream-K configuration)
 SK_INST(128, 128, 2, 4)
 #elif SK_DT >= 4
-// MXFP8 (e4m3), MXFP4 (e2m1) and MXFP6 (e2m3, e3m2) with E8M0 block
-// scales: K-contiguous operands only
+// MXFP8 (e4m3, e5m2), MXFP4 (e2m1) and MXFP6 (e2m3, e3m2) with E8M0
+// block scales: K-contiguous operands only
 #if SK_LA == 0 && SK_LB == 1
 SK_INST(256, 128, 4, 8)
 SK_INST(128, 128, 4, 8)

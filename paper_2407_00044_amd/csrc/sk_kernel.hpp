@@ -49,16 +49,17 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 typedef int v2i __attribute__((ext_vector_type(2)));
 
 enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3, DT_MX8 = 4, DT_MX4 = 5, DT_MX6 = 6,
-       DT_MX6E3 = 7 };
+       DT_MX6E3 = 7, DT_MX8E5 = 8 };
 // 8-bit e4m3 elements: plain (per-tensor scales, applied in the epilogue) or
 // MXFP8 (an E8M0 scale per 32 K-values of each row of A and column of B,
 // applied by the matrix core)
-constexpr bool is_f8(int dt) { return dt == DT_F8 || dt == DT_MX8; }
+constexpr bool is_mx8(int dt) { return dt == DT_MX8 || dt == DT_MX8E5; }
+constexpr bool is_f8(int dt) { return dt == DT_F8 || is_mx8(dt); }
 // MXFP4: E2M1 elements packed two per byte, with MXFP8's block scales.  The
 // kernels see its operands as bytes (K, lda, ldb in bytes, 256 elements per
 // 128-byte iteration).
 constexpr bool is_mx6(int dt) { return dt == DT_MX6 || dt == DT_MX6E3; }
-constexpr bool is_mx(int dt) { return dt == DT_MX8 || dt == DT_MX4 || is_mx6(dt); }
+constexpr bool is_mx(int dt) { return is_mx8(dt) || dt == DT_MX4 || is_mx6(dt); }
 enum { L_ROW = 0, L_COL = 1 };
 enum { R_FULL = 0, R_FINISH = 1, R_PARTIAL = 2, R_DP = 3 };
 
@@ -675,6 +676,8 @@ struct Frag { u32x4 c[is_f8(DT) ? 2 : 1]; };
 // MXFP8: the lane's 32 K-values and the E8M0 scale of their block
 template <>
 struct Frag<DT_MX8> { u32x4 c[2]; int32_t s; };
+template <>
+struct Frag<DT_MX8E5> { u32x4 c[2]; int32_t s; };
 // MXFP4: the lane's 32 K-values (16 bytes) and the scale of their block
 template <>
 struct Frag<DT_MX4> { u32x4 c[1]; int32_t s; };
@@ -724,13 +727,15 @@ __device__ __forceinline__ void mma(v16f& acc, const Frag<DT>& a, const Frag<DT>
     v8i bv = __builtin_bit_cast(v8i, b.c);
     // operand format 0 (e4m3) for A and B; E8M0 scale 127 = 2^0
     acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, 127, 0, 127);
-  } else if constexpr (DT == DT_MX8) {
+  } else if constexpr (is_mx8(DT)) {
     // MXFP8: each lane's 32 K-values (one block of its row of A / column of
     // B) carry that block's E8M0 scale; the matrix core multiplies every
     // product by 2^(sa-127) * 2^(sb-127)
     v8i av = __builtin_bit_cast(v8i, a.c);
     v8i bv = __builtin_bit_cast(v8i, b.c);
-    acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, a.s, 0, b.s);
+    // operand format 0 (e4m3) or 1 (e5m2)
+    constexpr int F = DT == DT_MX8 ? 0 : 1;
+    acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, F, F, 0, a.s, 0, b.s);
   } else if constexpr (is_mx6(DT)) {
     // MXFP6 (operand format 2, e2m3, or 3, e3m2): 24 bytes per lane, the
     // lane's block of 32 K-values with its scale (the lane half's 32 values
@@ -983,7 +988,7 @@ struct FragReader {
       f.s = (s & 1) ? 0 : (int32_t)(*(const uint32_t*)(op + sb + 128 * i) >> (8 * half));
     } else {
       int lo[2];
-      if constexpr (C::DT == DT_MX8) {
+      if constexpr (is_mx8(C::DT)) {
         lo[0] = frag_lane_off(l32, 4 * s + half);
         lo[1] = frag_lane_off(l32, 4 * s + 2 + half);
       } else if constexpr (is_f8(C::DT)) {
@@ -999,7 +1004,7 @@ struct FragReader {
       // bytes once, shifted to this lane's half; step 1 takes them from step
       // 0.s fragment (in step_fenced), so each iteration reads the scales
       // of a fragment with one LDS instruction instead of two.
-      if constexpr (C::DT == DT_MX8)
+      if constexpr (is_mx8(C::DT))
         f.s = (s & 1) ? 0 : (int32_t)(*(const uint32_t*)(op + sb + 128 * i) >> (8 * half));
       // MXFP4: step s covers K bytes 32s .. 32s+31 of the row, lane half h
       // the 16-byte block 2s + h of them (the scaled matrix core takes a
@@ -1205,7 +1210,7 @@ __device__ __forceinline__ void step_fenced(
       read_frag_n<C>(ra, rb, rda, rdb, opA, opB, rs, n);
       // MXFP8, step 1 read during step 0 of the same iteration: its scale
       // is byte 2 of step 0's (bytes 2s + half of the row's 4)
-      if constexpr (C::DT == DT_MX8 || is_mx6(C::DT)) {
+      if constexpr (is_mx8(C::DT) || is_mx6(C::DT)) {
         if (rs & 1) {
           if (n < 1) ra[0].s = fa[0].s >> 16;
           else if (n <= C::FN) rb[n - 1].s = fb[n - 1].s >> 16;

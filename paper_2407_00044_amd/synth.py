@@ -52,13 +52,19 @@ def fp8_scaled(x64):
     return q, scale
 
 
-def mx_quantize(x64, block=32):
+E5M2_MAX = 57344.0   # largest finite OCP e5m2 value
+_MX8 = {"e4m3": (torch.float8_e4m3fn, E4M3_MAX), "e5m2": (torch.float8_e5m2, E5M2_MAX)}
+
+
+def mx_quantize(x64, block=32, elem="e4m3"):
     """MX quantisation of rows along K: for each block of `block` consecutive
-    K-values of a row, the shared exponent X = ceil(log2(amax / 448)) (the
-    smallest power of two that brings the block into the e4m3fn range, so
-    nothing saturates; amax 0 gives X = 0) is stored as the E8M0 code
-    X + 127, and the elements become RNE_e4m3fn(x / 2^X).  Returns (e4m3 codes
-    tensor R x K, uint8 scale array R x ceil(K/block))."""
+    K-values of a row, the shared exponent X = ceil(log2(amax / emax)) (the
+    smallest power of two that brings the block into the element range, so
+    nothing saturates; emax 448 for e4m3, 57344 for e5m2; amax 0 gives
+    X = 0) is stored as the E8M0 code X + 127, and the elements become
+    RNE(x / 2^X) in the element format.  Returns (codes tensor R x K, uint8
+    scale array R x ceil(K/block))."""
+    tdtype, E4M3_MAX = _MX8[elem]   # noqa: N806 (the element format's max)
     x = np.asarray(x64, dtype=np.float64)
     R, K = x.shape
     nb = -(-K // block)
@@ -76,7 +82,7 @@ def mx_quantize(x64, block=32):
         e[:, b] = X + 127
         q[:, b * block:(b + 1) * block] = np.clip(blk / np.ldexp(1.0, X)[:, None], -E4M3_MAX,
                                                   E4M3_MAX)
-    codes_t = torch.from_numpy(np.ascontiguousarray(q)).to(torch.float8_e4m3fn)
+    codes_t = torch.from_numpy(np.ascontiguousarray(q)).to(tdtype)
     return codes_t, e.astype(np.uint8)
 
 

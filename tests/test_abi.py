@@ -391,3 +391,28 @@ def test_mx6_entry_point_host_checks():
                            dt, _abi.SK_F32, 1.0, 0.0, 1.0, 1.0)
         assert lib.sk_gemm(ctypes.byref(p), fake, fake, None, fake, None, 0, ctypes.byref(cfg),
                            None) == _abi.SK_ERR_INVALID_ARG
+
+
+def test_mx8_e5m2_entry_point_host_checks():
+    # MXFP8 with e5m2 elements takes the e4m3 rules; a type past the last
+    # one is refused; the binding refuses mixed element formats
+    lib = _abi.load()
+    fake = ctypes.c_void_p(1 << 20)
+    dt = _abi.SK_MXF8E5M2
+    cfg = sk.Config(tile=(128, 128), num_cu=8).c_struct(dt)
+    assert cfg.block_k == 128
+
+    def call(M, N, K, la=_abi.SK_ROW_MAJOR, dtype=dt, lds=8):
+        p = _abi.SkProblem(M, N, K, la, _abi.SK_COL_MAJOR, K if la == _abi.SK_ROW_MAJOR else M,
+                           K, N, dtype, _abi.SK_F32, 1.0, 0.0, 1.0, 1.0)
+        return lib.sk_gemm_mx(ctypes.byref(p), fake, fake, fake, lds, fake, lds, None, fake,
+                              None, 0, ctypes.byref(cfg), None)
+    assert call(256, 256, 192) == _abi.SK_ERR_UNSUPPORTED                  # K % 128
+    assert call(256, 256, 256, la=_abi.SK_COL_MAJOR) == _abi.SK_ERR_UNSUPPORTED
+    assert call(256, 256, 256, lds=4) == _abi.SK_ERR_INVALID_ARG          # scales < K/32
+    assert call(256, 256, 256, dtype=dt + 1) == _abi.SK_ERR_UNSUPPORTED    # no such type
+    a = torch.zeros((64, 128), dtype=torch.float8_e4m3fn)
+    b = torch.zeros((128, 64), dtype=torch.float8_e5m2)
+    s = torch.zeros((64, 8), dtype=torch.uint8)
+    with pytest.raises(TypeError):
+        sk.gemm_mx(a, b, s, s)

@@ -153,6 +153,32 @@ def test_decode_e4m3fn_all_codes():
     assert np.nanmax(vals) == 448.0 and np.isnan(vals).sum() == 2
 
 
+def test_decode_e5m2_all_codes():
+    # against torch's e5m2, then the published extremes of the OCP format,
+    # then the identity with the upper byte of an IEEE binary16 code
+    codes = np.arange(256, dtype=np.uint8)
+    _exhaustive(codes, np.uint8, torch.float8_e5m2, og.decode_e5m2)
+    vals = og.decode_e5m2(codes)
+    assert vals[0x7B] == 57344.0 and np.nanmax(vals[np.isfinite(vals)]) == 57344.0
+    assert vals[0x04] == 2.0 ** -14 and vals[0x01] == 2.0 ** -16 and vals[0x03] == 0.75 * 2 ** -14
+    assert vals[0x7C] == np.inf and vals[0xFC] == -np.inf and np.isnan(vals).sum() == 6
+    assert vals[0x3C] == 1.0 and vals[0xC0] == -2.0 and vals[0x80] == 0 and np.signbit(vals[0x80])
+    f16 = og.decode_f16(codes.astype(np.uint16) << 8)
+    assert np.array_equal(np.isnan(f16), np.isnan(vals))
+    assert np.array_equal(f16[~np.isnan(f16)], vals[~np.isnan(vals)])
+
+
+def test_mx_operand_e5m2_scales_exactly():
+    # a block of e5m2 codes times 2^(s - 127), s per 32 elements
+    rng = np.random.default_rng(12)
+    c = rng.integers(0, 256, size=(3, 64), dtype=np.uint8)
+    c[(c & 0x7C) == 0x7C] = 0x3C             # no infinities or NaN in this pin
+    s = np.array([[120, 130], [127, 127], [0, 254]], dtype=np.uint8)
+    got = og.mx_operand(c.reshape(-1), 64, s.reshape(-1), 2, 3, 64, elem="e5m2")
+    want = og.decode_e5m2(c) * np.repeat(np.ldexp(1.0, s.astype(int) - 127), 32, axis=1)
+    assert np.array_equal(got, want)
+
+
 def test_decode_f32_roundtrip():
     rng = np.random.default_rng(6)
     x = rng.standard_normal(1000).astype(np.float32)
