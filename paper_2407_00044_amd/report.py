@@ -237,9 +237,10 @@ def per_dtype(dev, reps=5, shape=(3840, 4096, 4096)):
 
 def mxfp8(dev, reps=5, shape=(3840, 4096, 4096), tile=(256, 128)):
     """MXFP8 (e4m3 elements with an E8M0 scale per 32 K-values, applied by
-    the matrix cores) at the headline shape, beside plain e4m3 with
-    per-tensor scales on the same tile: Stream-K (two-tile hybrid), the auto
-    policy and the data-parallel grid; % of the dense FP8 MFMA peak."""
+    the matrix cores) at the headline shape, beside MXFP8 with e5m2
+    elements and plain e4m3 with per-tensor scales on the same tile:
+    Stream-K (two-tile hybrid), the auto policy and the data-parallel grid;
+    % of the dense FP8 MFMA peak."""
     M, N, K = shape
     ws = api.Workspace(dev)
     ws.get(96 << 20, torch.cuda.current_stream().cuda_stream)
@@ -247,6 +248,10 @@ def mxfp8(dev, reps=5, shape=(3840, 4096, 4096), tile=(256, 128)):
     qb, sb = synth.mx_quantize(synth.normal((N, K), 62))
     A, B = qa.to(dev), qb.to(dev).t()
     SA, SB = torch.from_numpy(sa).to(dev), torch.from_numpy(sb).to(dev)
+    qa5, sa5 = synth.mx_quantize(synth.normal((M, K), 61), elem="e5m2")
+    qb5, sb5 = synth.mx_quantize(synth.normal((N, K), 62), elem="e5m2")
+    A5, B5 = qa5.to(dev), qb5.to(dev).t()
+    SA5, SB5 = torch.from_numpy(sa5).to(dev), torch.from_numpy(sb5).to(dev)
     out = torch.empty((M, N), device=dev)
     fl = 2.0 * M * N * K
     cfgs = {"stream_k": api.Config(tile=tile, mode="hybrid"),
@@ -256,11 +261,15 @@ def mxfp8(dev, reps=5, shape=(3840, 4096, 4096), tile=(256, 128)):
            for c in cfgs.values()]
     fns += [(lambda c: (lambda: api.gemm(A, B, out=out, config=c, workspace=ws)))(c)
             for c in cfgs.values()]
+    fns += [(lambda c: (lambda: api.gemm_mx(A5, B5, SA5, SB5, out=out, config=c,
+                                            workspace=ws)))(c) for c in cfgs.values()]
     ts = _time_all(fns, reps)
     res = {"workload": f"{M}x{N}x{K}, A row-major, B column-major, FP32 output, tile "
-                       f"{tile[0]}x{tile[1]}", "mxfp8": {}, "e4m3_per_tensor": {}}
+                       f"{tile[0]}x{tile[1]}", "mxfp8": {}, "mxfp8_e5m2": {},
+           "e4m3_per_tensor": {}}
     for i, n in enumerate(cfgs):
-        for key, t in (("mxfp8", ts[i]), ("e4m3_per_tensor", ts[i + 3])):
+        for key, t in (("mxfp8", ts[i]), ("e4m3_per_tensor", ts[i + 3]),
+                       ("mxfp8_e5m2", ts[i + 6])):
             res[key][n] = {"tflops": _tf(fl, t), "pct_peak": round(100 * fl / t / 1e9 / 5033.2, 2)}
     return res
 
