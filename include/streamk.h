@@ -86,6 +86,8 @@ typedef enum {
  * bias 3 and 2 mantissa bits, max 28; no infinities or NaNs) packed
  * little-endian, element k of a row at bits 6k .. 6k+5 of the row's bytes
  * (a block of 32 elements is 24 bytes), with the same E8M0 block scales.
+ * SK_F8E5M2 is OCP e5m2 with per-tensor scales, taken as SK_F8E4M3 is
+ * (every layout, the same tiles).
  * SK_MXF8E5M2 is OCP MXFP8 with e5m2 elements (sign, 5 exponent bits with
  * bias 15, 2 mantissa bits; exponent 31 holds infinities and NaNs; max
  * finite 57344), one byte each, with the same block scales.
@@ -93,7 +95,7 @@ typedef enum {
  * every input type. */
 typedef enum {
   SK_F32 = 0, SK_F16 = 1, SK_BF16 = 2, SK_F8E4M3 = 3, SK_MXF8E4M3 = 4, SK_MXF4E2M1 = 5,
-  SK_MXF6E2M3 = 6, SK_MXF6E3M2 = 7, SK_MXF8E5M2 = 8
+  SK_MXF6E2M3 = 6, SK_MXF6E3M2 = 7, SK_MXF8E5M2 = 8, SK_F8E5M2 = 9
 } sk_dtype;
 typedef enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 } sk_layout;
 

@@ -27,7 +27,7 @@ SK_ERR_DEVICE_TIMEOUT = -7
 
 # dtypes / layouts / modes / roles
 SK_F32, SK_F16, SK_BF16, SK_F8E4M3, SK_MXF8E4M3, SK_MXF4E2M1 = 0, 1, 2, 3, 4, 5
-SK_MXF6E2M3, SK_MXF6E3M2, SK_MXF8E5M2 = 6, 7, 8
+SK_MXF6E2M3, SK_MXF6E3M2, SK_MXF8E5M2, SK_F8E5M2 = 6, 7, 8, 9
 SK_ROW_MAJOR, SK_COL_MAJOR = 0, 1
 SK_MODE_HYBRID, SK_MODE_SK, SK_MODE_DP, SK_MODE_AUTO = 0, 1, 2, 3
 SK_ROLE_FULL, SK_ROLE_FINISH, SK_ROLE_PARTIAL, SK_ROLE_DP = 0, 1, 2, 3

@@ -15,12 +15,14 @@ from ._abi import (SK_COL_MAJOR, SK_ROW_MAJOR, SkConfig, SkDebug, SkGroupedPlan,
                    SkPlanInfo, SkProblem, SkSegment, check, load)
 
 DTYPE_CODES = {torch.float32: _abi.SK_F32, torch.float16: _abi.SK_F16,
-               torch.bfloat16: _abi.SK_BF16, torch.float8_e4m3fn: _abi.SK_F8E4M3}
+               torch.bfloat16: _abi.SK_BF16, torch.float8_e4m3fn: _abi.SK_F8E4M3,
+               torch.float8_e5m2: _abi.SK_F8E5M2}
 OUT_CODES = {torch.float32: _abi.SK_F32, torch.float16: _abi.SK_F16,
              torch.bfloat16: _abi.SK_BF16}
 K_PER_ITER = {_abi.SK_F32: 32, _abi.SK_F16: 64, _abi.SK_BF16: 64, _abi.SK_F8E4M3: 128,
               _abi.SK_MXF8E4M3: 128, _abi.SK_MXF4E2M1: 256, _abi.SK_MXF6E2M3: 128,
-              _abi.SK_MXF6E3M2: 128, _abi.SK_MXF8E5M2: 128}
+              _abi.SK_MXF6E3M2: 128, _abi.SK_MXF8E5M2: 128,
+              _abi.SK_F8E5M2: 128}
 # MXFP8 element formats: torch code dtype -> sk_dtype
 MX8_CODES = {torch.float8_e4m3fn: _abi.SK_MXF8E4M3, torch.float8_e5m2: _abi.SK_MXF8E5M2}
 
@@ -71,7 +73,7 @@ def default_tile(M, N, K, dtype, cus=256):
     code = DTYPE_CODES[dtype]
     if code == _abi.SK_F32:
         return (128, 128)
-    if code == _abi.SK_F8E4M3 and M <= 64:
+    if code in (_abi.SK_F8E4M3, _abi.SK_F8E5M2) and M <= 64:
         return (64, 128)
     iters = max(1, -(-K // K_PER_ITER[code]))
     t256 = -(-M // 256) * -(-N // 256)
@@ -81,7 +83,7 @@ def default_tile(M, N, K, dtype, cus=256):
     t256x128 = -(-M // 256) * -(-N // 128)
     if M >= 256 and t256x128 * 10 >= cus * 9:
         return (256, 128)
-    if code == _abi.SK_F8E4M3 and M >= 256 and t256x128 * iters >= 32 * cus:
+    if code in (_abi.SK_F8E4M3, _abi.SK_F8E5M2) and M >= 256 and t256x128 * iters >= 32 * cus:
         return (256, 128)
     return (128, 128)
 
@@ -819,11 +821,11 @@ def pack_pays(M, N, K, dtype):
     (and M*N*K >= 2^35 for e4m3) packs every product that gains and none that
     loses more than 1%."""
     code = DTYPE_CODES[dtype] if isinstance(dtype, torch.dtype) else dtype
-    if code not in (_abi.SK_F16, _abi.SK_BF16, _abi.SK_F8E4M3):
+    if code not in (_abi.SK_F16, _abi.SK_BF16, _abi.SK_F8E4M3, _abi.SK_F8E5M2):
         return False
     if K < 2048 or M * N < (1 << 22):
         return False
-    return code != _abi.SK_F8E4M3 or M * N * K >= (1 << 35)
+    return code not in (_abi.SK_F8E4M3, _abi.SK_F8E5M2) or M * N * K >= (1 << 35)
 
 
 class StreamKLinearFn(torch.autograd.Function):

@@ -23,7 +23,7 @@ BUILD = os.path.join(ROOT, "_build")
 
 ARCH = "gfx950"
 DTYPES = {0: "f32", 1: "f16", 2: "bf16", 3: "e4m3", 4: "mx8", 5: "mx4", 6: "mx6", 7: "mx6e3m2",
-          8: "mx8e5m2"}
+          8: "mx8e5m2", 9: "e5m2"}
 LAYOUTS = {0: "r", 1: "c"}
 
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
@@ -42,7 +42,7 @@ def _units():
     for dt, dn in DTYPES.items():
         for la, an in LAYOUTS.items():
             for lb, bn in LAYOUTS.items():
-                if dt >= 4 and (la, lb) != (0, 1):
+                if 4 <= dt <= 8 and (la, lb) != (0, 1):
                     continue   # MX formats: K-contiguous operands only
                 units.append((f"sk_inst_{dn}_{an}{bn}", os.path.join(CSRC, "sk_inst.hip"),
                               [f"-DSK_DT={dt}", f"-DSK_LA={la}", f"-DSK_LB={lb}"]))

@@ -108,7 +108,7 @@ static sk_status resident_per_cu(const KernelEntry* ke, int* per_cu) {
 static sk_status check_problem(const sk_problem& p) {
   if (p.M < 0 || p.N < 0 || p.K < 0) return SK_ERR_INVALID_ARG;
   if (p.M > kMaxIndex || p.N > kMaxIndex || p.K > kMaxIndex) return SK_ERR_UNSUPPORTED;
-  if (p.dtype_ab < 0 || p.dtype_ab > 8) return SK_ERR_UNSUPPORTED;
+  if (p.dtype_ab < 0 || p.dtype_ab > 9) return SK_ERR_UNSUPPORTED;
   if (p.dtype_c < 0 || p.dtype_c > 2) return SK_ERR_UNSUPPORTED;
   if ((p.layout_a != SK_ROW_MAJOR && p.layout_a != SK_COL_MAJOR) ||
       (p.layout_b != SK_ROW_MAJOR && p.layout_b != SK_COL_MAJOR))
@@ -593,8 +593,9 @@ static sk_status gemm_common(const sk_problem* p, const void* A, const void* B, 
                              void* Cout, void* ws, size_t ws_bytes_, const sk_config* cfg,
                              const sk_debug* dbg, void* stream, const MxScales* mx = nullptr) {
   if (p == nullptr) return SK_ERR_INVALID_ARG;
+  if (p->dtype_ab < 0 || p->dtype_ab > SK_F8E5M2) return SK_ERR_UNSUPPORTED;
   // MX inputs need their block scales (sk_gemm_mx); others take none
-  const bool is_mx = p->dtype_ab >= SK_MXF8E4M3;
+  const bool is_mx = p->dtype_ab >= SK_MXF8E4M3 && p->dtype_ab <= SK_MXF8E5M2;
   if (is_mx != (mx != nullptr)) return SK_ERR_INVALID_ARG;
   Plan P;
   sk_status st = plan_problems(p, 1, cfg, &P);
@@ -868,7 +869,7 @@ static sk_status grouped_prepare(const sk_problem* probs, const void* const* A,
   sk_status st = plan_problems(probs, nprobs, cfg, &P);
   if (st != SK_OK) return st;
   // MX problems need their block scales (sk_grouped_prepare_mx); others take none
-  const bool mx = probs[0].dtype_ab >= SK_MXF8E4M3;
+  const bool mx = probs[0].dtype_ab >= SK_MXF8E4M3 && probs[0].dtype_ab <= SK_MXF8E5M2;
   if (mx != (sA != nullptr && ldsa != nullptr && sB != nullptr && ldsb != nullptr))
     return SK_ERR_INVALID_ARG;
   if (desc_bytes < (size_t)nprobs * sizeof(ProbDesc)) return SK_ERR_WORKSPACE;

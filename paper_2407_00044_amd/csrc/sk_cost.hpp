@@ -64,7 +64,7 @@ inline double auto_margin(int32_t dt) { return dt == 0 ? kAutoMarginF32 : kAutoM
 // the row of the same type whose tile area is closest.
 inline const CostRow* cost_row(int32_t dt, int32_t bm, int32_t bn) {
   // f16 and MXFP4 (four 16-byte steps per iteration) as bf16, MXFP8 (both
-  // element formats) and MXFP6 (two steps) as e4m3
+  // element formats), per-tensor e5m2 and MXFP6 (two steps) as e4m3
   const int32_t d = (dt == 1 || dt == 5) ? 2 : dt >= 4 ? 3 : dt;
   const CostRow* best = nullptr;
   int64_t best_gap = 0;

@@ -18,7 +18,7 @@
 #if SK_DT == 0
 // f32: 128x128x32 (the 512^3 Stream-K configuration)
 SK_INST(128, 128, 2, 4)
-#elif SK_DT >= 4
+#elif SK_DT >= 4 && SK_DT <= 8
 // MXFP8 (e4m3, e5m2), MXFP4 (e2m1) and MXFP6 (e2m3, e3m2) with E8M0
 // block scales: K-contiguous operands only
 #if SK_LA == 0 && SK_LB == 1
@@ -26,7 +26,7 @@ SK_INST(256, 128, 4, 8)
 SK_INST(128, 128, 4, 8)
 #endif
 #else
-// f16 / bf16 / e4m3: large tiles for compute-bound shapes, smaller ones for
+// f16 / bf16 / e4m3 / e5m2: large tiles for compute-bound shapes, smaller ones for
 // small or skinny problems.  Both operands are copied LDS-direct in every
 // layout (M/N-major ones read back with transposing LDS reads), and the
 // three large tiles run 8 waves, two per SIMD, which hide LDS and load
@@ -35,7 +35,7 @@ SK_INST(128, 128, 4, 8)
 SK_INST(256, 256, 2, 8)
 SK_INST(256, 128, 4, 8)
 SK_INST(128, 128, 4, 8)
-#if SK_DT == 3
+#if SK_DT == 3 || SK_DT == 9
 SK_INST(64, 128, 2, 4)
 #endif
 #endif

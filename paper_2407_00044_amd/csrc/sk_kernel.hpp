@@ -49,12 +49,13 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 typedef int v2i __attribute__((ext_vector_type(2)));
 
 enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3, DT_MX8 = 4, DT_MX4 = 5, DT_MX6 = 6,
-       DT_MX6E3 = 7, DT_MX8E5 = 8 };
+       DT_MX6E3 = 7, DT_MX8E5 = 8, DT_F8E5 = 9 };
 // 8-bit e4m3 elements: plain (per-tensor scales, applied in the epilogue) or
 // MXFP8 (an E8M0 scale per 32 K-values of each row of A and column of B,
 // applied by the matrix core)
 constexpr bool is_mx8(int dt) { return dt == DT_MX8 || dt == DT_MX8E5; }
-constexpr bool is_f8(int dt) { return dt == DT_F8 || is_mx8(dt); }
+constexpr bool is_f8pt(int dt) { return dt == DT_F8 || dt == DT_F8E5; }   // per-tensor scales
+constexpr bool is_f8(int dt) { return is_f8pt(dt) || is_mx8(dt); }
 // MXFP4: E2M1 elements packed two per byte, with MXFP8's block scales.  The
 // kernels see its operands as bytes (K, lda, ldb in bytes, 256 elements per
 // 128-byte iteration).
@@ -722,11 +723,12 @@ __device__ __forceinline__ void mma(v16f& acc, const Frag<DT>& a, const Frag<DT>
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a.c[0]),
                                                   __builtin_bit_cast(v8bf, b.c[0]), acc, 0, 0,
                                                   0);
-  } else if constexpr (DT == DT_F8) {
+  } else if constexpr (is_f8pt(DT)) {
     v8i av = __builtin_bit_cast(v8i, a.c);
     v8i bv = __builtin_bit_cast(v8i, b.c);
-    // operand format 0 (e4m3) for A and B; E8M0 scale 127 = 2^0
-    acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, 127, 0, 127);
+    // operand format 0 (e4m3) or 1 (e5m2) for A and B; E8M0 scale 127 = 2^0
+    constexpr int F = DT == DT_F8 ? 0 : 1;
+    acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, F, F, 0, 127, 0, 127);
   } else if constexpr (is_mx8(DT)) {
     // MXFP8: each lane's 32 K-values (one block of its row of A / column of
     // B) carry that block's E8M0 scale; the matrix core multiplies every
@@ -782,7 +784,7 @@ struct Cfg {
   // M/N-contiguous 16-bit operands are read with transposing LDS reads
   // (e4m3: tiles of at least 128 rows)
   static constexpr bool TR16 = (DT == DT_F16 || DT == DT_BF16) && SK_MN_TR && SK_KMAJOR_DMA;
-  static constexpr bool TR8 = DT == DT_F8 && SK_MN_TR && SK_KMAJOR_DMA;
+  static constexpr bool TR8 = is_f8pt(DT) && SK_MN_TR && SK_KMAJOR_DMA;
   static constexpr bool TRA = LA == L_COL && (TR16 || (TR8 && BM >= 128));
   static constexpr bool TRB = LB == L_ROW && (TR16 || (TR8 && BN >= 128));
   // Both operands copied LDS-direct: as many stages as fit in 160 KiB (at

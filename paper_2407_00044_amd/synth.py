@@ -14,9 +14,10 @@ import torch
 E4M3_MAX = 448.0   # largest finite OCP e4m3fn value
 
 TORCH_DTYPES = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16,
-                "e4m3": torch.float8_e4m3fn}
+                "e4m3": torch.float8_e4m3fn, "e5m2": torch.float8_e5m2}
 CODE_VIEW = {"f32": (torch.int32, np.uint32), "f16": (torch.int16, np.uint16),
-             "bf16": (torch.int16, np.uint16), "e4m3": (torch.uint8, np.uint8)}
+             "bf16": (torch.int16, np.uint16), "e4m3": (torch.uint8, np.uint8),
+             "e5m2": (torch.uint8, np.uint8)}
 
 
 def rng(seed):
@@ -41,14 +42,17 @@ def round_to(x64, dtype):
     return torch.from_numpy(np.ascontiguousarray(x64)).to(TORCH_DTYPES[dtype])
 
 
-def fp8_scaled(x64):
-    """Per-tensor amax scaling into the e4m3fn range.
+def fp8_scaled(x64, elem="e4m3"):
+    """Per-tensor amax scaling into the e4m3fn range (elem="e5m2": the e5m2
+    range).
 
-    scale = max|x| / 448 (as a float32), q = RNE_e4m3fn(x / scale); |q| <= 448
-    by construction, so nothing saturates.  Returns (q tensor, scale float)."""
+    scale = max|x| / emax (as a float32; emax 448, e5m2 57344), q = RNE(x /
+    scale) in the element format; |q| <= emax by construction, so nothing
+    saturates.  Returns (q tensor, scale float)."""
+    tdtype, emax = _MX8[elem]
     amax = float(np.max(np.abs(x64))) if x64.size else 0.0
-    scale = float(np.float32(amax / E4M3_MAX)) if amax > 0 else 1.0
-    q = torch.from_numpy(np.ascontiguousarray(x64 / scale)).to(torch.float8_e4m3fn)
+    scale = float(np.float32(amax / emax)) if amax > 0 else 1.0
+    q = torch.from_numpy(np.ascontiguousarray(x64 / scale)).to(tdtype)
     return q, scale
 
 
@@ -223,8 +227,9 @@ def place(t, col_major=False, ld=None, device=None, fill=0):
     if ld < inner:
         raise ValueError("leading dimension smaller than the matrix extent")
     outer = cols if col_major else rows
-    store = torch.full((outer, ld), fill, dtype=t.dtype) if t.dtype != torch.float8_e4m3fn \
-        else torch.zeros((outer, ld), dtype=torch.uint8).view(torch.float8_e4m3fn)
+    store = torch.full((outer, ld), fill, dtype=t.dtype) \
+        if t.dtype not in (torch.float8_e4m3fn, torch.float8_e5m2) \
+        else torch.zeros((outer, ld), dtype=torch.uint8).view(t.dtype)
     if col_major:
         store[:, :rows] = t.t()
     else:

@@ -410,9 +410,22 @@ def test_mx8_e5m2_entry_point_host_checks():
     assert call(256, 256, 192) == _abi.SK_ERR_UNSUPPORTED                  # K % 128
     assert call(256, 256, 256, la=_abi.SK_COL_MAJOR) == _abi.SK_ERR_UNSUPPORTED
     assert call(256, 256, 256, lds=4) == _abi.SK_ERR_INVALID_ARG          # scales < K/32
-    assert call(256, 256, 256, dtype=dt + 1) == _abi.SK_ERR_UNSUPPORTED    # no such type
+    # the per-tensor type takes no block scales; a type past the last is unknown
+    assert call(256, 256, 256, dtype=_abi.SK_F8E5M2) == _abi.SK_ERR_INVALID_ARG
+    assert call(256, 256, 256, dtype=_abi.SK_F8E5M2 + 1) == _abi.SK_ERR_UNSUPPORTED
     a = torch.zeros((64, 128), dtype=torch.float8_e4m3fn)
     b = torch.zeros((128, 64), dtype=torch.float8_e5m2)
     s = torch.zeros((64, 8), dtype=torch.uint8)
     with pytest.raises(TypeError):
         sk.gemm_mx(a, b, s, s)
+
+
+def test_f8_e5m2_plans_as_e4m3():
+    # per-tensor e5m2 takes e4m3's iteration depth, tile menu and schedule
+    cfg = sk.Config(tile=(64, 128), mode="hybrid", num_cu=64, min_iters=1)
+    for shape in [(700, 520, 1000), (64, 4096, 8192)]:
+        assert sk.plan([shape], torch.float8_e5m2, cfg) == \
+            sk.plan([shape], torch.float8_e4m3fn, cfg)
+    assert sk.default_tile(64, 4096, 4096, torch.float8_e5m2) == (64, 128)
+    assert sk.pack_pays(4096, 4096, 4096, torch.float8_e5m2) == \
+        sk.pack_pays(4096, 4096, 4096, torch.float8_e4m3fn)
